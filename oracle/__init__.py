@@ -1,0 +1,350 @@
+"""FP64 CPU oracle of the vectorised per-object training step (vMAP, arXiv 2302.01838).
+
+TEST INFRASTRUCTURE ONLY. This package is the slow, plain reference that the GPU path is checked
+against. Only the tests, the package entry's smoke check and the benchmark's CPU-baseline leg may
+import it; the product path never does. It shares no code with the HIP library: the only common
+module is ``scenes`` (seeded inputs, none of the step's arithmetic).
+
+Everything here is float64 numpy written from the paper's definitions, in the paper's order and
+notation, with numpy matmul as the only library primitive:
+
+* point normalisation into the object's unit box (supplement Sec. B, object-level positional
+  encoding: every object is scaled into [-1, 1]^3 by its own bound);
+* Gaussian Fourier features gamma(x) = [sin(x B), cos(x B)] (the build's stand-in for the
+  paper's integrated positional encoding, supplement Sec. B);
+* one MLP per object: hidden ReLU layers and a linear head to (r, g, b, occupancy), with a
+  sigmoid on every output (Sec. 3.3, "Surface and Volume Rendering": occupancy in [0, 1]);
+* occupancy rendering, Eq. 3: T_i = o_i prod_{j<i}(1 - o_j); O = sum T_i, D = sum T_i t_i,
+  C = sum T_i c_i;
+* the per-object depth, colour and occupancy L1 losses (Eqs. 4-6) and the weighted total
+  (Eq. 7, lambda_1 = 5, lambda_2 = 10);
+* the gradient by plain reverse-mode differentiation of those steps;
+* one Adam update per object (the optimiser is not named in the paper; Adam with lr 1e-3 is
+  the workload's choice), skipped for objects without rays (Sec. 3.2: each object can be
+  stopped or resumed without interfering with the others).
+
+Readings where the paper is silent or garbled:
+
+* losses are sums over the object's rays (Eqs. 4-6 as printed), the mask applies per ray, and
+  the colour residual is the L1 norm over the three channels;
+* B has entries of variance 25; phi = x B with no 2 pi factor; gamma lists all sines, then all
+  cosines;
+* depth d_i in Eq. 3 is the ray parameter t_i (unit directions);
+* for a ray inside the mask the occupancy residual O - 1 is evaluated as -prod_i(1 - o_i),
+  which equals it exactly and keeps its sign when O rounds to 1;
+* sgn(0) = 0 for the L1 subgradient and ReLU'(0) = 0;
+* Adam: beta = (0.9, 0.999), eps = 1e-8 added outside the square root, bias-corrected with
+  each object's own step count, no weight decay;
+* weights are Xavier-uniform with bound sqrt(6 / (fan_in + fan_out)), biases zero, the
+  uniforms drawn from SplitMix64 (Steele, Lea and Flood 2014) in counter mode.
+
+Parity is pinned in ``tests/test_oracle_pins.py`` by closed forms, brute force, finite
+differences, torch's autograd and torch's Adam, and invariants. The absolute loss values of a
+full step are pinned only by that composition: the paper prints no worked example.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "LAMBDA_COLOUR", "LAMBDA_OCC", "N_OUT", "layer_shapes", "n_params", "unpack",
+    "splitmix64", "xavier_init", "normalise", "encode", "mlp_forward", "heads", "render",
+    "render_vjp", "ray_losses", "object_forward", "object_loss_and_grad", "adam_update",
+    "ObjectState", "step", "query",
+]
+
+LAMBDA_COLOUR = 5.0   # lambda_1 of Eq. 7
+LAMBDA_OCC = 10.0     # lambda_2 of Eq. 7
+N_OUT = 4             # (r, g, b, occupancy)
+
+
+# --------------------------------------------------------------------------- parameter layout
+
+def layer_shapes(H: int, L: int, E: int) -> List[tuple]:
+    """(fan_out, fan_in) of each linear map: E -> H (L times H -> H in total) -> 4."""
+    widths = [E] + [H] * L + [N_OUT]
+    return [(widths[i + 1], widths[i]) for i in range(len(widths) - 1)]
+
+
+def n_params(H: int, L: int, E: int) -> int:
+    return sum(o * i + o for o, i in layer_shapes(H, L, E))
+
+
+def unpack(theta: np.ndarray, H: int, L: int, E: int):
+    """Views (W_l [out, in], b_l [out]) into a flat parameter vector, in layout order."""
+    out, off = [], 0
+    for o, i in layer_shapes(H, L, E):
+        W = theta[off:off + o * i].reshape(o, i)
+        off += o * i
+        b = theta[off:off + o]
+        off += o
+        out.append((W, b))
+    assert off == theta.shape[0]
+    return out
+
+
+# --------------------------------------------------------------------------- initialisation
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, index: np.ndarray) -> np.ndarray:
+    """Output number ``index`` (0-based) of a SplitMix64 stream started at state ``seed``.
+
+    The state advances by the odd constant 0x9E3779B97F4A7C15 and every output is the state's
+    avalanche mix (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+    OOPSLA 2014). Evaluated in Python integers so the wrap-around is explicit.
+    """
+    out = np.empty(len(index), dtype=np.uint64)
+    for j, n in enumerate(np.asarray(index, dtype=np.int64).tolist()):
+        z = (int(seed) + (n + 1) * 0x9E3779B97F4A7C15) & _MASK64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        out[j] = z ^ (z >> 31)
+    return out
+
+
+def xavier_init(seed: int, H: int, L: int, E: int) -> np.ndarray:
+    """Xavier-uniform weights, zero biases, as the FP32 vector both sides start from.
+
+    Parameter p of the flat layout draws u_p = (top 24 bits of output p) * 2^-24 in [0, 1);
+    a weight of a layer with bound a = sqrt(6 / (fan_in + fan_out)) is a * (2 u_p - 1),
+    evaluated in FP64 and rounded once to FP32.
+    """
+    P = n_params(H, L, E)
+    bits = splitmix64(seed, np.arange(P))
+    u = (bits >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    theta = np.zeros(P, dtype=np.float64)
+    off = 0
+    for o, i in layer_shapes(H, L, E):
+        a = np.sqrt(6.0 / (i + o))
+        theta[off:off + o * i] = a * (2.0 * u[off:off + o * i] - 1.0)
+        off += o * i + o
+    return theta.astype(np.float32)
+
+
+# --------------------------------------------------------------------------- forward pieces
+
+def normalise(rays_o, rays_d, t, centre, scale) -> np.ndarray:
+    """x = (o + t d - c) / s for every sample: [R, S, 3] in FP64."""
+    o = np.asarray(rays_o, np.float64)[:, None, :]
+    d = np.asarray(rays_d, np.float64)[:, None, :]
+    tt = np.asarray(t, np.float64)[:, :, None]
+    c = np.asarray(centre, np.float64)
+    return (o + tt * d - c) / np.float64(scale)
+
+
+def encode(x: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """gamma = [sin(x B), cos(x B)] over the last axis (3 -> 2F)."""
+    phi = x @ np.asarray(B, np.float64)
+    return np.concatenate([np.sin(phi), np.cos(phi)], axis=-1)
+
+
+def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int):
+    """Rows of ``gamma`` through the object's MLP. Returns z [N, 4] and the pre-activations."""
+    layers = unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
+    h = gamma
+    pre = []
+    for W, b in layers[:-1]:
+        a = h @ W.T + b
+        pre.append(a)
+        h = np.maximum(a, 0.0)
+    W, b = layers[-1]
+    return h @ W.T + b, pre
+
+
+def _sigmoid(z):
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-z))
+
+
+def heads(z: np.ndarray):
+    """c = sigmoid(z[..., :3]) (colour), o = sigmoid(z[..., 3]) (occupancy)."""
+    return _sigmoid(z[..., :3]), _sigmoid(z[..., 3])
+
+
+def render(o: np.ndarray, c: np.ndarray, t: np.ndarray):
+    """Eq. 3 along each ray. o, t [R, S]; c [R, S, 3].
+
+    Returns (O_hat [R], D_hat [R], C_hat [R, 3], T [R, S], P [R, S+1]) where P_i is the
+    product of (1 - o_j) over the samples before i, so T_i = o_i P_i and P_{S+1} is what is
+    left after the last sample.
+    """
+    R, S = o.shape
+    P = np.empty((R, S + 1))
+    P[:, 0] = 1.0
+    for i in range(S):
+        P[:, i + 1] = P[:, i] * (1.0 - o[:, i])
+    T = o * P[:, :S]
+    return T.sum(1), (T * t).sum(1), (T[:, :, None] * c).sum(1), T, P
+
+
+def render_vjp(o, c, t, gO, gD, gC, gPend):
+    """Reverse-mode derivative of ``render``: cotangents of (O, D, C, P_{S+1}) -> (do, dc).
+
+    Walks the recurrence P_{i+1} = P_i (1 - o_i) backwards from the last sample.
+    """
+    R, S = o.shape
+    _, _, _, T, P = render(o, c, t)
+    gT = gO[:, None] + gD[:, None] * t + np.einsum("rk,rsk->rs", gC, c)
+    do = np.zeros((R, S))
+    gP_next = np.asarray(gPend, np.float64).copy()      # cotangent of P_{i+1}
+    for i in range(S - 1, -1, -1):
+        # T_i = o_i P_i and P_{i+1} = P_i (1 - o_i)
+        do[:, i] = gT[:, i] * P[:, i] - gP_next * P[:, i]
+        gP_next = gT[:, i] * o[:, i] + gP_next * (1.0 - o[:, i])
+    dc = T[:, :, None] * gC[:, None, :]
+    return do, dc
+
+
+def _sgn(x):
+    return np.sign(x)   # sign(0) = 0
+
+
+def ray_losses(O, D, C, P_end, depth, rgb, mask):
+    """Per-ray terms of Eqs. 4-6 and the occupancy residual rho.
+
+    rho = O - M, computed as -P_{S+1} where M = 1 (exactly equal, see module notes).
+    """
+    rho = np.where(mask == 1.0, -P_end, O - mask)
+    l_depth = mask * np.abs(D - depth)
+    l_colour = mask * np.abs(C - rgb).sum(-1)
+    l_occ = np.abs(rho)
+    return l_depth, l_colour, l_occ, rho
+
+
+# --------------------------------------------------------------------------- one object
+
+def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t):
+    """Encode + MLP + heads + render for one object's rays. Returns a dict of intermediates."""
+    R, S = np.shape(t)
+    x = normalise(rays_o, rays_d, t, centre, scale)
+    gamma = encode(x, B)
+    z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L)
+    c, o = heads(z)
+    c = c.reshape(R, S, 3)
+    o = o.reshape(R, S)
+    tt = np.asarray(t, np.float64)
+    O, D, C, T, P = render(o, c, tt)
+    return dict(x=x, gamma=gamma.reshape(R * S, -1), pre=pre, z=z, c=c, o=o, t=tt, O=O, D=D,
+                C=C, T=T, P=P)
+
+
+def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth, rgb, mask,
+                         upstream: float = 1.0, want_grad: bool = True):
+    """L^k of Eq. 7 for one object and, optionally, upstream * dL^k/dtheta.
+
+    Returns (loss, grad or None, forward dict).
+    """
+    depth = np.asarray(depth, np.float64)
+    rgb = np.asarray(rgb, np.float64)
+    mask = np.asarray(mask, np.float64)
+    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t)
+    R, S = fw["o"].shape
+    ld, lc, lo, rho = ray_losses(fw["O"], fw["D"], fw["C"], fw["P"][:, S], depth, rgb, mask)
+    loss = float(np.sum(ld) + LAMBDA_COLOUR * np.sum(lc) + LAMBDA_OCC * np.sum(lo))
+    if not want_grad:
+        return loss, None, fw
+    theta64 = np.asarray(theta, np.float64)
+    # cotangents of the rendered quantities (L1 subgradients)
+    gD = upstream * mask * _sgn(fw["D"] - depth)
+    gC = upstream * LAMBDA_COLOUR * mask[:, None] * _sgn(fw["C"] - rgb)
+    g_rho = upstream * LAMBDA_OCC * _sgn(rho)
+    inside = mask == 1.0
+    gO = np.where(inside, 0.0, g_rho)           # rho = O - M when M = 0
+    gPend = np.where(inside, -g_rho, 0.0)       # rho = -P_{S+1} when M = 1
+    do, dc = render_vjp(fw["o"], fw["c"], fw["t"], gO, gD, gC, gPend)
+    # through the sigmoids to the head outputs
+    dz = np.empty((R * S, N_OUT))
+    cf = fw["c"].reshape(R * S, 3)
+    of = fw["o"].reshape(R * S)
+    dz[:, :3] = dc.reshape(R * S, 3) * cf * (1.0 - cf)
+    dz[:, 3] = do.reshape(R * S) * of * (1.0 - of)
+    # MLP backward, last layer first
+    layers = unpack(theta64, H, L, fw["gamma"].shape[-1])
+    hs = [fw["gamma"]] + [np.maximum(a, 0.0) for a in fw["pre"]]
+    grads = []
+    delta = dz
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        grads.append((delta.T @ hs[li], delta.sum(0)))
+        if li > 0:
+            delta = (delta @ W) * (fw["pre"][li - 1] > 0.0)
+    grads.reverse()
+    g = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    return loss, g, fw
+
+
+def adam_update(theta, m, v, g, step_count, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step with bias correction at step ``step_count`` (already incremented)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step_count)
+    v_hat = v / (1.0 - beta2 ** step_count)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+# --------------------------------------------------------------------------- the step
+
+class ObjectState:
+    """Parameters, Adam moments and step count of one object model, all FP64."""
+
+    def __init__(self, theta, H: int, L: int, centre, scale):
+        self.theta = np.asarray(theta, np.float64).copy()
+        self.m = np.zeros_like(self.theta)
+        self.v = np.zeros_like(self.theta)
+        self.t = 0
+        self.H, self.L = int(H), int(L)
+        self.centre = np.asarray(centre, np.float64)
+        self.scale = float(scale)
+
+    def copy(self) -> "ObjectState":
+        c = ObjectState(self.theta, self.H, self.L, self.centre, self.scale)
+        c.m, c.v, c.t = self.m.copy(), self.v.copy(), self.t
+        return c
+
+
+def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, beta2=0.999,
+         eps=1e-8, apply_adam: bool = True, upstream: Optional[Sequence[float]] = None):
+    """One training step over a CSR batch; objects are independent and processed in order.
+
+    Returns (losses [n] FP64, grads {id: g}, renders dict with O, D, C per ray). ``states`` is
+    updated in place when ``apply_adam`` is true; objects with no rays are left untouched.
+    """
+    ids = [int(k) for k in batch["object_ids"]]
+    offs = np.asarray(batch["ray_offsets"], np.int64)
+    R = int(offs[-1])
+    losses = np.zeros(len(ids))
+    grads = {}
+    O = np.zeros(R)
+    D = np.zeros(R)
+    C = np.zeros((R, 3))
+    for j, k in enumerate(ids):
+        r0, r1 = offs[j], offs[j + 1]
+        st = states[k]
+        if r1 == r0:
+            grads[k] = np.zeros_like(st.theta)
+            continue
+        up = 1.0 if upstream is None else float(upstream[j])
+        loss, g, fw = object_loss_and_grad(
+            st.theta, st.H, st.L, B, st.centre, st.scale, batch["rays_o"][r0:r1],
+            batch["rays_d"][r0:r1], batch["t"][r0:r1], batch["depth"][r0:r1],
+            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up)
+        losses[j] = loss
+        grads[k] = g
+        O[r0:r1], D[r0:r1], C[r0:r1] = fw["O"], fw["D"], fw["C"]
+        if apply_adam:
+            st.t += 1
+            st.theta, st.m, st.v = adam_update(st.theta, st.m, st.v, g, st.t, lr, beta1, beta2,
+                                               eps)
+    return losses, grads, dict(O=O, D=D, C=C)
+
+
+def query(theta, H: int, L: int, B, centre, scale, pts):
+    """Occupancy and colour of world-frame points inside one object's bound."""
+    x = (np.asarray(pts, np.float64) - np.asarray(centre, np.float64)) / np.float64(scale)
+    z, _ = mlp_forward(theta, encode(x, B), H, L)
+    c, o = heads(z)
+    return o, c
