@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the vectorised per-object training step on one MI355X.
+
+Workload: 50 objects (spheres and boxes), rays per object uniform in [60, 600] drawn once, 20
+samples per ray (10 stratified + 10 within +-5 cm of the surface), hidden 32, 4 hidden layers,
+Adam lr 1e-3. Batches are synthetic, pre-generated and resident in HBM before timing. The same
+batches train a fresh model stack twice: the plain FP32 form and the BF16-MFMA form; each form
+runs `warmup` untimed steps and then `steps` timed steps.
+
+Prints one JSON line: the BF16 form's ray-samples/s as `value`, both forms' object-steps/s and
+ray-samples/s, their final losses (mean total loss over the last 10 steps) and whether they
+match within 2e-2, the roofline of the dominant kernel (the fused tile kernel, timed with HIP
+events on its launch stream), and the FP64 oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "k50_uneven"
+# Algorithmic FLOPs per sample of one training step at H = 32, four hidden layers, E = 32, four
+# outputs: forward 4,224 MACs, backward 7,424 MACs (all weight gradients, input gradients of
+# layers 2..5), 2 FLOPs per MAC. No recomputation, padding or encoding/rendering work counted.
+FLOP_PER_SAMPLE_H32 = 2 * (4224 + 7424)
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gen_batches(scene, n):
+    import scenes
+    return [scenes.make_batch(scene, step) for step in range(n)]
+
+
+def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
+    import torch
+    import paper_2302_01838_amd as vm
+    nrays = max(db.n_rays for db in dev_batches)
+    objs = vm.ObjectSet(max_objects=scene.n_objects, B=scene.B, hidden=32, precision=precision,
+                        max_rays=nrays, max_samples_per_ray=scene.S)
+    for ob in scene.objects:
+        objs.add(ob.norm_centre, ob.norm_scale, hidden=ob.hidden, seed=ob.seed)
+    objs.set_graph_mode(graph)
+    n_obj = scene.n_objects
+    loss_hist = torch.zeros(warmup + steps, n_obj, device="cuda")
+    for i in range(warmup):
+        objs.step(dev_batches[i % len(dev_batches)], loss_hist[i])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        objs.step(dev_batches[(warmup + i) % len(dev_batches)], loss_hist[warmup + i])
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    losses = loss_hist.sum(1).cpu().numpy()
+    samples = [dev_batches[(warmup + i) % len(dev_batches)].n_samples for i in range(steps)]
+    active = [int(np.sum(np.diff(dev_batches[(warmup + i) % len(dev_batches)].ray_offsets) > 0))
+              for i in range(steps)]
+    # dominant kernel: time the tile kernel with events on its stream (plain launches)
+    objs.set_graph_mode(False)
+    objs.kernel_timing(1)
+    for i in range(timing_steps):
+        objs.step(dev_batches[i % len(dev_batches)])
+    torch.cuda.synchronize()
+    k_ms, k_n = objs.kernel_timing(0)
+    k_samples = statistics.mean(dev_batches[i % len(dev_batches)].n_samples for i in range(timing_steps))
+    scale, skipped, err = objs.step_info()
+    objs.close()
+    return dict(
+        precision=precision,
+        wall_s=wall,
+        ms_per_step=1e3 * wall / steps,
+        median_event_ms=statistics.median(per_step_ms[min(10, steps - 1):]),
+        ray_samples_per_s=sum(samples) / wall,
+        object_steps_per_s=sum(active) / wall,
+        final_loss=float(np.mean(losses[-10:])),
+        first_loss=float(losses[0]),
+        loss_scale=scale,
+        skipped_last=skipped,
+        device_error=err,
+        kernel_ms=k_ms,
+        kernel_launches=k_n,
+        kernel_samples=k_samples,
+    )
+
+
+def cpu_baseline(scene, batches, budget_s=15.0):
+    """The FP64 oracle (numpy; OpenBLAS threads as configured) on consecutive steps."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    states = {k: oracle.ObjectState(oracle.xavier_init(o.seed, o.hidden, 4, 32), o.hidden, 4,
+                                    o.norm_centre, o.norm_scale)
+              for k, o in enumerate(scene.objects)}
+    t0 = time.perf_counter()
+    n = samples = 0
+    while n < len(batches):
+        b = batches[n]
+        oracle.step(states, b, scene.B)
+        samples += b["t"].size
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
+                sample=f"{n} consecutive training steps of the {WORKLOAD} workload "
+                       f"({samples} samples) from the initial models, FP64 numpy",
+                seconds=dt, object_steps_per_s=n * scene.n_objects / dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
+    ap.add_argument("--distinct-batches", type=int, default=0,
+                    help="distinct pre-generated batches (default: warmup + steps)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--forms", default="fp32,bf16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the step has no "
+              "cross-GPU exchange; objects would be sharded across GPUs, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import scenes
+    import paper_2302_01838_amd as vm
+
+    vm.load_library()
+    scene = scenes.make_scene(WORKLOAD)
+    n_batches = args.distinct_batches or (args.warmup + args.steps)
+    log(f"generating {n_batches} batches of {WORKLOAD}")
+    batches = gen_batches(scene, n_batches)
+    dev_batches = [vm.DeviceBatch(b) for b in batches]
+    torch.cuda.synchronize()
+
+    forms = {}
+    for prec in args.forms.split(","):
+        log(f"form {prec}: {args.warmup} warmup + {args.steps} timed steps")
+        forms[prec] = run_form(prec, scene, dev_batches, args.steps, args.warmup,
+                               bool(args.graph), timing_steps=min(args.steps, 50))
+        log(f"form {prec}: {forms[prec]['ms_per_step']:.4f} ms/step, "
+            f"{forms[prec]['ray_samples_per_s']:.4g} samples/s, final loss "
+            f"{forms[prec]['final_loss']:.6g}")
+
+    head = forms.get("bf16") or next(iter(forms.values()))
+    prec = head["precision"]
+    matched = None
+    if "bf16" in forms and "fp32" in forms:
+        matched = abs(forms["bf16"]["final_loss"] - forms["fp32"]["final_loss"]) <= \
+            2e-2 * abs(forms["fp32"]["final_loss"])
+    flops = FLOP_PER_SAMPLE_H32 * head["kernel_samples"]
+    achieved = flops / (head["kernel_ms"] * 1e-3) if head["kernel_ms"] > 0 else 0.0
+    roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK[prec], traffic=None,
+                    kernel="k_step_tiles (fused encode+MLP+render+loss+backward)",
+                    kernel_avg_ms=head["kernel_ms"], flop_per_launch=flops)
+    log(f"cpu baseline: oracle for up to {args.cpu_budget:.0f} s")
+    cpu = cpu_baseline(scene, batches, args.cpu_budget)
+    out = {
+        "metric": "object-steps/s and ray-samples/s at K=50, BF16 vs FP32, at matched final loss",
+        "value": head["ray_samples_per_s"],
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": "K=50 objects, rays/object U[60,600], 20 samples/ray, hidden 32, "
+                               "4 hidden layers, Adam lr 1e-3",
+                   "objects": scene.n_objects, "samples_per_step": dev_batches[0].n_samples,
+                   "graph": bool(args.graph), "parallelism": "single GPU"},
+        "object_steps_per_s": head["object_steps_per_s"],
+        "forms": {k: {kk: v[kk] for kk in ("ray_samples_per_s", "object_steps_per_s", "ms_per_step",
+                                           "median_event_ms", "final_loss", "first_loss",
+                                           "loss_scale", "skipped_last", "device_error",
+                                           "kernel_ms")} for k, v in forms.items()},
+        "matched_final_loss": matched,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

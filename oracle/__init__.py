@@ -52,7 +52,7 @@ __all__ = [
     "LAMBDA_COLOUR", "LAMBDA_OCC", "N_OUT", "layer_shapes", "n_params", "unpack",
     "splitmix64", "xavier_init", "normalise", "encode", "mlp_forward", "heads", "render",
     "render_vjp", "ray_losses", "object_forward", "object_loss_and_grad", "adam_update",
-    "ObjectState", "step", "query",
+    "ObjectState", "step", "query", "bf16_round",
 ]
 
 LAMBDA_COLOUR = 5.0   # lambda_1 of Eq. 7
@@ -125,6 +125,23 @@ def xavier_init(seed: int, H: int, L: int, E: int) -> np.ndarray:
     return theta.astype(np.float32)
 
 
+# --------------------------------------------------------------------------- BF16 diagnosis
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), via FP32, returned as FP64.
+
+    Only for the optional BF16 diagnostic mode: it tells the error that BF16 products bring by
+    themselves apart from the GPU's accumulation order. The default mode is pure FP64.
+    """
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(x):
+    return x
+
+
 # --------------------------------------------------------------------------- forward pieces
 
 def normalise(rays_o, rays_d, t, centre, scale) -> np.ndarray:
@@ -142,17 +159,21 @@ def encode(x: np.ndarray, B: np.ndarray) -> np.ndarray:
     return np.concatenate([np.sin(phi), np.cos(phi)], axis=-1)
 
 
-def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int):
-    """Rows of ``gamma`` through the object's MLP. Returns z [N, 4] and the pre-activations."""
+def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int, rnd=_identity):
+    """Rows of ``gamma`` through the object's MLP. Returns z [N, 4] and the pre-activations.
+
+    ``rnd`` is applied to both operands of every product (identity: exact FP64; bf16_round:
+    the diagnostic BF16 mode).
+    """
     layers = unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
     h = gamma
     pre = []
     for W, b in layers[:-1]:
-        a = h @ W.T + b
+        a = rnd(h) @ rnd(W).T + b
         pre.append(a)
         h = np.maximum(a, 0.0)
     W, b = layers[-1]
-    return h @ W.T + b, pre
+    return rnd(h) @ rnd(W).T + b, pre
 
 
 def _sigmoid(z):
@@ -217,12 +238,12 @@ def ray_losses(O, D, C, P_end, depth, rgb, mask):
 
 # --------------------------------------------------------------------------- one object
 
-def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t):
+def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identity):
     """Encode + MLP + heads + render for one object's rays. Returns a dict of intermediates."""
     R, S = np.shape(t)
     x = normalise(rays_o, rays_d, t, centre, scale)
     gamma = encode(x, B)
-    z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L)
+    z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L, rnd)
     c, o = heads(z)
     c = c.reshape(R, S, 3)
     o = o.reshape(R, S)
@@ -233,15 +254,17 @@ def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t):
 
 
 def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth, rgb, mask,
-                         upstream: float = 1.0, want_grad: bool = True):
+                         upstream: float = 1.0, want_grad: bool = True, rnd=_identity):
     """L^k of Eq. 7 for one object and, optionally, upstream * dL^k/dtheta.
 
-    Returns (loss, grad or None, forward dict).
+    Returns (loss, grad or None, forward dict). With ``rnd`` = bf16_round the products of the
+    MLP (forward and backward) take BF16-rounded operands, except the seed dz of the output
+    layer, which stays FP64 (diagnostic mode).
     """
     depth = np.asarray(depth, np.float64)
     rgb = np.asarray(rgb, np.float64)
     mask = np.asarray(mask, np.float64)
-    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t)
+    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd)
     R, S = fw["o"].shape
     ld, lc, lo, rho = ray_losses(fw["O"], fw["D"], fw["C"], fw["P"][:, S], depth, rgb, mask)
     loss = float(np.sum(ld) + LAMBDA_COLOUR * np.sum(lc) + LAMBDA_OCC * np.sum(lo))
@@ -267,11 +290,13 @@ def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth
     hs = [fw["gamma"]] + [np.maximum(a, 0.0) for a in fw["pre"]]
     grads = []
     delta = dz
-    for li in range(len(layers) - 1, -1, -1):
+    last = len(layers) - 1
+    for li in range(last, -1, -1):
         W, _ = layers[li]
-        grads.append((delta.T @ hs[li], delta.sum(0)))
+        d_op = delta if li == last else rnd(delta)
+        grads.append((d_op.T @ rnd(hs[li]), d_op.sum(0)))
         if li > 0:
-            delta = (delta @ W) * (fw["pre"][li - 1] > 0.0)
+            delta = (d_op @ rnd(W)) * (fw["pre"][li - 1] > 0.0)
     grads.reverse()
     g = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return loss, g, fw
@@ -307,7 +332,8 @@ class ObjectState:
 
 
 def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, beta2=0.999,
-         eps=1e-8, apply_adam: bool = True, upstream: Optional[Sequence[float]] = None):
+         eps=1e-8, apply_adam: bool = True, upstream: Optional[Sequence[float]] = None,
+         rnd=_identity):
     """One training step over a CSR batch; objects are independent and processed in order.
 
     Returns (losses [n] FP64, grads {id: g}, renders dict with O, D, C per ray). ``states`` is
@@ -331,7 +357,7 @@ def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, bet
         loss, g, fw = object_loss_and_grad(
             st.theta, st.H, st.L, B, st.centre, st.scale, batch["rays_o"][r0:r1],
             batch["rays_d"][r0:r1], batch["t"][r0:r1], batch["depth"][r0:r1],
-            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up)
+            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up, rnd=rnd)
         losses[j] = loss
         grads[k] = g
         O[r0:r1], D[r0:r1], C[r0:r1] = fw["O"], fw["D"], fw["C"]

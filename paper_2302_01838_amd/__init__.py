@@ -1,0 +1,380 @@
+"""Python binding of libvmap: vectorised per-object neural-field training on MI355X (gfx950).
+
+Thin ctypes marshalling over the C ABI in ``include/vmap.h``: every step of the computation runs
+in the library's HIP kernels. PyTorch supplies device memory (tensors) and the current HIP
+stream. There is no fallback: if ``libvmap.so`` is missing, importing the binding's entry points
+raises.
+
+    objs = ObjectSet(max_objects=50, B=B, precision="bf16", max_rays=40000)
+    ids = [objs.add(centre, scale, seed=s) for centre, scale, s in ...]
+    batch = DeviceBatch(batch_dict)            # rays of several objects, CSR-segmented
+    losses = objs.step(batch)                  # one vectorised training step
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+__all__ = ["VmapError", "load_library", "library_path", "ObjectSet", "DeviceBatch", "RenderLoss",
+           "VMAP_FP32", "VMAP_BF16", "STATE_PARAMS", "STATE_ADAM_M", "STATE_ADAM_V",
+           "STATE_GRAD", "STATE_STEP", "EXPORTED"]
+
+VMAP_FP32, VMAP_BF16 = 0, 1
+STATE_PARAMS, STATE_ADAM_M, STATE_ADAM_V, STATE_GRAD, STATE_STEP = 0, 1, 2, 3, 4
+_STATUS = {0: "VMAP_OK", 1: "VMAP_EINVAL", 2: "VMAP_ECAPACITY", 3: "VMAP_EHIP", 4: "VMAP_ESTATE",
+           5: "VMAP_ENOTSUP"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libvmap.so")
+
+
+class VmapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class VmapConfig(ctypes.Structure):
+    _fields_ = [("max_objects", ctypes.c_int32), ("n_features", ctypes.c_int32),
+                ("hidden", ctypes.c_int32), ("n_hidden_layers", ctypes.c_int32),
+                ("max_hidden", ctypes.c_int32), ("max_samples_per_ray", ctypes.c_int32),
+                ("max_rays", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rays_per_tile", ctypes.c_int32), ("scale_growth_interval", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("lambda_colour", ctypes.c_double),
+                ("lambda_occ", ctypes.c_double), ("loss_scale_init", ctypes.c_double)]
+
+
+class VmapObjectDesc(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_float * 3), ("scale", ctypes.c_float),
+                ("hidden", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class VmapBatch(ctypes.Structure):
+    _fields_ = [("n_objects", ctypes.c_int32), ("n_rays_total", ctypes.c_int32),
+                ("samples_per_ray", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("object_ids", ctypes.c_void_p), ("ray_offsets", ctypes.c_void_p),
+                ("rays_o", ctypes.c_void_p), ("rays_d", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_CFG = ctypes.POINTER(VmapConfig)
+_BATCH = ctypes.POINTER(VmapBatch)
+
+# name -> (restype, argtypes); the exported C ABI of include/vmap.h
+EXPORTED = {
+    "vmap_state_bytes": (ctypes.c_size_t, [_CFG]),
+    "vmap_workspace_bytes": (ctypes.c_size_t, [_CFG]),
+    "vmap_object_params": (_I, [_CFG, _I]),
+    "vmap_init_objects": (ctypes.c_int, [_CFG, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
+                                         ctypes.POINTER(_P)]),
+    "vmap_add_object": (ctypes.c_int, [_P, ctypes.POINTER(VmapObjectDesc), _P, _P,
+                                       ctypes.POINTER(_I)]),
+    "vmap_train_step": (ctypes.c_int, [_P, _BATCH, _P, _P]),
+    "vmap_render": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P]),
+    "vmap_query_occupancy": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, _P, _P]),
+    "vmap_forward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P, _P]),
+    "vmap_backward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P]),
+    "vmap_adam_step": (ctypes.c_int, [_P, _BATCH, _P]),
+    "vmap_get_state": (ctypes.c_int, [_P, _I, _I, _P, ctypes.c_size_t, _P]),
+    "vmap_set_state": (ctypes.c_int, [_P, _I, _I, _P, ctypes.c_size_t, _P]),
+    "vmap_step_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_I),
+                                      ctypes.POINTER(_I), _P]),
+    "vmap_param_layout": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "vmap_set_graph_mode": (ctypes.c_int, [_P, _I]),
+    "vmap_set_launch": (ctypes.c_int, [_P, _I, _I]),
+    "vmap_kernel_timing": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(_I)]),
+    "vmap_last_error": (ctypes.c_char_p, [_P]),
+    "vmap_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load_library():
+    """Load libvmap.so (built by ``__graft_entry__.build()``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2302_01838_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTED.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_config(**kw) -> VmapConfig:
+    c = VmapConfig(max_objects=64, n_features=16, hidden=32, n_hidden_layers=4, max_hidden=0,
+                   max_samples_per_ray=32, max_rays=1 << 16, precision=VMAP_FP32,
+                   rays_per_tile=0, scale_growth_interval=2000, lr=1e-3, beta1=0.9, beta2=0.999,
+                   eps=1e-8, lambda_colour=5.0, lambda_occ=10.0, loss_scale_init=4096.0)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    if c.max_hidden == 0:
+        c.max_hidden = c.hidden
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+class DeviceBatch:
+    """A batch resident in device memory (torch tensors), with its C ``vmap_batch`` view."""
+
+    FIELDS = ("object_ids", "ray_offsets", "rays_o", "rays_d", "t", "depth", "rgb", "mask")
+
+    def __init__(self, batch: Dict[str, np.ndarray], device=None):
+        torch = _torch()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        self.S = int(batch["S"])
+        self.tensors = {}
+        for k in self.FIELDS:
+            arr = np.ascontiguousarray(batch[k])
+            dt = torch.int32 if k in ("object_ids", "ray_offsets") else torch.float32
+            self.tensors[k] = torch.as_tensor(arr).to(device=dev, dtype=dt).contiguous()
+        self.n_objects = int(self.tensors["object_ids"].numel())
+        self.n_rays = int(np.asarray(batch["ray_offsets"])[-1]) if self.n_objects else 0
+        self.n_samples = self.n_rays * self.S
+        self.object_ids = np.asarray(batch["object_ids"], dtype=np.int32)
+        self.ray_offsets = np.asarray(batch["ray_offsets"], dtype=np.int64)
+        self.c = VmapBatch(n_objects=self.n_objects, n_rays_total=self.n_rays,
+                           samples_per_ray=self.S, reserved=0,
+                           **{k: self.tensors[k].data_ptr() for k in self.FIELDS})
+
+    def __getitem__(self, k):
+        return self.tensors[k]
+
+
+class ObjectSet:
+    """A stack of per-object MLPs trained together (the library context plus its buffers)."""
+
+    def __init__(self, max_objects: int, B: np.ndarray, hidden: int = 32, precision: str = "fp32",
+                 max_rays: int = 1 << 16, max_samples_per_ray: int = 32,
+                 max_hidden: Optional[int] = None, rays_per_tile: int = 0, lr: float = 1e-3,
+                 betas=(0.9, 0.999), eps: float = 1e-8, lambda_colour: float = 5.0,
+                 lambda_occ: float = 10.0, loss_scale_init: float = 4096.0,
+                 scale_growth_interval: int = 2000, device=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.cfg = default_config(
+            max_objects=max_objects, hidden=hidden, max_hidden=max_hidden or hidden,
+            max_samples_per_ray=max_samples_per_ray, max_rays=max_rays,
+            precision=VMAP_BF16 if precision == "bf16" else VMAP_FP32,
+            rays_per_tile=rays_per_tile, scale_growth_interval=scale_growth_interval, lr=lr,
+            beta1=betas[0], beta2=betas[1], eps=eps, lambda_colour=lambda_colour,
+            lambda_occ=lambda_occ, loss_scale_init=loss_scale_init)
+        self.precision = precision
+        sb = self.lib.vmap_state_bytes(ctypes.byref(self.cfg))
+        wb = self.lib.vmap_workspace_bytes(ctypes.byref(self.cfg))
+        if sb == 0 or wb == 0:
+            raise VmapError(1, "invalid configuration")
+        self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        Bc = np.ascontiguousarray(B, dtype=np.float32)
+        assert Bc.shape == (3, 16)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.vmap_init_objects(ctypes.byref(self.cfg), Bc.ctypes.data,
+                                        self.state.data_ptr(), sb, self.workspace.data_ptr(), wb,
+                                        _stream(), ctypes.byref(ctx))
+        if rc != 0:
+            raise VmapError(rc, self.lib.vmap_last_error(None).decode())
+        self.ctx = ctx
+        self.n_params: Dict[int, int] = {}
+        self.p_stride = 0
+
+    # -- helpers
+    def _check(self, rc: int):
+        if rc != 0:
+            raise VmapError(rc, self.lib.vmap_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.vmap_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- model stack
+    def add(self, centre, scale: float, hidden: int = 0, seed: int = 0,
+            init: Optional[np.ndarray] = None) -> int:
+        d = VmapObjectDesc(hidden=hidden, reserved=0, seed=int(seed) & ((1 << 64) - 1))
+        for i in range(3):
+            d.centre[i] = float(centre[i])
+        d.scale = float(scale)
+        oid = ctypes.c_int32()
+        ptr = None
+        if init is not None:
+            init = np.ascontiguousarray(init, dtype=np.float32)
+            ptr = init.ctypes.data
+        self._check(self.lib.vmap_add_object(self.ctx, ctypes.byref(d), ptr, _stream(),
+                                             ctypes.byref(oid)))
+        k = oid.value
+        n, s = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.vmap_param_layout(self.ctx, k, ctypes.byref(n), ctypes.byref(s)))
+        self.n_params[k] = n.value
+        self.p_stride = s.value
+        return k
+
+    # -- the step and its parts
+    def step(self, batch: DeviceBatch, losses=None):
+        torch = _torch()
+        if losses is None:
+            losses = torch.empty(batch.n_objects, dtype=torch.float32, device=self.device)
+        self._check(self.lib.vmap_train_step(self.ctx, ctypes.byref(batch.c),
+                                             losses.data_ptr() if batch.n_objects else None,
+                                             _stream()))
+        return losses
+
+    def forward(self, batch: DeviceBatch, renders: bool = True):
+        torch = _torch()
+        loss = torch.empty(batch.n_objects, dtype=torch.float32, device=self.device)
+        R = batch.n_rays
+        depth = torch.empty(R, dtype=torch.float32, device=self.device) if renders else None
+        rgb = torch.empty(R, 3, dtype=torch.float32, device=self.device) if renders else None
+        occ = torch.empty(R, dtype=torch.float32, device=self.device) if renders else None
+        ptr = lambda x: None if x is None or x.numel() == 0 else x.data_ptr()
+        self._check(self.lib.vmap_forward(self.ctx, ctypes.byref(batch.c), ptr(loss), ptr(depth),
+                                          ptr(rgb), ptr(occ), _stream()))
+        return loss, depth, rgb, occ
+
+    def backward(self, batch: DeviceBatch, dloss):
+        torch = _torch()
+        dloss = dloss.to(device=self.device, dtype=torch.float32).contiguous()
+        grad = torch.empty(batch.n_objects, self.p_stride, dtype=torch.float32, device=self.device)
+        self._check(self.lib.vmap_backward(self.ctx, ctypes.byref(batch.c),
+                                           dloss.data_ptr() if batch.n_objects else None,
+                                           grad.data_ptr() if batch.n_objects else None,
+                                           _stream()))
+        return grad
+
+    def adam_step(self, batch: DeviceBatch):
+        self._check(self.lib.vmap_adam_step(self.ctx, ctypes.byref(batch.c), _stream()))
+
+    def render(self, batch: DeviceBatch):
+        torch = _torch()
+        R = batch.n_rays
+        depth = torch.empty(R, dtype=torch.float32, device=self.device)
+        rgb = torch.empty(R, 3, dtype=torch.float32, device=self.device)
+        occ = torch.empty(R, dtype=torch.float32, device=self.device)
+        self._check(self.lib.vmap_render(self.ctx, ctypes.byref(batch.c),
+                                         depth.data_ptr() if R else None,
+                                         rgb.data_ptr() if R else None,
+                                         occ.data_ptr() if R else None, _stream()))
+        return depth, rgb, occ
+
+    def query(self, k: int, pts):
+        torch = _torch()
+        pts = torch.as_tensor(pts).to(device=self.device, dtype=torch.float32).contiguous()
+        n = pts.shape[0]
+        occ = torch.empty(n, dtype=torch.float32, device=self.device)
+        rgb = torch.empty(n, 3, dtype=torch.float32, device=self.device)
+        self._check(self.lib.vmap_query_occupancy(self.ctx, k, pts.data_ptr() if n else None, n,
+                                                  occ.data_ptr() if n else None,
+                                                  rgb.data_ptr() if n else None, _stream()))
+        return occ, rgb
+
+    # -- state I/O and diagnostics
+    def get_state(self, k: int, which: int = STATE_PARAMS) -> np.ndarray:
+        if which == STATE_STEP:
+            out = np.zeros(1, dtype=np.int32)
+        else:
+            out = np.zeros(self.n_params[k], dtype=np.float32)
+        self._check(self.lib.vmap_get_state(self.ctx, k, which, out.ctypes.data, out.nbytes,
+                                            _stream()))
+        return out if which != STATE_STEP else int(out[0])
+
+    def set_state(self, k: int, which: int, value) -> None:
+        if which == STATE_STEP:
+            arr = np.asarray([value], dtype=np.int32)
+        else:
+            arr = np.ascontiguousarray(value, dtype=np.float32)
+        self._check(self.lib.vmap_set_state(self.ctx, k, which, arr.ctypes.data, arr.nbytes,
+                                            _stream()))
+
+    def step_info(self):
+        s = ctypes.c_float()
+        sk, er = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.vmap_step_info(self.ctx, ctypes.byref(s), ctypes.byref(sk),
+                                            ctypes.byref(er), _stream()))
+        return s.value, sk.value, er.value
+
+    def set_graph_mode(self, on: bool):
+        self._check(self.lib.vmap_set_graph_mode(self.ctx, 1 if on else 0))
+
+    def set_launch(self, waves: int = 4, grid_blocks: int = 0):
+        self._check(self.lib.vmap_set_launch(self.ctx, waves, grid_blocks))
+
+    def kernel_timing(self, enable: int = -1):
+        avg = ctypes.c_double()
+        cnt = ctypes.c_int32()
+        self._check(self.lib.vmap_kernel_timing(self.ctx, enable, ctypes.byref(avg),
+                                                ctypes.byref(cnt)))
+        return avg.value, cnt.value
+
+
+def _render_loss_backward(ctx, dloss, *unused):
+    grad = ctx.objset.backward(ctx.batch, dloss)
+    return grad, None, None
+
+
+class RenderLoss:
+    """``torch.autograd.Function`` over the library's forward and hand-written adjoint.
+
+    ``RenderLoss.apply(token, objset, batch)`` returns the per-object losses of the batch;
+    ``token`` is a [n_objects, p_stride] tensor with ``requires_grad`` that carries the gradient
+    of the batch objects' parameters (the parameters themselves live in the library state).
+    After ``backward`` the library's gradient slots hold the same gradient, so
+    ``objset.adam_step(batch)`` applies the update.
+    """
+
+    _fn = None
+
+    @classmethod
+    def function(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _RenderLoss(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, token, objset, batch):
+                    ctx.objset = objset
+                    ctx.batch = batch
+                    loss, _, _, _ = objset.forward(batch, renders=False)
+                    return loss
+
+                @staticmethod
+                def backward(ctx, dloss):
+                    return _render_loss_backward(ctx, dloss)
+
+            cls._fn = _RenderLoss
+        return cls._fn
+
+    @classmethod
+    def apply(cls, token, objset, batch):
+        return cls.function().apply(token, objset, batch)

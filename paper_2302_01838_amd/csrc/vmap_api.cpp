@@ -1,0 +1,682 @@
+// Host side of the C ABI declared in include/vmap.h: context, object registry, validation,
+// buffer layout, launch sequencing and optional hipGraph replay of the training step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "vmap.h"
+#include "vmap_internal.h"
+
+using namespace vmapi;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int pad_params(int P) { return (P + 63) / 64 * 64; }
+
+struct StateLayout {
+  size_t desc, scaler, B, theta, m, v, grad, total;
+};
+
+struct WorkLayout {
+  size_t tile_start, flags, tile_loss, partial, total;
+  int max_tiles;
+};
+
+bool hidden_ok(int H, int precision) {
+  if (precision == VMAP_BF16) return H == 32 || H == 64;
+  return H == 32 || H == 64;
+}
+
+const char* check_config(const vmap_config* c) {
+  if (!c) return "config is NULL";
+  if (c->max_objects < 1 || c->max_objects > 65536) return "max_objects must be in [1, 65536]";
+  if (c->n_features != kFeatures) return "n_features must be 16";
+  if (c->n_hidden_layers != kLayers) return "n_hidden_layers must be 4";
+  if (c->precision != VMAP_FP32 && c->precision != VMAP_BF16) return "precision must be VMAP_FP32 or VMAP_BF16";
+  if (!hidden_ok(c->hidden, c->precision)) return "hidden width not supported (32 or 64)";
+  if (c->max_hidden < c->hidden || !hidden_ok(c->max_hidden, c->precision))
+    return "max_hidden must be a supported width >= hidden";
+  if (c->max_samples_per_ray < 1 || c->max_samples_per_ray > kSlots) return "max_samples_per_ray must be in [1, 64]";
+  if (c->max_rays < 0 || c->max_rays > (1 << 26)) return "max_rays must be in [0, 2^26]";
+  if (c->rays_per_tile < 0 || c->rays_per_tile > (1 << 16)) return "rays_per_tile must be in [0, 65536]";
+  if (!(c->lr > 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
+      !(c->eps > 0.0))
+    return "Adam settings out of range (lr > 0, 0 <= beta < 1, eps > 0)";
+  if (!(c->lambda_colour >= 0.0) || !(c->lambda_occ >= 0.0)) return "loss weights must be >= 0";
+  if (c->precision == VMAP_BF16) {
+    if (!(c->loss_scale_init > 0.0) || !std::isfinite(c->loss_scale_init)) return "loss_scale_init must be > 0";
+    if (c->scale_growth_interval < 1) return "scale_growth_interval must be >= 1";
+  }
+  return nullptr;
+}
+
+int default_rays_per_tile(const vmap_config* c) {
+  if (c->rays_per_tile > 0) return c->rays_per_tile;
+  const int rpw = std::max(1, kSlots / c->max_samples_per_ray);
+  return rpw * 4 * 2;  // two sub-tiles per wave of a four-wave block
+}
+
+StateLayout state_layout(const vmap_config* c) {
+  StateLayout s{};
+  const size_t K = (size_t)c->max_objects;
+  const size_t ps = (size_t)pad_params(n_params_of(c->max_hidden));
+  size_t off = 0;
+  s.desc = off; off = align256(off + K * sizeof(ObjDesc));
+  s.scaler = off; off = align256(off + sizeof(ScalerState));
+  s.B = off; off = align256(off + 3 * kFeatures * sizeof(float));
+  s.theta = off; off = align256(off + K * ps * 4);
+  s.m = off; off = align256(off + K * ps * 4);
+  s.v = off; off = align256(off + K * ps * 4);
+  s.grad = off; off = align256(off + K * ps * 4);
+  s.total = off;
+  return s;
+}
+
+WorkLayout work_layout(const vmap_config* c) {
+  WorkLayout w{};
+  const int rpt = default_rays_per_tile(c);
+  const size_t ps = (size_t)pad_params(n_params_of(c->max_hidden));
+  w.max_tiles = (c->max_rays + rpt - 1) / rpt + c->max_objects;
+  size_t off = 0;
+  w.tile_start = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
+  w.flags = off; off = align256(off + (size_t)c->max_objects * 4);
+  w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
+  w.partial = off; off = align256(off + (size_t)w.max_tiles * ps * 4);
+  w.total = off;
+  return w;
+}
+
+struct HostObj {
+  int registered = 0;
+  int hidden = 0;
+  int n_params = 0;
+};
+
+struct TimedLaunch {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct vmap_ctx {
+  vmap_config cfg{};
+  StateLayout sl{};
+  WorkLayout wl{};
+  unsigned char* state = nullptr;
+  unsigned char* work = nullptr;
+  int p_stride = 0;
+  int rays_per_tile = 0;
+  int waves = 4;
+  int grid_blocks = 0;
+  int device = 0;
+  std::vector<HostObj> objs;
+  int n_registered = 0;
+  std::string err;
+  // timing of the tile kernel
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  // graph replay of the training step
+  bool graph_mode = false;
+  struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<std::vector<int64_t>, GraphEntry> graphs;
+  hipStream_t capture_stream = nullptr;
+
+  ObjDesc* desc() { return reinterpret_cast<ObjDesc*>(state + sl.desc); }
+  ScalerState* scaler() { return reinterpret_cast<ScalerState*>(state + sl.scaler); }
+  float* B() { return reinterpret_cast<float*>(state + sl.B); }
+  float* theta() { return reinterpret_cast<float*>(state + sl.theta); }
+  float* m() { return reinterpret_cast<float*>(state + sl.m); }
+  float* v() { return reinterpret_cast<float*>(state + sl.v); }
+  float* grad() { return reinterpret_cast<float*>(state + sl.grad); }
+  int32_t* tile_start() { return reinterpret_cast<int32_t*>(work + wl.tile_start); }
+  int32_t* flags() { return reinterpret_cast<int32_t*>(work + wl.flags); }
+  float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
+  float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return VMAP_EHIP;
+  }
+};
+
+namespace {
+
+int validate_batch(vmap_ctx* c, const vmap_batch* b, bool need_targets) {
+  if (!b) return c->fail(VMAP_EINVAL, "batch is NULL");
+  if (b->n_objects < 0) return c->fail(VMAP_EINVAL, "batch.n_objects must be >= 0");
+  if (b->n_objects > c->cfg.max_objects)
+    return c->fail(VMAP_ECAPACITY, "batch.n_objects exceeds max_objects");
+  if (b->n_rays_total < 0) return c->fail(VMAP_EINVAL, "batch.n_rays_total must be >= 0");
+  if (b->n_rays_total > c->cfg.max_rays) return c->fail(VMAP_ECAPACITY, "batch.n_rays_total exceeds max_rays");
+  if (b->samples_per_ray < 1 || b->samples_per_ray > c->cfg.max_samples_per_ray)
+    return c->fail(VMAP_EINVAL, "batch.samples_per_ray out of [1, max_samples_per_ray]");
+  if (b->n_objects > 0 && (!b->object_ids || !b->ray_offsets))
+    return c->fail(VMAP_EINVAL, "batch.object_ids and batch.ray_offsets must not be NULL");
+  if (b->n_rays_total > 0) {
+    if (!b->rays_o || !b->rays_d || !b->t) return c->fail(VMAP_EINVAL, "batch ray arrays must not be NULL");
+    if (need_targets && (!b->depth || !b->rgb || !b->mask))
+      return c->fail(VMAP_EINVAL, "batch targets (depth, rgb, mask) must not be NULL");
+  }
+  const int rpt = c->rays_per_tile;
+  const long long tiles = ((long long)b->n_rays_total + rpt - 1) / rpt + b->n_objects;
+  if (tiles > c->wl.max_tiles) return c->fail(VMAP_ECAPACITY, "batch needs more tiles than the workspace holds");
+  return VMAP_OK;
+}
+
+std::vector<int> widths_present(vmap_ctx* c) {
+  std::vector<int> w;
+  for (const auto& o : c->objs)
+    if (o.registered && std::find(w.begin(), w.end(), o.hidden) == w.end()) w.push_back(o.hidden);
+  std::sort(w.begin(), w.end());
+  return w;
+}
+
+StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
+  StepArgs a{};
+  a.n_objects = b->n_objects;
+  a.S = b->samples_per_ray;
+  a.rays_per_tile = c->rays_per_tile;
+  a.max_objects = c->cfg.max_objects;
+  a.object_ids = b->object_ids;
+  a.ray_offsets = b->ray_offsets;
+  a.rays_o = b->rays_o;
+  a.rays_d = b->rays_d;
+  a.t = b->t;
+  a.depth = b->depth;
+  a.rgb = b->rgb;
+  a.mask = b->mask;
+  a.theta = c->theta();
+  a.p_stride = c->p_stride;
+  a.desc = c->desc();
+  a.scaler = c->scaler();
+  a.B = c->B();
+  a.tile_start = c->tile_start();
+  a.partial = c->partial();
+  a.tile_loss = c->tile_loss();
+  a.lambda_c = (float)c->cfg.lambda_colour;
+  a.lambda_o = (float)c->cfg.lambda_occ;
+  return a;
+}
+
+hipEvent_t pooled_event(vmap_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue the tile kernel for every width group.
+int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss, float* d_out,
+                  float* rgb_out, float* occ_out, hipStream_t s, bool allow_timing) {
+  StepArgs a = make_step_args(c, b);
+  a.dloss = dloss;
+  a.out_depth = d_out;
+  a.out_rgb = rgb_out;
+  a.out_occ = occ_out;
+  a.use_scale = (mode == MODE_TRAIN && c->cfg.precision == VMAP_BF16) ? 1 : 0;
+  const bool bf = c->cfg.precision == VMAP_BF16;
+  const int bound = (b->n_rays_total + c->rays_per_tile - 1) / c->rays_per_tile + b->n_objects;
+  int grid = bound;
+  if (c->grid_blocks > 0) grid = std::min(grid, c->grid_blocks);
+  TimedLaunch tl{};
+  const bool timed = allow_timing && c->timing;
+  if (timed) {
+    tl.a = pooled_event(c);
+    tl.b = pooled_event(c);
+    if (!tl.a || !tl.b) return c->fail(VMAP_EHIP, "hipEventCreate failed");
+    hipError_t e = hipEventRecord(tl.a, s);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+  }
+  for (int H : widths_present(c)) {
+    a.hidden = H;
+    a.lds = lds_layout(H, bf, c->waves);
+    hipError_t e = launch_tiles(H, bf, mode, a, c->waves, grid, s);
+    if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
+  }
+  if (timed) {
+    hipError_t e = hipEventRecord(tl.b, s);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+    c->timed.push_back(tl);
+  }
+  return VMAP_OK;
+}
+
+int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing) {
+  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
+                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+  if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
+  int rc = enqueue_tiles(c, b, MODE_TRAIN, nullptr, nullptr, nullptr, nullptr, s, allow_timing);
+  if (rc) return rc;
+  const int bf = c->cfg.precision == VMAP_BF16;
+  e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
+                    c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), bf, c->grad(), nullptr,
+                    c->flags(), loss_out, 1, s);
+  if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
+  e = launch_adam(b->n_objects, b->object_ids, b->ray_offsets, c->cfg.max_objects, c->desc(),
+                  c->scaler(), c->flags(), c->theta(), c->m(), c->v(), c->grad(), c->p_stride,
+                  c->cfg.lr, c->cfg.beta1, c->cfg.beta2, c->cfg.eps, bf,
+                  c->cfg.scale_growth_interval, s);
+  if (e != hipSuccess) return c->hip_fail(e, "adam launch");
+  return VMAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vmap_state_bytes(const vmap_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return state_layout(cfg).total;
+}
+
+size_t vmap_workspace_bytes(const vmap_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return work_layout(cfg).total;
+}
+
+int32_t vmap_object_params(const vmap_config* cfg, int32_t hidden) {
+  if (check_config(cfg) || !hidden_ok(hidden, cfg->precision) || hidden > cfg->max_hidden) return 0;
+  return n_params_of(hidden);
+}
+
+int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_dev,
+                      size_t state_bytes, void* workspace_dev, size_t workspace_bytes,
+                      void* stream, vmap_ctx** out) {
+  if (!out) {
+    g_init_error = "out is NULL";
+    return VMAP_EINVAL;
+  }
+  *out = nullptr;
+  if (const char* m = check_config(cfg)) {
+    g_init_error = m;
+    return (cfg && (cfg->n_hidden_layers != kLayers || cfg->n_features != kFeatures)) ? VMAP_ENOTSUP : VMAP_EINVAL;
+  }
+  if (!B_host || !state_dev || !workspace_dev) {
+    g_init_error = "B_host, state_dev and workspace_dev must not be NULL";
+    return VMAP_EINVAL;
+  }
+  if (((uintptr_t)state_dev & 255) || ((uintptr_t)workspace_dev & 255)) {
+    g_init_error = "state and workspace buffers must be 256-byte aligned";
+    return VMAP_EINVAL;
+  }
+  const StateLayout sl = state_layout(cfg);
+  const WorkLayout wl = work_layout(cfg);
+  if (state_bytes < sl.total || workspace_bytes < wl.total) {
+    g_init_error = "state or workspace buffer smaller than vmap_state_bytes / vmap_workspace_bytes";
+    return VMAP_ECAPACITY;
+  }
+  for (int i = 0; i < 3 * kFeatures; ++i) {
+    if (!std::isfinite(B_host[i])) {
+      g_init_error = "B contains a non-finite value";
+      return VMAP_EINVAL;
+    }
+  }
+  const bool bf = cfg->precision == VMAP_BF16;
+  const LdsLayout L = lds_layout(cfg->max_hidden, bf, 4);
+  if (L.total > 160 * 1024) {
+    g_init_error = "model too large for the 160 KB LDS of a workgroup";
+    return VMAP_ENOTSUP;
+  }
+  vmap_ctx* c = new vmap_ctx();
+  c->cfg = *cfg;
+  c->sl = sl;
+  c->wl = wl;
+  c->state = reinterpret_cast<unsigned char*>(state_dev);
+  c->work = reinterpret_cast<unsigned char*>(workspace_dev);
+  c->p_stride = pad_params(n_params_of(cfg->max_hidden));
+  c->rays_per_tile = default_rays_per_tile(cfg);
+  c->objs.resize(cfg->max_objects);
+  hipGetDevice(&c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_zero(state_dev, sl.total, s);
+  if (e == hipSuccess) e = launch_fill_zero(workspace_dev, wl.total, s);
+  if (e == hipSuccess) e = launch_init_scaler(c->scaler(), bf ? (float)cfg->loss_scale_init : 1.0f, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->B(), B_host, 3 * kFeatures * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    g_init_error = std::string("initialising state: ") + hipGetErrorString(e);
+    delete c;
+    return VMAP_EHIP;
+  }
+  *out = c;
+  return VMAP_OK;
+}
+
+int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_params_host,
+                    void* stream, int32_t* object_id_out) {
+  if (!c) return VMAP_EINVAL;
+  if (!d || !object_id_out) return c->fail(VMAP_EINVAL, "desc and object_id_out must not be NULL");
+  const int H = d->hidden ? d->hidden : c->cfg.hidden;
+  if (!hidden_ok(H, c->cfg.precision) || H > c->cfg.max_hidden)
+    return c->fail(VMAP_ENOTSUP, "object hidden width not supported or above max_hidden");
+  if (!(d->scale > 0.f) || !std::isfinite(d->scale)) return c->fail(VMAP_EINVAL, "desc.scale must be > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(d->centre[i])) return c->fail(VMAP_EINVAL, "desc.centre must be finite");
+  if (c->n_registered >= c->cfg.max_objects) return c->fail(VMAP_ECAPACITY, "model stack is full (max_objects)");
+  const int k = c->n_registered;
+  const int P = n_params_of(H);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ObjDesc od{};
+  for (int i = 0; i < 3; ++i) od.centre[i] = (double)d->centre[i];
+  od.inv_scale = 1.0 / (double)d->scale;
+  od.hidden = H;
+  od.registered = 1;
+  od.step = 0;
+  od.n_params = P;
+  double bounds[kLayers + 1];
+  for (int l = 0; l <= kLayers; ++l) {
+    const int fi = (l == 0) ? kEnc : H;
+    const int fo = (l == kLayers) ? kOut : H;
+    bounds[l] = std::sqrt(6.0 / (double)(fi + fo));
+  }
+  hipError_t e = launch_init_object(k, H, d->seed, bounds, od, c->desc(), c->theta(), c->m(), c->v(),
+                                    c->grad(), c->p_stride, init_params_host ? 0 : 1, s);
+  if (e != hipSuccess) return c->hip_fail(e, "init kernel launch");
+  if (init_params_host) {
+    e = hipMemcpyAsync(c->theta() + (size_t)k * c->p_stride, init_params_host, (size_t)P * 4,
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return c->hip_fail(e, "copying initial parameters");
+  }
+  c->objs[k].registered = 1;
+  c->objs[k].hidden = H;
+  c->objs[k].n_params = P;
+  c->n_registered++;
+  *object_id_out = k;
+  return VMAP_OK;
+}
+
+int vmap_train_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  int rc = validate_batch(c, b, true);
+  if (rc) return rc;
+  if (b->n_objects == 0) return VMAP_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!c->graph_mode) return enqueue_train(c, b, loss_out, s, true);
+  // graph replay: one executable graph per batch shape and buffer set
+  std::vector<int64_t> key = {b->n_objects, b->n_rays_total, b->samples_per_ray,
+                              (int64_t)(intptr_t)b->object_ids, (int64_t)(intptr_t)b->ray_offsets,
+                              (int64_t)(intptr_t)b->rays_o, (int64_t)(intptr_t)b->rays_d,
+                              (int64_t)(intptr_t)b->t, (int64_t)(intptr_t)b->depth,
+                              (int64_t)(intptr_t)b->rgb, (int64_t)(intptr_t)b->mask,
+                              (int64_t)(intptr_t)loss_out, c->waves, c->grid_blocks,
+                              (int64_t)widths_present(c).size()};
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (!c->capture_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return c->hip_fail(e, "hipStreamCreate");
+    }
+    hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
+    rc = enqueue_train(c, b, loss_out, c->capture_stream, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->capture_stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      return c->hip_fail(e, "hipGraphInstantiate");
+    }
+    it = c->graphs.emplace(key, vmap_ctx::GraphEntry{g, x}).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second.exec, s);
+  if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
+  return VMAP_OK;
+}
+
+int vmap_forward(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* depth_out, float* rgb_out,
+                 float* occ_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  int rc = validate_batch(c, b, loss_out != nullptr);
+  if (rc) return rc;
+  if (b->n_objects == 0) return VMAP_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
+                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+  if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
+  rc = enqueue_tiles(c, b, MODE_FWD, nullptr, depth_out, rgb_out, occ_out, s, true);
+  if (rc) return rc;
+  if (loss_out) {
+    e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
+                      c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), 0, c->grad(), nullptr,
+                      c->flags(), loss_out, 0, s);
+    if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
+  }
+  return VMAP_OK;
+}
+
+int vmap_render(vmap_ctx* c, const vmap_batch* b, float* depth_out, float* rgb_out, float* occ_out,
+                void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (!b) return c->fail(VMAP_EINVAL, "batch is NULL");
+  if (b->n_rays_total > 0 && !depth_out && !rgb_out && !occ_out)
+    return c->fail(VMAP_EINVAL, "vmap_render needs at least one output");
+  // rendering reads no targets: the batch's depth, rgb and mask may be NULL
+  vmap_batch rb = *b;
+  rb.depth = nullptr;
+  rb.rgb = nullptr;
+  rb.mask = nullptr;
+  b = &rb;
+  return vmap_forward(c, b, nullptr, depth_out, rgb_out, occ_out, stream);
+}
+
+int vmap_backward(vmap_ctx* c, const vmap_batch* b, const float* dloss, float* grad_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  int rc = validate_batch(c, b, true);
+  if (rc) return rc;
+  if (!dloss && b->n_objects > 0) return c->fail(VMAP_EINVAL, "dloss must not be NULL");
+  if (b->n_objects == 0) return VMAP_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
+                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+  if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
+  rc = enqueue_tiles(c, b, MODE_TRAIN, dloss, nullptr, nullptr, nullptr, s, true);
+  if (rc) return rc;
+  const int bf = c->cfg.precision == VMAP_BF16;
+  e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
+                    c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), bf, c->grad(), grad_out,
+                    c->flags(), nullptr, 1, s);
+  if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
+  return VMAP_OK;
+}
+
+int vmap_adam_step(vmap_ctx* c, const vmap_batch* b, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  int rc = validate_batch(c, b, false);
+  if (rc) return rc;
+  if (b->n_objects == 0) return VMAP_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int bf = c->cfg.precision == VMAP_BF16;
+  hipError_t e = launch_adam(b->n_objects, b->object_ids, b->ray_offsets, c->cfg.max_objects, c->desc(),
+                             c->scaler(), c->flags(), c->theta(), c->m(), c->v(), c->grad(), c->p_stride,
+                             c->cfg.lr, c->cfg.beta1, c->cfg.beta2, c->cfg.eps, bf,
+                             c->cfg.scale_growth_interval, s);
+  if (e != hipSuccess) return c->hip_fail(e, "adam launch");
+  return VMAP_OK;
+}
+
+int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, float* occ_out,
+                         float* rgb_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (k < 0 || k >= c->cfg.max_objects || !c->objs[k].registered)
+    return c->fail(VMAP_ESTATE, "object id is not registered");
+  if (n < 0) return c->fail(VMAP_EINVAL, "n must be >= 0");
+  if (n == 0) return VMAP_OK;
+  if (!pts || !occ_out) return c->fail(VMAP_EINVAL, "pts and occ_out must not be NULL");
+  if (n > ((int64_t)1 << 40)) return c->fail(VMAP_EINVAL, "n too large");
+  QueryArgs q{};
+  q.pts = pts;
+  q.n = n;
+  q.k = k;
+  q.theta = c->theta();
+  q.p_stride = c->p_stride;
+  q.desc = c->desc();
+  q.B = c->B();
+  q.occ = occ_out;
+  q.rgb = rgb_out;
+  const bool bf = c->cfg.precision == VMAP_BF16;
+  q.lds = lds_layout(c->objs[k].hidden, bf, 4);
+  hipError_t e = launch_query(c->objs[k].hidden, bf, q, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return c->hip_fail(e, "query launch");
+  return VMAP_OK;
+}
+
+static int state_ptr(vmap_ctx* c, int32_t k, int32_t which, size_t bytes, void** dev) {
+  if (k < 0 || k >= c->cfg.max_objects || !c->objs[k].registered)
+    return c->fail(VMAP_ESTATE, "object id is not registered");
+  const size_t P = (size_t)c->objs[k].n_params;
+  float* base = nullptr;
+  switch (which) {
+    case VMAP_STATE_PARAMS: base = c->theta(); break;
+    case VMAP_STATE_ADAM_M: base = c->m(); break;
+    case VMAP_STATE_ADAM_V: base = c->v(); break;
+    case VMAP_STATE_GRAD: base = c->grad(); break;
+    case VMAP_STATE_STEP:
+      if (bytes != 4) return c->fail(VMAP_EINVAL, "step count is 4 bytes (int32)");
+      *dev = &c->desc()[k].step;
+      return VMAP_OK;
+    default: return c->fail(VMAP_EINVAL, "unknown state selector");
+  }
+  if (bytes != P * 4) return c->fail(VMAP_EINVAL, "bytes must equal 4 * n_params of the object");
+  *dev = base + (size_t)k * c->p_stride;
+  return VMAP_OK;
+}
+
+int vmap_get_state(vmap_ctx* c, int32_t k, int32_t which, void* host_dst, size_t bytes, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (!host_dst) return c->fail(VMAP_EINVAL, "host_dst must not be NULL");
+  void* dev = nullptr;
+  int rc = state_ptr(c, k, which, bytes, &dev);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(host_dst, dev, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "reading state");
+  return VMAP_OK;
+}
+
+int vmap_set_state(vmap_ctx* c, int32_t k, int32_t which, const void* host_src, size_t bytes, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (!host_src) return c->fail(VMAP_EINVAL, "host_src must not be NULL");
+  void* dev = nullptr;
+  int rc = state_ptr(c, k, which, bytes, &dev);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(dev, host_src, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "writing state");
+  return VMAP_OK;
+}
+
+int vmap_step_info(vmap_ctx* c, float* loss_scale, int32_t* skipped, int32_t* device_error, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  ScalerState h{};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&h, c->scaler(), sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "reading step info");
+  if (loss_scale) *loss_scale = h.scale;
+  if (skipped) *skipped = h.skipped;
+  if (device_error) *device_error = h.device_error;
+  return VMAP_OK;
+}
+
+int vmap_param_layout(const vmap_ctx* c, int32_t k, int32_t* n_params, int32_t* stride) {
+  if (!c) return VMAP_EINVAL;
+  if (k < 0 || k >= c->cfg.max_objects || !c->objs[k].registered) return VMAP_ESTATE;
+  if (n_params) *n_params = c->objs[k].n_params;
+  if (stride) *stride = c->p_stride;
+  return VMAP_OK;
+}
+
+int vmap_set_graph_mode(vmap_ctx* c, int32_t enabled) {
+  if (!c) return VMAP_EINVAL;
+  c->graph_mode = enabled != 0;
+  return VMAP_OK;
+}
+
+int vmap_set_launch(vmap_ctx* c, int32_t waves, int32_t grid_blocks) {
+  if (!c) return VMAP_EINVAL;
+  if (waves < 1 || waves > 4) return c->fail(VMAP_EINVAL, "waves_per_block must be in [1, 4]");
+  if (grid_blocks < 0) return c->fail(VMAP_EINVAL, "grid_blocks must be >= 0");
+  c->waves = waves;
+  c->grid_blocks = grid_blocks;
+  return VMAP_OK;
+}
+
+int vmap_kernel_timing(vmap_ctx* c, int32_t enable, double* avg_ms, int32_t* count) {
+  if (!c) return VMAP_EINVAL;
+  double total = 0.0;
+  int n = 0;
+  for (auto& t : c->timed) {
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventElapsedTime");
+    total += ms;
+    ++n;
+  }
+  if (avg_ms) *avg_ms = n ? total / n : 0.0;
+  if (count) *count = n;
+  if (enable >= 0) {
+    for (auto& t : c->timed) {
+      c->event_pool.push_back(t.a);
+      c->event_pool.push_back(t.b);
+    }
+    c->timed.clear();
+    c->timing = enable != 0;
+  }
+  return VMAP_OK;
+}
+
+const char* vmap_last_error(const vmap_ctx* c) {
+  if (!c) return g_init_error.c_str();
+  return c->err.c_str();
+}
+
+void vmap_destroy(vmap_ctx* c) {
+  if (!c) return;
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+  }
+  for (auto& t : c->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : c->event_pool) hipEventDestroy(e);
+  if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal types shared by the host library (vmap_api.cpp) and the HIP kernels (vmap_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vmapi {
+
+constexpr int kFeatures = 16;        // Fourier features per sine/cosine half
+constexpr int kEnc = 2 * kFeatures;  // encoding width E
+constexpr int kOut = 4;              // (r, g, b, occupancy)
+constexpr int kLayers = 4;           // hidden ReLU layers
+constexpr int kWave = 64;
+constexpr int kSlots = 64;           // sample slots per wave sub-tile (two MFMA column blocks)
+
+enum Mode { MODE_FWD = 0, MODE_TRAIN = 1 };
+
+// Per-object descriptor in device memory (one slot per possible object id).
+struct ObjDesc {
+  double centre[3];    // normalisation centre c_k
+  double inv_scale;    // 1 / s_k
+  int32_t hidden;      // MLP width
+  int32_t registered;  // 1 once vmap_add_object ran
+  int32_t step;        // Adam step count t_k
+  int32_t n_params;    // parameters of this object
+};
+
+// Loss scaler and step bookkeeping in device memory.
+struct ScalerState {
+  float scale;          // dynamic loss scale (1 in FP32 mode)
+  int32_t good_steps;   // consecutive steps without a skipped object
+  int32_t skipped;      // objects skipped by the last Adam launch
+  int32_t device_error; // set when a batch names an invalid object
+  int32_t ticket;       // completion counter of the Adam launch (last block finalises)
+  int32_t pad[11];
+};
+
+// Byte offsets of the LDS regions of the tile kernel (computed identically on host and device).
+struct LdsLayout {
+  int w_off[kLayers];  // W_l, rows = H, padded row stride, permuted columns
+  int w_stride[kLayers];
+  int b_off;           // kLayers x H biases (FP32)
+  int wh_off;          // head weights [4][H + 4] FP32, permuted columns
+  int bh_off;          // head biases [4]
+  int B_off;           // encoding matrix [3][16] FP32
+  int scratch_off;     // per-wave staging, then the tile's gradient sum
+  int scratch_wave;    // bytes per wave
+  int loss_off;        // one float
+  int total;
+};
+
+__host__ __device__ inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+__host__ __device__ inline int n_params_of(int H) {
+  return (H * kEnc + H) + (kLayers - 1) * (H * H + H) + (kOut * H + kOut);
+}
+
+__host__ __device__ inline LdsLayout lds_layout(int H, bool bf16, int nwaves) {
+  LdsLayout L{};
+  const int es = bf16 ? 2 : 4;
+  const int pad = bf16 ? 8 : 4;
+  int off = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : H;
+    L.w_stride[l] = K + pad;
+    L.w_off[l] = off;
+    off = round_up(off + H * (K + pad) * es, 16);
+  }
+  L.b_off = off;
+  off = round_up(off + kLayers * H * 4, 16);
+  L.wh_off = off;
+  off = round_up(off + kOut * (H + 4) * 4, 16);
+  L.bh_off = off;
+  off = round_up(off + kOut * 4, 16);
+  L.B_off = off;
+  off = round_up(off + 3 * kFeatures * 4, 16);
+  L.loss_off = off;
+  off = round_up(off + 16, 16);
+  // staging per wave: delta and activation tiles plus dz [32][4]
+  const int tile_bytes = bf16 ? (H * 40 * 2) : (32 * (H + 4) * 4);
+  L.scratch_wave = round_up(2 * tile_bytes + 32 * kOut * 4, 16);
+  L.scratch_off = off;
+  int scratch = nwaves * L.scratch_wave;
+  const int red = n_params_of(H) * 4;
+  if (red > scratch) scratch = red;
+  off = round_up(off + scratch, 16);
+  L.total = off;
+  return L;
+}
+
+struct StepArgs {
+  // batch
+  int n_objects;
+  int S;
+  int rays_per_tile;
+  int max_objects;
+  const int32_t* object_ids;
+  const int32_t* ray_offsets;
+  const float* rays_o;
+  const float* rays_d;
+  const float* t;
+  const float* depth;
+  const float* rgb;
+  const float* mask;
+  // model state
+  const float* theta;
+  int p_stride;
+  int hidden;            // width handled by this launch
+  const ObjDesc* desc;
+  ScalerState* scaler;
+  const float* B;        // [3][16]
+  // work buffers
+  const int32_t* tile_start;  // [n_objects + 1]
+  float* partial;             // [tiles][p_stride]
+  float* tile_loss;           // [tiles]
+  const float* dloss;         // [n_objects] upstream weights (backward) or NULL
+  float* out_depth;
+  float* out_rgb;
+  float* out_occ;
+  float lambda_c;
+  float lambda_o;
+  int use_scale;              // multiply seeds by the loss scale (BF16 training)
+  LdsLayout lds;
+};
+
+struct QueryArgs {
+  const float* pts;
+  int64_t n;
+  int k;
+  const float* theta;
+  int p_stride;
+  const ObjDesc* desc;
+  const float* B;
+  float* occ;
+  float* rgb;
+  LdsLayout lds;
+};
+
+// Kernel launchers (vmap_kernels.hip). Return hipSuccess or the launch error.
+hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
+                           int rays_per_tile, int max_objects, int32_t* tile_start,
+                           int32_t* flags, hipStream_t s);
+hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,
+                        hipStream_t s);
+hipError_t launch_reduce(int n_objects, const int32_t* object_ids, const int32_t* tile_start,
+                         const float* partial, const float* tile_loss, int p_stride,
+                         int max_objects, const ObjDesc* desc, const ScalerState* scaler,
+                         int unscale, float* grad, float* grad_out, int32_t* flags,
+                         float* loss_out, int want_grad, hipStream_t s);
+hipError_t launch_adam(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
+                       int max_objects, ObjDesc* desc, ScalerState* scaler,
+                       const int32_t* flags, float* theta, float* m, float* v,
+                       const float* grad, int p_stride, double lr, double beta1,
+                       double beta2, double eps, int bf16, int growth_interval,
+                       hipStream_t s);
+hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,
+                              const ObjDesc& d, ObjDesc* desc, float* theta, float* m,
+                              float* v, float* grad, int p_stride, int use_rng,
+                              hipStream_t s);
+hipError_t launch_query(int H, bool bf16, const QueryArgs& q, hipStream_t s);
+hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s);
+int tiles_supported(int H, bool bf16);
+
+}  // namespace vmapi

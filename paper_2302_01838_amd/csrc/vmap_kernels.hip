@@ -1,0 +1,1008 @@
+// HIP kernels for gfx950 (CDNA4) of the vectorised per-object training step.
+//
+// Work decomposition. A batch holds the rays of many objects, segmented by CSR offsets. Each
+// object's rays are cut into tiles of `rays_per_tile` consecutive rays; a tile never straddles
+// two objects and its boundaries are relative to the object's first ray, so an object's result
+// does not depend on the other objects in the batch. One workgroup processes one tile at a time
+// (grid-stride, so the launch may be persistent). Inside a tile, each 64-lane wave takes
+// sub-tiles of floor(64 / S) whole rays: the S samples of a ray occupy S consecutive lanes.
+//
+// Per sub-tile a wave runs, without leaving registers except for two small LDS transposes:
+//   1. point normalisation in FP64, rounded once to FP32, and Gaussian Fourier features
+//      (object-level encoding, supplement Sec. B);
+//   2. the MLP on MFMA, 32 samples per pass, features on the M axis and samples on the N axis,
+//      so each layer's accumulator layout is directly the next layer's B operand (the K axis
+//      is permuted consistently in the weights instead of moving data);
+//   3. occupancy rendering of Eq. 3 with ray-segmented wavefront scans: an exclusive
+//      multiplicative scan of (1 - o) and additive scans for the rendered sums;
+//   4. the masked L1 losses of Eqs. 4-7;
+//   5. the adjoint of rendering: with g_i the derivative of the loss with respect to the
+//      termination probability T_i, a reverse affine scan S_i = o_{i+1} g_{i+1} +
+//      (1 - o_{i+1}) S_{i+1} gives dL/do_i = P_i (g_i - S_i) with no division;
+//   6. the MLP backward: dX products on MFMA from the accumulator layout, dW products on MFMA
+//      after an LDS transpose, accumulated in registers across the wave's sub-tiles.
+// The waves of a workgroup then add their gradients in a fixed order and write one partial
+// per tile; a second kernel sums each object's tile partials in tile order (no float atomics,
+// bitwise reproducible), and a third applies Adam per object.
+//
+// Precision. FP32 mode uses v_mfma_f32_32x32x2f32 and accurate sincosf/expf. BF16 mode rounds
+// weights, activations and back-propagated deltas to BF16 (round to nearest even) where they
+// enter a product and uses v_mfma_f32_32x32x16_bf16 with FP32 accumulation; encoding, head
+// activations, rendering, losses, reductions and Adam stay FP32.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "vmap_internal.h"
+
+namespace vmapi {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Accumulator row held in register r (0..15) by lanes of half h (0, 1) of a 32x32 MFMA tile.
+// The same map orders the K axis: K slot (h, r) of a block carries feature rowof(r, h).
+__host__ __device__ constexpr int rowof(int r, int h) { return ((r >> 2) << 3) + (h << 2) + (r & 3); }
+// Position of feature c (0..31) of a block in the permuted weight-column order.
+__host__ __device__ constexpr int colpos(int c) { return (((c >> 2) & 1) << 4) + ((c >> 3) << 2) + (c & 3); }
+
+__device__ __forceinline__ void wave_lds_sync() {
+  // Orders this wave's LDS accesses across lanes: the compiler may not move LDS loads or stores
+  // across it, and the wave waits until its own LDS operations have completed.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+__device__ __forceinline__ float sgnf(float x) { return (x > 0.f) ? 1.f : ((x < 0.f) ? -1.f : 0.f); }
+
+template <bool BF>
+__device__ __forceinline__ float round_w(float x) {
+  if constexpr (BF) return (float)(__bf16)x;
+  return x;
+}
+
+// Activations of one 32-sample pass: NL + 1 layers (encoding first), H/32 blocks, D layout.
+template <int H, bool BF>
+struct Acts;
+template <int H>
+struct Acts<H, false> {
+  float v[kLayers + 1][H / 32][16];
+  __device__ __forceinline__ float get(int l, int b, int r) const { return v[l][b][r]; }
+  __device__ __forceinline__ void set(int l, int b, int r, float x) { v[l][b][r] = x; }
+};
+template <int H>
+struct Acts<H, true> {
+  bf16x8 v[kLayers + 1][H / 32][2];
+  __device__ __forceinline__ float get(int l, int b, int r) const { return (float)v[l][b][r >> 3][r & 7]; }
+  __device__ __forceinline__ void set(int l, int b, int r, float x) { v[l][b][r >> 3][r & 7] = (__bf16)x; }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Weight staging: object k's parameters -> LDS (permuted columns; BF16 in BF16 mode).
+
+template <int H, bool BF>
+__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem, const LdsLayout& L) {
+  using WT = typename std::conditional<BF, __bf16, float>::type;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int off = 0;
+  float* bias = reinterpret_cast<float*>(smem + L.b_off);
+#pragma unroll
+  for (int l = 0; l < kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : H;
+    WT* W = reinterpret_cast<WT*>(smem + L.w_off[l]);
+    const int ws = L.w_stride[l];
+    for (int e = tid; e < H * K; e += nt) {
+      const int row = e / K, col = e - row * K;
+      W[row * ws + (col & ~31) + colpos(col & 31)] = (WT)th[off + e];
+    }
+    off += H * K;
+    for (int e = tid; e < H; e += nt) bias[l * H + e] = th[off + e];
+    off += H;
+  }
+  float* Wh = reinterpret_cast<float*>(smem + L.wh_off);
+  for (int e = tid; e < kOut * H; e += nt) {
+    const int c = e / H, col = e - c * H;
+    Wh[c * (H + 4) + (col & ~31) + colpos(col & 31)] = round_w<BF>(th[off + e]);
+  }
+  off += kOut * H;
+  float* bh = reinterpret_cast<float*>(smem + L.bh_off);
+  if (tid < kOut) bh[tid] = th[off + tid];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward of one 32-sample pass for the calling wave. xt: this lane's normalised point (the
+// sample of column n = lane & 31; both lane halves hold the same point). Fills acts and
+// returns the four head outputs z (identical in both halves).
+
+template <int H, bool BF>
+__device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
+                                             const LdsLayout& L, Acts<H, BF>& A, float z[4]) {
+  constexpr int MT = H / 32;
+  // Weights are re-read from LDS on every pass instead of being held in registers across passes.
+  asm volatile("" ::: "memory");
+  const int lane = threadIdx.x & 63, n = lane & 31, hf = lane >> 5;
+  const float* Bm = reinterpret_cast<const float*>(smem + L.B_off);
+  // Gaussian Fourier features: register r of block 0 holds feature rowof(r, hf):
+  // r = 0..3 sin(phi[4hf + r]), 4..7 sin(phi[8 + 4hf + r - 4]), 8..15 the cosines.
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = 8 * g + 4 * hf + i;
+      const float phi = xt[0] * Bm[f] + xt[1] * Bm[kFeatures + f] + xt[2] * Bm[2 * kFeatures + f];
+      float s, c;
+      sincosf(phi, &s, &c);
+      A.set(0, 0, 4 * g + i, s);
+      A.set(0, 0, 8 + 4 * g + i, c);
+    }
+  }
+  const float* bias = reinterpret_cast<const float*>(smem + L.b_off);
+#pragma unroll
+  for (int l = 0; l < kLayers; ++l) {
+    const int KB = (l == 0) ? 1 : MT;
+    const int ws = L.w_stride[l];
+#pragma unroll
+    for (int mo = 0; mo < MT; ++mo) {
+      f32x16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = bias[l * H + mo * 32 + rowof(r, hf)];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        if constexpr (BF) {
+          const __bf16* wrow = reinterpret_cast<const __bf16*>(smem + L.w_off[l]) +
+                               (mo * 32 + n) * ws + kb * 32 + 16 * hf;
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const bf16x8 wa = *reinterpret_cast<const bf16x8*>(wrow + 8 * jj);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, A.v[l][kb][jj], acc, 0, 0, 0);
+          }
+        } else {
+          const float* wrow = reinterpret_cast<const float*>(smem + L.w_off[l]) +
+                              (mo * 32 + n) * ws + kb * 32 + 16 * hf;
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wrow[q], A.v[l][kb][q], acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) A.set(l + 1, mo, r, fmaxf(acc[r], 0.0f));
+    }
+  }
+  // output layer (4 x H) on the VALU: each half sums its 16 features per block, then the halves
+  // are added (the same two addends in both halves, so both hold the same value)
+  const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+  const float* bh = reinterpret_cast<const float*>(smem + L.bh_off);
+#pragma unroll
+  for (int c = 0; c < kOut; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * A.get(kLayers, mt, r);
+    s += __shfl_xor(s, 32);
+    z[c] = s + bh[c];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The step's tile kernel.
+
+template <int H, bool BF, int MODE>
+__global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
+  constexpr int MT = H / 32;
+  constexpr bool TRAIN = (MODE == MODE_TRAIN);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const LdsLayout& L = a.lds;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = lane & 31, hf = lane >> 5;
+  const int S = a.S;
+  const int rpw = kSlots / S;
+  const int n_tiles = a.tile_start[a.n_objects];
+  const float lc = a.lambda_c, lo = a.lambda_o;
+
+  if (tid < 3 * kFeatures) reinterpret_cast<float*>(smem + L.B_off)[tid] = a.B[tid];
+  int staged = -1;
+
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // object of this tile: largest j with tile_start[j] <= tile
+    int jlo = 0, jhi = a.n_objects;
+    while (jhi - jlo > 1) {
+      const int mid = (jlo + jhi) >> 1;
+      if (a.tile_start[mid] <= tile) jlo = mid; else jhi = mid;
+    }
+    const int j = jlo;
+    const int k = a.object_ids[j];
+    if (k < 0 || k >= a.max_objects || !a.desc[k].registered) {
+      if (tid == 0) atomicOr(&a.scaler->device_error, 1);
+      continue;
+    }
+    if (a.desc[k].hidden != H) continue;  // handled by the launch for that width
+    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * a.rays_per_tile;
+    const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
+    if (k != staged) {
+      __syncthreads();
+      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, L);
+      staged = k;
+    }
+    __syncthreads();
+    const double cx = a.desc[k].centre[0], cy = a.desc[k].centre[1], cz = a.desc[k].centre[2];
+    const double inv_s = a.desc[k].inv_scale;
+    float wseed = 1.0f;
+    if constexpr (TRAIN) {
+      if (a.dloss) wseed = a.dloss[j];
+      if (a.use_scale) wseed *= a.scaler->scale;
+    }
+
+    f32x16 accW[kLayers][MT][MT];
+    float accH[kOut][MT];
+    float accDb[kLayers][MT];
+    float accDbH[kOut];
+    if constexpr (TRAIN) {
+#pragma unroll
+      for (int l = 0; l < kLayers; ++l)
+#pragma unroll
+        for (int mo = 0; mo < MT; ++mo) {
+          accDb[l][mo] = 0.f;
+#pragma unroll
+          for (int ki = 0; ki < MT; ++ki)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) accW[l][mo][ki][r] = 0.f;
+        }
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) {
+        accDbH[c] = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) accH[c][mt] = 0.f;
+      }
+    }
+    float wave_loss = 0.f;
+
+    unsigned char* scr = smem + L.scratch_off + wave * L.scratch_wave;
+    const int nrays = ray_hi - ray_lo;
+    const int nsub = (nrays + rpw - 1) / rpw;
+
+    for (int sub = wave; sub < nsub; sub += nw) {
+      asm volatile("" ::: "memory");
+      const int r0 = ray_lo + sub * rpw;
+      const int nr = min(rpw, ray_hi - r0);
+      const int nslots = nr * S;
+
+      // ---------------- forward. Pass 0 (samples 0..31) is recomputed before its backward, so
+      // only one pass of activations is live at a time; pass 1 keeps its activations.
+      auto point = [&](int p, float xt[3]) {
+        const int slot = 32 * p + n;
+        xt[0] = xt[1] = xt[2] = 0.f;
+        if (slot < nslots) {
+          const int ray = r0 + slot / S;
+          const double tt = (double)a.t[(size_t)r0 * S + slot];
+          const float* o3 = a.rays_o + 3 * (size_t)ray;
+          const float* d3 = a.rays_d + 3 * (size_t)ray;
+          xt[0] = (float)(((double)o3[0] + tt * (double)d3[0] - cx) * inv_s);
+          xt[1] = (float)(((double)o3[1] + tt * (double)d3[1] - cy) * inv_s);
+          xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - cz) * inv_s);
+        }
+      };
+      Acts<H, BF> act;
+      float zs[kOut];
+      {
+        float xt[3], z[kOut];
+        point(0, xt);
+        forward_pass<H, BF>(xt, smem, L, act, z);
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) zs[c] = z[c];
+        point(1, xt);
+        forward_pass<H, BF>(xt, smem, L, act, z);
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) zs[c] = (hf == 1) ? z[c] : zs[c];
+      }
+
+      // ---------------- rendering along each ray: lane = slot
+      const bool valid = lane < nslots;
+      const int jr = valid ? lane / S : 0;
+      const int si = valid ? lane - jr * S : 0;
+      const int ray = r0 + jr;
+      float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f}, tt = 0.f;
+      if (valid) {
+        o = sigm(zs[3]);
+        q = sigm(-zs[3]);  // 1 - o, without cancellation
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
+        tt = a.t[(size_t)r0 * S + lane];
+      }
+      // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift
+      float Pin = q;
+      for (int off = 1; off < S; off <<= 1) {
+        const float u = __shfl_up(Pin, off);
+        if (si >= off) Pin *= u;
+      }
+      float Pex = __shfl_up(Pin, 1);
+      if (si == 0) Pex = 1.f;
+      const float Tw = o * Pex;  // termination probability T_i
+      float sO = Tw, sD = Tw * tt, sC0 = Tw * c3[0], sC1 = Tw * c3[1], sC2 = Tw * c3[2];
+      for (int off = 1; off < S; off <<= 1) {
+        const float u0 = __shfl_up(sO, off), u1 = __shfl_up(sD, off), u2 = __shfl_up(sC0, off),
+                    u3 = __shfl_up(sC1, off), u4 = __shfl_up(sC2, off);
+        if (si >= off) { sO += u0; sD += u1; sC0 += u2; sC1 += u3; sC2 += u4; }
+      }
+      const int last = jr * S + S - 1;
+      const float Oh = __shfl(sO, last), Dh = __shfl(sD, last);
+      const float Ch[3] = {__shfl(sC0, last), __shfl(sC1, last), __shfl(sC2, last)};
+      const float Pend = __shfl(Pin, last);
+
+      float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
+      if (valid) {
+        // rendering without targets (forward mode, NULL target buffers) evaluates the loss terms
+        // against zero targets; that loss is not reported
+        const bool tg = TRAIN || a.depth != nullptr;
+        const float D = tg ? a.depth[ray] : 0.f, M = tg ? a.mask[ray] : 0.f;
+        const float rD = Dh - D;
+        float rC[3] = {Ch[0], Ch[1], Ch[2]};
+        if (tg) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rC[c] -= a.rgb[3 * ray + c];
+        }
+        const float rho = (M == 1.0f) ? -Pend : (Oh - M);
+        if (si == 0) {
+          wave_loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
+          if constexpr (!TRAIN) {
+            if (a.out_depth) a.out_depth[ray] = Dh;
+            if (a.out_occ) a.out_occ[ray] = Oh;
+            if (a.out_rgb) { a.out_rgb[3 * ray] = Ch[0]; a.out_rgb[3 * ray + 1] = Ch[1]; a.out_rgb[3 * ray + 2] = Ch[2]; }
+          }
+        }
+        if constexpr (TRAIN) {
+          const float aD = wseed * M * sgnf(rD);
+          const float aO = wseed * lo * sgnf(rho);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) aC[c] = wseed * lc * M * sgnf(rC[c]);
+          g = aD * tt + aC[0] * c3[0] + aC[1] * c3[1] + aC[2] * c3[2] + aO;
+        }
+      }
+      if constexpr (!TRAIN) continue;
+
+      // ---------------- adjoint of rendering: reverse affine scan Q_i = o_i g_i + (1 - o_i) Q_{i+1}
+      float Aq = q, Bq = o * g;
+      for (int off = 1; off < S; off <<= 1) {
+        const float A2 = __shfl_down(Aq, off), B2 = __shfl_down(Bq, off);
+        if (si + off < S) { Bq = Bq + Aq * B2; Aq = Aq * A2; }
+      }
+      float Snext = __shfl_down(Bq, 1);
+      if (si == S - 1) Snext = 0.f;
+      float dzs[kOut];
+      if (valid) {
+        const float dO = Pex * (g - Snext);
+        dzs[3] = dO * o * q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dzs[c] = Tw * aC[c] * c3[c] * cq[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) dzs[c] = 0.f;
+      }
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
+
+      // ---------------- MLP backward, one pass of 32 samples at a time
+      float* dzl = reinterpret_cast<float*>(scr);
+      unsigned char* dtile = scr + 32 * kOut * 4;
+      unsigned char* htile = dtile + (BF ? H * 40 * 2 : 32 * (H + 4) * 4);
+      const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        const int p = 1 - pp;
+        if (p == 0) {  // recompute the activations of pass 0
+          float xt[3], z[kOut];
+          point(0, xt);
+          forward_pass<H, BF>(xt, smem, L, act, z);
+        }
+        float dz[kOut];
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) dz[c] = __shfl(dzs[c], 32 * p + n);
+        // stage dz and h_L, transposed for the output layer's weight gradient
+        wave_lds_sync();
+        if (hf == 0) {
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) dzl[n * kOut + c] = dz[c];
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int f = mt * 32 + rowof(r, hf);
+            if constexpr (BF)
+              reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[kLayers][mt][r >> 3][r & 7];
+            else
+              reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[kLayers][mt][r];
+          }
+        wave_lds_sync();
+        // output-layer weight gradient: lane owns feature mt*32 + n, half hf takes 16 samples
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int s2 = 0; s2 < 16; ++s2) {
+            const int s = 16 * hf + s2;
+            float hv;
+            if constexpr (BF) hv = (float)reinterpret_cast<const __bf16*>(htile)[(mt * 32 + n) * 40 + s];
+            else hv = reinterpret_cast<const float*>(htile)[s * (H + 4) + mt * 32 + n];
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) accH[c][mt] += dzl[s * kOut + c] * hv;
+          }
+        }
+        // delta of the last hidden layer: (W_out^T dz) masked by ReLU'
+        float dl[MT][16];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * dz[c];
+            dl[mt][r] = (act.get(kLayers, mt, r) > 0.f) ? s : 0.f;
+          }
+#pragma unroll
+        for (int l = kLayers - 1; l >= 0; --l) {
+          const int KB = (l == 0) ? 1 : MT;
+          // stage delta_l (out features) and h_{l-1} (in features) transposed
+          wave_lds_sync();
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int f = mt * 32 + rowof(r, hf);
+              if constexpr (BF) reinterpret_cast<__bf16*>(dtile)[f * 40 + n] = (__bf16)dl[mt][r];
+              else reinterpret_cast<float*>(dtile)[n * (H + 4) + f] = dl[mt][r];
+            }
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int f = kb * 32 + rowof(r, hf);
+              if constexpr (BF)
+                reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[l][kb][r >> 3][r & 7];
+              else
+                reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[l][kb][r];
+            }
+          wave_lds_sync();
+          // weight gradient dW_l += delta_l h_{l-1}^T over the pass's 32 samples
+#pragma unroll
+          for (int mo = 0; mo < MT; ++mo) {
+#pragma unroll
+            for (int ki = 0; ki < KB; ++ki) {
+              if constexpr (BF) {
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                  const bf16x8 da = *reinterpret_cast<const bf16x8*>(
+                      reinterpret_cast<const __bf16*>(dtile) + (mo * 32 + n) * 40 + 16 * jj + 8 * hf);
+                  const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
+                      reinterpret_cast<const __bf16*>(htile) + (ki * 32 + n) * 40 + 16 * jj + 8 * hf);
+                  accW[l][mo][ki] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, hb, accW[l][mo][ki], 0, 0, 0);
+                  if (ki == 0) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) s += (float)da[e];
+                    accDb[l][mo] += s;
+                  }
+                }
+              } else {
+#pragma unroll
+                for (int qq = 0; qq < 16; ++qq) {
+                  const int s = 2 * qq + hf;
+                  const float da = reinterpret_cast<const float*>(dtile)[s * (H + 4) + mo * 32 + n];
+                  const float hb = reinterpret_cast<const float*>(htile)[s * (H + 4) + ki * 32 + n];
+                  accW[l][mo][ki] = __builtin_amdgcn_mfma_f32_32x32x2f32(da, hb, accW[l][mo][ki], 0, 0, 0);
+                  if (ki == 0) accDb[l][mo] += da;
+                }
+              }
+            }
+          }
+          if (l == 0) break;
+          // delta_{l-1} = (W_l^T delta_l) masked by ReLU' of layer l-1
+          const int ws = L.w_stride[l];
+          float nd[MT][16];
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi) {
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            const int col = mi * 32 + colpos(n);
+#pragma unroll
+            for (int ko = 0; ko < MT; ++ko) {
+              if constexpr (BF) {
+                const __bf16* W = reinterpret_cast<const __bf16*>(smem + L.w_off[l]);
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                  bf16x8 wa, db;
+#pragma unroll
+                  for (int e = 0; e < 8; ++e) {
+                    wa[e] = W[(ko * 32 + rowof(8 * jj + e, hf)) * ws + col];
+                    db[e] = (__bf16)dl[ko][8 * jj + e];
+                  }
+                  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, db, acc, 0, 0, 0);
+                }
+              } else {
+                const float* W = reinterpret_cast<const float*>(smem + L.w_off[l]);
+#pragma unroll
+                for (int qq = 0; qq < 16; ++qq)
+                  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W[(ko * 32 + rowof(qq, hf)) * ws + col],
+                                                             dl[ko][qq], acc, 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) nd[mi][r] = (act.get(l, mi, r) > 0.f) ? acc[r] : 0.f;
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dl[mt][r] = nd[mt][r];
+        }
+      }
+    }  // sub-tiles
+
+    // ---------------- combine the waves of the workgroup in a fixed order
+    // per-wave reductions in registers first
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) wave_loss += __shfl_xor(wave_loss, off);
+    if constexpr (TRAIN) {
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) accDbH[c] += __shfl_xor(accDbH[c], off);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) accH[c][mt] += __shfl_xor(accH[c][mt], 32);
+      }
+#pragma unroll
+      for (int l = 0; l < kLayers; ++l)
+#pragma unroll
+        for (int mo = 0; mo < MT; ++mo) accDb[l][mo] += __shfl_xor(accDb[l][mo], 32);
+    }
+    __syncthreads();  // staging buffers are free: reuse them for the tile's gradient
+    float* red = reinterpret_cast<float*>(smem + L.scratch_off);
+    float* lsum = reinterpret_cast<float*>(smem + L.loss_off);
+    for (int w = 0; w < nw; ++w) {
+      if (wave == w) {
+        const bool first = (w == 0);
+        if (lane == 0) lsum[0] = (first ? 0.f : lsum[0]) + wave_loss;
+        if constexpr (TRAIN) {
+          int off = 0;
+#pragma unroll
+          for (int l = 0; l < kLayers; ++l) {
+            const int K = (l == 0) ? kEnc : H;
+            const int KB = K / 32;
+#pragma unroll
+            for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+              for (int ki = 0; ki < KB; ++ki)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                  const int idx = off + (mo * 32 + rowof(r, hf)) * K + ki * 32 + n;
+                  red[idx] = (first ? 0.f : red[idx]) + accW[l][mo][ki][r];
+                }
+            off += H * K;
+            if (hf == 0) {
+#pragma unroll
+              for (int mo = 0; mo < MT; ++mo) {
+                const int idx = off + mo * 32 + n;
+                red[idx] = (first ? 0.f : red[idx]) + accDb[l][mo];
+              }
+            }
+            off += H;
+          }
+          if (hf == 0) {
+#pragma unroll
+            for (int c = 0; c < kOut; ++c)
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                const int idx = off + c * H + mt * 32 + n;
+                red[idx] = (first ? 0.f : red[idx]) + accH[c][mt];
+              }
+          }
+          off += kOut * H;
+          if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) red[off + c] = (first ? 0.f : red[off + c]) + accDbH[c];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if constexpr (TRAIN) {
+      const int P = n_params_of(H);
+      float* dst = a.partial + (size_t)tile * a.p_stride;
+      for (int e = tid; e < P; e += blockDim.x) dst[e] = red[e];
+    }
+    if (tid == 0) a.tile_loss[tile] = lsum[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Shape query of one object: forward only, 64 points per wave iteration.
+
+template <int H, bool BF>
+__global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const LdsLayout& L = qa.lds;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n = lane & 31, hf = lane >> 5;
+  if (tid < 3 * kFeatures) reinterpret_cast<float*>(smem + L.B_off)[tid] = qa.B[tid];
+  stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem, L);
+  __syncthreads();
+  const ObjDesc d = qa.desc[qa.k];
+  for (int64_t chunk = (int64_t)blockIdx.x * nw + wave; chunk * kSlots < qa.n; chunk += (int64_t)gridDim.x * nw) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int64_t i = chunk * kSlots + 32 * p + n;
+      float xt[3] = {0.f, 0.f, 0.f};
+      if (i < qa.n) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xt[c] = (float)(((double)qa.pts[3 * i + c] - d.centre[c]) * d.inv_scale);
+      }
+      Acts<H, BF> act;
+      float z[kOut];
+      forward_pass<H, BF>(xt, smem, L, act, z);
+      if (i < qa.n && hf == 0) {
+        qa.occ[i] = sigm(z[3]);
+        if (qa.rgb) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) qa.rgb[3 * i + c] = sigm(z[c]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Tile offsets per batch object (exclusive scan of ceil(rays / rays_per_tile)); clears the
+// non-finite flags of the batch's objects.
+
+__global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t* __restrict__ ids,
+                                                   const int32_t* __restrict__ offs, int rpt,
+                                                   int max_objects, int32_t* __restrict__ tile_start,
+                                                   int32_t* __restrict__ flags) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (n_objects + nt - 1) / nt;
+  const int j0 = min(tid * per, n_objects), j1 = min(j0 + per, n_objects);
+  int local = 0;
+  for (int j = j0; j < j1; ++j) {
+    const int nr = offs[j + 1] - offs[j];
+    local += (nr > 0) ? (nr + rpt - 1) / rpt : 0;
+    const int k = ids[j];
+    if (k >= 0 && k < max_objects) flags[k] = 0;
+  }
+  part[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - local;
+  for (int j = j0; j < j1; ++j) {
+    tile_start[j] = run;
+    const int nr = offs[j + 1] - offs[j];
+    run += (nr > 0) ? (nr + rpt - 1) / rpt : 0;
+  }
+  if (tid == nt - 1) tile_start[n_objects] = part[nt - 1];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-object gradient: sum of the object's tile partials in tile order, unscaled.
+
+__global__ void __launch_bounds__(256) k_reduce(int n_objects, const int32_t* __restrict__ ids,
+                                                const int32_t* __restrict__ tile_start,
+                                                const float* __restrict__ partial,
+                                                const float* __restrict__ tile_loss, int p_stride,
+                                                int max_objects, const ObjDesc* __restrict__ desc,
+                                                const ScalerState* __restrict__ scaler, int unscale,
+                                                float* __restrict__ grad, float* __restrict__ grad_out,
+                                                int32_t* __restrict__ flags, float* __restrict__ loss_out,
+                                                int want_grad) {
+  const int j = blockIdx.y;
+  const int k = ids[j];
+  const bool valid = k >= 0 && k < max_objects && desc[k].registered;
+  const int t0 = tile_start[j], t1 = tile_start[j + 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
+    float s = 0.f;
+    if (valid)
+      for (int t = t0; t < t1; ++t) s += tile_loss[t];
+    loss_out[j] = s;
+  }
+  if (!want_grad || !valid) return;
+  const int P = desc[k].n_params;
+  const float inv = unscale ? 1.0f / scaler->scale : 1.0f;
+  bool bad = false;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < p_stride; p += gridDim.x * blockDim.x) {
+    float g = 0.f;
+    if (p < P) {
+      for (int t = t0; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
+      g *= inv;
+      bad |= !isfinite(g);
+    }
+    grad[(size_t)k * p_stride + p] = g;
+    if (grad_out) grad_out[(size_t)j * p_stride + p] = g;
+  }
+  if (bad) atomicOr(&flags[k], 1);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adam per object; the last block to finish advances the step counts and the loss scaler.
+
+__global__ void __launch_bounds__(256) k_adam(int n_objects, const int32_t* __restrict__ ids,
+                                              const int32_t* __restrict__ offs, int max_objects,
+                                              ObjDesc* __restrict__ desc, ScalerState* __restrict__ sc,
+                                              const int32_t* __restrict__ flags, float* __restrict__ theta,
+                                              float* __restrict__ mom, float* __restrict__ vel,
+                                              const float* __restrict__ grad, int p_stride, double lr,
+                                              double beta1, double beta2, double eps, int bf16,
+                                              int growth) {
+  __shared__ float coef[4];
+  __shared__ int is_last;
+  __shared__ int red[256];
+  const int j = blockIdx.y;
+  const int k = ids[j];
+  const bool valid = k >= 0 && k < max_objects && desc[k].registered;
+  const bool active = valid && (offs[j + 1] > offs[j]) && flags[k] == 0;
+  if (active) {
+    if (threadIdx.x == 0) {
+      const double t = (double)(desc[k].step + 1);
+      const double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
+      coef[0] = (float)(lr / bc1);
+      coef[1] = (float)(1.0 / sqrt(bc2));
+    }
+    __syncthreads();
+    const float step = coef[0], rs = coef[1];
+    const float b1 = (float)beta1, c1 = (float)(1.0 - beta1), b2 = (float)beta2, c2 = (float)(1.0 - beta2);
+    const float ep = (float)eps;
+    const int P = desc[k].n_params;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+      const size_t i = (size_t)k * p_stride + p;
+      const float g = grad[i];
+      const float m = b1 * mom[i] + c1 * g;
+      const float v = b2 * vel[i] + c2 * g * g;
+      mom[i] = m;
+      vel[i] = v;
+      theta[i] = theta[i] - step * m / (sqrtf(v) * rs + ep);
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tk = atomicAdd(&sc->ticket, 1);
+    is_last = (tk == (int)(gridDim.x * gridDim.y) - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  int skipped = 0;
+  for (int jj = threadIdx.x; jj < n_objects; jj += blockDim.x) {
+    const int kk = ids[jj];
+    if (kk < 0 || kk >= max_objects || !desc[kk].registered) continue;
+    if (offs[jj + 1] <= offs[jj]) continue;
+    if (flags[kk]) ++skipped; else desc[kk].step += 1;
+  }
+  red[threadIdx.x] = skipped;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int total = red[0];
+    sc->skipped = total;
+    if (bf16) {
+      if (total > 0) {
+        sc->scale *= 0.5f;
+        sc->good_steps = 0;
+      } else if (++sc->good_steps >= growth) {
+        sc->scale *= 2.0f;
+        sc->good_steps = 0;
+      }
+    }
+    sc->ticket = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Object initialisation: Xavier-uniform weights from SplitMix64 in counter mode, zero biases,
+// zero Adam moments and gradient; also writes the object's descriptor.
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct InitBounds {
+  double bound[kLayers + 1];
+  int w_end[kLayers + 1];
+  int b_end[kLayers + 1];
+};
+
+__global__ void __launch_bounds__(256) k_init(int k, uint64_t seed, InitBounds ib, ObjDesc d,
+                                              ObjDesc* __restrict__ desc, float* __restrict__ theta,
+                                              float* __restrict__ mom, float* __restrict__ vel,
+                                              float* __restrict__ grad, int p_stride, int P, int use_rng) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) desc[k] = d;
+  if (p >= p_stride) return;
+  const size_t i = (size_t)k * p_stride + p;
+  if (use_rng) {
+    float w = 0.f;
+    if (p < P) {
+      for (int l = 0; l <= kLayers; ++l) {
+        if (p < ib.w_end[l]) {  // weight of layer l
+          const uint64_t z = splitmix64_at(seed, (uint64_t)p);
+          const double u = (double)(z >> 40) * 0x1p-24;
+          w = (float)(ib.bound[l] * (2.0 * u - 1.0));
+          break;
+        }
+        if (p < ib.b_end[l]) break;  // bias of layer l: zero
+      }
+    }
+    theta[i] = w;
+  } else if (p >= P) {
+    theta[i] = 0.f;
+  }
+  mom[i] = 0.f;
+  vel[i] = 0.f;
+  grad[i] = 0.f;
+}
+
+__global__ void k_fill_zero(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_init_scaler(ScalerState* sc, float scale) {
+  if (threadIdx.x == 0) {
+    sc->scale = scale;
+    sc->good_steps = 0;
+    sc->skipped = 0;
+    sc->device_error = 0;
+    sc->ticket = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launchers.
+
+template <int H, bool BF, int MODE>
+static hipError_t launch_tiles_t(const StepArgs& a, int nwaves, int grid, hipStream_t s) {
+  static bool attr_done = false;
+  auto fn = k_step_tiles<H, BF, MODE>;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(nwaves * kWave), a.lds.total, s, a);
+  return hipGetLastError();
+}
+
+int tiles_supported(int H, bool bf16) {
+  (void)bf16;
+  return H == 32 || H == 64;
+}
+
+hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,
+                        hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define VMAP_TILES(HH, BB)                                                                     \
+  if (H == HH && bf16 == BB) {                                                                 \
+    return mode == MODE_TRAIN ? launch_tiles_t<HH, BB, MODE_TRAIN>(a, nwaves, grid, s)        \
+                              : launch_tiles_t<HH, BB, MODE_FWD>(a, nwaves, grid, s);         \
+  }
+  VMAP_TILES(32, false)
+  VMAP_TILES(32, true)
+  VMAP_TILES(64, false)
+  VMAP_TILES(64, true)
+#undef VMAP_TILES
+  return hipErrorInvalidValue;
+}
+
+template <int H, bool BF>
+static hipError_t launch_query_t(const QueryArgs& q, hipStream_t s) {
+  static bool attr_done = false;
+  auto fn = k_query<H, BF>;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  const int nw = 4;
+  int64_t chunks = (q.n + kSlots - 1) / kSlots;
+  int grid = (int)std::min<int64_t>((chunks + nw - 1) / nw, 2048);
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(nw * kWave), q.lds.total, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(int H, bool bf16, const QueryArgs& q, hipStream_t s) {
+  if (H == 32 && !bf16) return launch_query_t<32, false>(q, s);
+  if (H == 32 && bf16) return launch_query_t<32, true>(q, s);
+  if (H == 64 && !bf16) return launch_query_t<64, false>(q, s);
+  if (H == 64 && bf16) return launch_query_t<64, true>(q, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s, reinterpret_cast<uint32_t*>(dst), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
+                           int rays_per_tile, int max_objects, int32_t* tile_start,
+                           int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, object_ids, ray_offsets,
+                     rays_per_tile, max_objects, tile_start, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int n_objects, const int32_t* object_ids, const int32_t* tile_start,
+                         const float* partial, const float* tile_loss, int p_stride,
+                         int max_objects, const ObjDesc* desc, const ScalerState* scaler,
+                         int unscale, float* grad, float* grad_out, int32_t* flags,
+                         float* loss_out, int want_grad, hipStream_t s) {
+  if (n_objects <= 0) return hipSuccess;
+  const int gx = want_grad ? (p_stride + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_reduce, dim3(gx, n_objects), dim3(256), 0, s, n_objects, object_ids,
+                     tile_start, partial, tile_loss, p_stride, max_objects, desc, scaler, unscale,
+                     grad, grad_out, flags, loss_out, want_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
+                       int max_objects, ObjDesc* desc, ScalerState* scaler,
+                       const int32_t* flags, float* theta, float* m, float* v,
+                       const float* grad, int p_stride, double lr, double beta1,
+                       double beta2, double eps, int bf16, int growth_interval,
+                       hipStream_t s) {
+  if (n_objects <= 0) return hipSuccess;
+  const int gx = (p_stride + 255) / 256;
+  hipLaunchKernelGGL(k_adam, dim3(gx, n_objects), dim3(256), 0, s, n_objects, object_ids,
+                     ray_offsets, max_objects, desc, scaler, flags, theta, m, v, grad, p_stride,
+                     lr, beta1, beta2, eps, bf16, growth_interval);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,
+                              const ObjDesc& d, ObjDesc* desc, float* theta, float* m,
+                              float* v, float* grad, int p_stride, int use_rng,
+                              hipStream_t s) {
+  InitBounds ib{};
+  int off = 0;
+  for (int l = 0; l <= kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : H;
+    const int O = (l == kLayers) ? kOut : H;
+    ib.bound[l] = bounds[l];
+    off += O * K;
+    ib.w_end[l] = off;
+    off += O;
+    ib.b_end[l] = off;
+  }
+  const int P = off;
+  hipLaunchKernelGGL(k_init, dim3((p_stride + 255) / 256), dim3(256), 0, s, k, seed, ib, d, desc,
+                     theta, m, v, grad, p_stride, P, use_rng);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_scaler, dim3(1), dim3(64), 0, s, sc, scale);
+  return hipGetLastError();
+}
+
+}  // namespace vmapi

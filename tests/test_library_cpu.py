@@ -1,0 +1,91 @@
+"""Host-side checks of libvmap that need no GPU: the library loads, exports every entry point
+that include/vmap.h declares, and rejects bad configurations before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2302_01838_amd as vm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "vmap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vmap_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(vm.library_path()):
+        pytest.skip("libvmap.so is not built")
+    return vm.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(vm.EXPORTED), set(names) ^ set(vm.EXPORTED)
+
+
+def test_sizes_and_params(lib):
+    cfg = vm.default_config(max_objects=50, hidden=32, max_rays=20000, max_samples_per_ray=20)
+    sb = lib.vmap_state_bytes(ctypes.byref(cfg))
+    wb = lib.vmap_workspace_bytes(ctypes.byref(cfg))
+    stride = (4356 + 63) // 64 * 64
+    assert sb >= 4 * 50 * stride * 4           # theta, m, v, grad
+    assert wb >= 20000 // 24 * stride * 4        # one partial per tile
+    assert lib.vmap_object_params(ctypes.byref(cfg), 32) == 4356
+    cfg64 = vm.default_config(hidden=64)
+    assert lib.vmap_object_params(ctypes.byref(cfg64), 64) == 14852
+
+
+@pytest.mark.parametrize("field,value", [("max_objects", 0), ("n_features", 8),
+                                         ("n_hidden_layers", 3), ("hidden", 48),
+                                         ("max_samples_per_ray", 65), ("precision", 7),
+                                         ("lr", 0.0), ("beta2", 1.0), ("max_rays", -1)])
+def test_invalid_config_rejected(lib, field, value):
+    cfg = vm.default_config()
+    setattr(cfg, field, value)
+    assert lib.vmap_state_bytes(ctypes.byref(cfg)) == 0
+    assert lib.vmap_workspace_bytes(ctypes.byref(cfg)) == 0
+    ctx = ctypes.c_void_p()
+    B = np.zeros((3, 16), np.float32)
+    rc = lib.vmap_init_objects(ctypes.byref(cfg), B.ctypes.data, ctypes.c_void_p(256), 1 << 30,
+                               ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx))
+    assert rc in (1, 5) and not ctx.value
+    assert lib.vmap_last_error(None)
+
+
+def test_init_argument_errors_before_device_use(lib):
+    cfg = vm.default_config()
+    ctx = ctypes.c_void_p()
+    B = np.zeros((3, 16), np.float32)
+    # NULL encoding matrix
+    assert lib.vmap_init_objects(ctypes.byref(cfg), None, ctypes.c_void_p(256), 1 << 30,
+                                 ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx)) == 1
+    # misaligned buffers
+    assert lib.vmap_init_objects(ctypes.byref(cfg), B.ctypes.data, ctypes.c_void_p(260), 1 << 30,
+                                 ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx)) == 1
+    # buffers too small
+    assert lib.vmap_init_objects(ctypes.byref(cfg), B.ctypes.data, ctypes.c_void_p(256), 16,
+                                 ctypes.c_void_p(256), 16, None, ctypes.byref(ctx)) == 2
+    # non-finite B
+    B[1, 3] = np.nan
+    assert lib.vmap_init_objects(ctypes.byref(cfg), B.ctypes.data, ctypes.c_void_p(256), 1 << 30,
+                                 ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx)) == 1
+    assert b"non-finite" in lib.vmap_last_error(None)
+    # NULL context handles are rejected, destroy(NULL) is a no-op
+    assert lib.vmap_train_step(None, None, None, None) == 1
+    lib.vmap_destroy(None)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(vm.VmapConfig) == 10 * 4 + 7 * 8
+    assert ctypes.sizeof(vm.VmapObjectDesc) == 32
+    assert ctypes.sizeof(vm.VmapBatch) == 16 + 8 * 8

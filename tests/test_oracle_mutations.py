@@ -1,0 +1,106 @@
+"""Planted mistakes in the oracle (on the CPU) must each fail at least one of its pins.
+
+Every mutation below is a plausible slip when writing the oracle from the paper: a dropped term,
+a wrong sign or index, a swapped head, a transposed operand. The test patches it into the oracle
+module, runs the pins that should notice, and requires at least one of them to fail.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+
+def _render_no_shift(o, c, t):
+    # T_i uses the product up to and including sample i (index off by one)
+    R, S = o.shape
+    P = np.empty((R, S + 1))
+    P[:, 0] = 1.0
+    for i in range(S):
+        P[:, i + 1] = P[:, i] * (1.0 - o[:, i])
+    T = o * P[:, 1:]
+    return T.sum(1), (T * t).sum(1), (T[:, :, None] * c).sum(1), T, P
+
+
+_orig_render = oracle.render
+_orig_vjp = oracle.render_vjp
+_orig_heads = oracle.heads
+_orig_mlp = oracle.mlp_forward
+_orig_adam = oracle.adam_update
+_orig_encode = oracle.encode
+_orig_ray_losses = oracle.ray_losses
+
+
+def _vjp_sign(o, c, t, gO, gD, gC, gPend):
+    do, dc = _orig_vjp(o, c, t, gO, gD, gC, -np.asarray(gPend))
+    return do, dc
+
+
+def _heads_swapped(z):
+    return _orig_heads(z[..., [3, 1, 2, 0]])
+
+
+def _mlp_no_relu(theta, gamma, H, L, rnd=None):
+    layers = oracle.unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
+    h = gamma
+    pre = []
+    for W, b in layers[:-1]:
+        a = h @ W.T + b
+        pre.append(a)
+        h = a
+    W, b = layers[-1]
+    return h @ W.T + b, pre
+
+
+def _adam_no_bias_correction(theta, m, v, g, step_count, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    return theta - lr * m / (np.sqrt(v) + eps), m, v
+
+
+def _encode_swapped(x, B):
+    phi = x @ np.asarray(B, np.float64)
+    return np.concatenate([np.cos(phi), np.sin(phi)], axis=-1)
+
+
+def _losses_no_colour_mask(O, D, C, P_end, depth, rgb, mask):
+    ld, lc, lo, rho = _orig_ray_losses(O, D, C, P_end, depth, rgb, mask)
+    return ld, np.abs(C - rgb).sum(-1), lo, rho
+
+
+MUTATIONS = {
+    "render_index_off_by_one": ("render", _render_no_shift),
+    "vjp_wrong_sign_of_leftover_transmittance": ("render_vjp", _vjp_sign),
+    "occupancy_and_red_heads_swapped": ("heads", _heads_swapped),
+    "relu_dropped": ("mlp_forward", _mlp_no_relu),
+    "adam_without_bias_correction": ("adam_update", _adam_no_bias_correction),
+    "sin_cos_swapped": ("encode", _encode_swapped),
+    "colour_loss_not_masked": ("ray_losses", _losses_no_colour_mask),
+}
+
+PINS = [
+    pins.test_encoding_at_origin,
+    pins.test_mlp_forward_matches_torch_linear,
+    pins.test_render_brute_force_product,
+    pins.test_render_special_cases,
+    pins.test_render_vjp_closed_form,
+    pins.test_loss_hand_example,
+    lambda: pins.test_render_constant_occupancy_closed_form(0.3, 10),
+    lambda: pins.test_gradient_matches_torch_autograd(0),
+    pins.test_adam_first_step_closed_form,
+    pins.test_adam_second_step_values,
+    pins.test_adam_matches_torch_optim,
+]
+
+
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(oracle, attr, fn)
+    failures = 0
+    for pin in PINS:
+        try:
+            pin()
+        except (AssertionError, ValueError, IndexError):
+            failures += 1
+    assert failures > 0, f"no pin caught the planted mistake {name}"
