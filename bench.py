@@ -136,7 +136,19 @@ def main():
                     help="distinct pre-generated batches (default: warmup + steps)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the step has no "
               "cross-GPU exchange; objects would be sharded across GPUs, see DESIGN.md)",

@@ -32,8 +32,7 @@ struct ScalerState {
   int32_t good_steps;   // consecutive steps without a skipped object
   int32_t skipped;      // objects skipped by the last Adam launch
   int32_t device_error; // set when a batch names an invalid object
-  int32_t ticket;       // completion counter of the Adam launch (last block finalises)
-  int32_t pad[11];
+  int32_t pad[12];
 };
 
 // Byte offsets of the LDS regions of the tile kernel (computed identically on host and device).
@@ -50,13 +49,15 @@ struct LdsLayout {
   int total;
 };
 
-__host__ __device__ inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+__host__ __device__ constexpr int round_up(int x, int a) { return (x + a - 1) / a * a; }
 
-__host__ __device__ inline int n_params_of(int H) {
+__host__ __device__ constexpr int n_params_of(int H) {
   return (H * kEnc + H) + (kLayers - 1) * (H * H + H) + (kOut * H + kOut);
 }
 
-__host__ __device__ inline LdsLayout lds_layout(int H, bool bf16, int nwaves) {
+// Every offset except `total` is independent of the wave count, so kernels evaluate the layout at
+// compile time (immediate LDS offsets) and only the host needs `total`.
+__host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves) {
   LdsLayout L{};
   const int es = bf16 ? 2 : 4;
   const int pad = bf16 ? 8 : 4;

@@ -25,7 +25,10 @@
 // per tile; a second kernel sums each object's tile partials in tile order (no float atomics,
 // bitwise reproducible), and a third applies Adam per object.
 //
-// Precision. FP32 mode uses v_mfma_f32_32x32x2f32 and accurate sincosf/expf. BF16 mode rounds
+// Precision. Both modes use the sine/cosine of vmap_math.h (error below 2.5e-7; the hardware
+// v_sin/v_cos approximations were tried for BF16 and moved enough features across BF16 rounding
+// boundaries to show in the gradients) and accurate expf. FP32 mode uses v_mfma_f32_32x32x2f32.
+// BF16 mode rounds
 // weights, activations and back-propagated deltas to BF16 (round to nearest even) where they
 // enter a product and uses v_mfma_f32_32x32x16_bf16 with FP32 accumulation; encoding, head
 // activations, rendering, losses, reductions and Adam stay FP32.
@@ -38,6 +41,7 @@
 #include <type_traits>
 
 #include "vmap_internal.h"
+#include "vmap_math.h"
 
 namespace vmapi {
 
@@ -89,7 +93,8 @@ struct Acts<H, true> {
 // Weight staging: object k's parameters -> LDS (permuted columns; BF16 in BF16 mode).
 
 template <int H, bool BF>
-__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem, const LdsLayout& L) {
+__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem) {
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
   using WT = typename std::conditional<BF, __bf16, float>::type;
   const int tid = threadIdx.x, nt = blockDim.x;
   int off = 0;
@@ -124,8 +129,9 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem,
 
 template <int H, bool BF>
 __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
-                                             const LdsLayout& L, Acts<H, BF>& A, float z[4]) {
+                                             Acts<H, BF>& A, float z[4]) {
   constexpr int MT = H / 32;
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
   // Weights are re-read from LDS on every pass instead of being held in registers across passes.
   asm volatile("" ::: "memory");
   const int lane = threadIdx.x & 63, n = lane & 31, hf = lane >> 5;
@@ -139,7 +145,7 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
       const int f = 8 * g + 4 * hf + i;
       const float phi = xt[0] * Bm[f] + xt[1] * Bm[kFeatures + f] + xt[2] * Bm[2 * kFeatures + f];
       float s, c;
-      sincosf(phi, &s, &c);
+      vmap_sincosf(phi, &s, &c);
       A.set(0, 0, 4 * g + i, s);
       A.set(0, 0, 8 + 4 * g + i, c);
     }
@@ -200,7 +206,7 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
   constexpr int MT = H / 32;
   constexpr bool TRAIN = (MODE == MODE_TRAIN);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const LdsLayout& L = a.lds;
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = lane & 31, hf = lane >> 5;
   const int S = a.S;
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
     const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
     if (k != staged) {
       __syncthreads();
-      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, L);
+      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem);
       staged = k;
     }
     __syncthreads();
@@ -275,8 +281,9 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
       const int nr = min(rpw, ray_hi - r0);
       const int nslots = nr * S;
 
-      // ---------------- forward. Pass 0 (samples 0..31) is recomputed before its backward, so
-      // only one pass of activations is live at a time; pass 1 keeps its activations.
+      // ---------------- forward of both passes for the head outputs only. Each pass's
+      // activations are recomputed right before its backward (activation recomputation), so no
+      // activation is held across the rendering.
       auto point = [&](int p, float xt[3]) {
         const int slot = 32 * p + n;
         xt[0] = xt[1] = xt[2] = 0.f;
@@ -290,18 +297,15 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
           xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - cz) * inv_s);
         }
       };
-      Acts<H, BF> act;
-      float zs[kOut];
-      {
+      float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+        Acts<H, BF> tmp;
         float xt[3], z[kOut];
-        point(0, xt);
-        forward_pass<H, BF>(xt, smem, L, act, z);
+        point(p, xt);
+        forward_pass<H, BF>(xt, smem, tmp, z);
 #pragma unroll
-        for (int c = 0; c < kOut; ++c) zs[c] = z[c];
-        point(1, xt);
-        forward_pass<H, BF>(xt, smem, L, act, z);
-#pragma unroll
-        for (int c = 0; c < kOut; ++c) zs[c] = (hf == 1) ? z[c] : zs[c];
+        for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
       }
 
       // ---------------- rendering along each ray: lane = slot
@@ -394,13 +398,13 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
       unsigned char* dtile = scr + 32 * kOut * 4;
       unsigned char* htile = dtile + (BF ? H * 40 * 2 : 32 * (H + 4) * 4);
       const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
-#pragma unroll
-      for (int pp = 0; pp < 2; ++pp) {
-        const int p = 1 - pp;
-        if (p == 0) {  // recompute the activations of pass 0
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+        Acts<H, BF> act;
+        {  // recompute the activations of this pass
           float xt[3], z[kOut];
-          point(0, xt);
-          forward_pass<H, BF>(xt, smem, L, act, z);
+          point(p, xt);
+          forward_pass<H, BF>(xt, smem, act, z);
         }
         float dz[kOut];
 #pragma unroll
@@ -628,11 +632,11 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
 template <int H, bool BF>
 __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const LdsLayout& L = qa.lds;
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = lane & 31, hf = lane >> 5;
   if (tid < 3 * kFeatures) reinterpret_cast<float*>(smem + L.B_off)[tid] = qa.B[tid];
-  stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem, L);
+  stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem);
   __syncthreads();
   const ObjDesc d = qa.desc[qa.k];
   for (int64_t chunk = (int64_t)blockIdx.x * nw + wave; chunk * kSlots < qa.n; chunk += (int64_t)gridDim.x * nw) {
@@ -646,7 +650,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
       }
       Acts<H, BF> act;
       float z[kOut];
-      forward_pass<H, BF>(xt, smem, L, act, z);
+      forward_pass<H, BF>(xt, smem, act, z);
       if (i < qa.n && hf == 0) {
         qa.occ[i] = sigm(z[3]);
         if (qa.rgb) {
@@ -723,7 +727,16 @@ __global__ void __launch_bounds__(256) k_reduce(int n_objects, const int32_t* __
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < p_stride; p += gridDim.x * blockDim.x) {
     float g = 0.f;
     if (p < P) {
-      for (int t = t0; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
+      // loads are issued eight at a time, then added in tile order
+      int t = t0;
+      for (; t + 8 <= t1; t += 8) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g += x[u];
+      }
+      for (; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
       g *= inv;
       bad |= !isfinite(g);
     }
@@ -734,7 +747,10 @@ __global__ void __launch_bounds__(256) k_reduce(int n_objects, const int32_t* __
 }
 
 // ---------------------------------------------------------------------------------------------
-// Adam per object; the last block to finish advances the step counts and the loss scaler.
+// Adam, one block per batch object: the block updates all of the object's parameters and then
+// advances its step count, so no other block reads or writes that count. Block 0 also updates
+// the loss scaler from the non-finite flags, which the reduction kernel finished writing. No
+// device-scope fence is needed: every cross-block dependency crosses a kernel boundary.
 
 __global__ void __launch_bounds__(256) k_adam(int n_objects, const int32_t* __restrict__ ids,
                                               const int32_t* __restrict__ offs, int max_objects,
@@ -744,71 +760,66 @@ __global__ void __launch_bounds__(256) k_adam(int n_objects, const int32_t* __re
                                               const float* __restrict__ grad, int p_stride, double lr,
                                               double beta1, double beta2, double eps, int bf16,
                                               int growth) {
-  __shared__ float coef[4];
-  __shared__ int is_last;
+  __shared__ float coef[2];
   __shared__ int red[256];
-  const int j = blockIdx.y;
+  const int j = blockIdx.x;
   const int k = ids[j];
   const bool valid = k >= 0 && k < max_objects && desc[k].registered;
   const bool active = valid && (offs[j + 1] > offs[j]) && flags[k] == 0;
-  if (active) {
+  if (j == 0) {
+    // loss scaler: count the batch objects with rays whose gradient was not finite
+    int skipped = 0;
+    for (int jj = threadIdx.x; jj < n_objects; jj += blockDim.x) {
+      const int kk = ids[jj];
+      if (kk >= 0 && kk < max_objects && desc[kk].registered && offs[jj + 1] > offs[jj] && flags[kk])
+        ++skipped;
+    }
+    red[threadIdx.x] = skipped;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
     if (threadIdx.x == 0) {
-      const double t = (double)(desc[k].step + 1);
-      const double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
-      coef[0] = (float)(lr / bc1);
-      coef[1] = (float)(1.0 / sqrt(bc2));
-    }
-    __syncthreads();
-    const float step = coef[0], rs = coef[1];
-    const float b1 = (float)beta1, c1 = (float)(1.0 - beta1), b2 = (float)beta2, c2 = (float)(1.0 - beta2);
-    const float ep = (float)eps;
-    const int P = desc[k].n_params;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-      const size_t i = (size_t)k * p_stride + p;
-      const float g = grad[i];
-      const float m = b1 * mom[i] + c1 * g;
-      const float v = b2 * vel[i] + c2 * g * g;
-      mom[i] = m;
-      vel[i] = v;
-      theta[i] = theta[i] - step * m / (sqrtf(v) * rs + ep);
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tk = atomicAdd(&sc->ticket, 1);
-    is_last = (tk == (int)(gridDim.x * gridDim.y) - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  int skipped = 0;
-  for (int jj = threadIdx.x; jj < n_objects; jj += blockDim.x) {
-    const int kk = ids[jj];
-    if (kk < 0 || kk >= max_objects || !desc[kk].registered) continue;
-    if (offs[jj + 1] <= offs[jj]) continue;
-    if (flags[kk]) ++skipped; else desc[kk].step += 1;
-  }
-  red[threadIdx.x] = skipped;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const int total = red[0];
-    sc->skipped = total;
-    if (bf16) {
-      if (total > 0) {
-        sc->scale *= 0.5f;
-        sc->good_steps = 0;
-      } else if (++sc->good_steps >= growth) {
-        sc->scale *= 2.0f;
-        sc->good_steps = 0;
+      const int total = red[0];
+      sc->skipped = total;
+      if (bf16) {
+        if (total > 0) {
+          sc->scale *= 0.5f;
+          sc->good_steps = 0;
+        } else if (++sc->good_steps >= growth) {
+          sc->scale *= 2.0f;
+          sc->good_steps = 0;
+        }
       }
     }
-    sc->ticket = 0;
   }
+  if (!active) return;
+  const int t = desc[k].step + 1;
+  if (threadIdx.x == 0) {
+    const double bc1 = 1.0 - pow(beta1, (double)t), bc2 = 1.0 - pow(beta2, (double)t);
+    coef[0] = (float)(lr / bc1);
+    coef[1] = (float)(1.0 / sqrt(bc2));
+  }
+  __syncthreads();
+  const float step = coef[0], rs = coef[1];
+  const float b1 = (float)beta1, c1 = (float)(1.0 - beta1), b2 = (float)beta2, c2 = (float)(1.0 - beta2);
+  const float ep = (float)eps;
+  const int P = desc[k].n_params;
+  float* th = theta + (size_t)k * p_stride;
+  float* mm = mom + (size_t)k * p_stride;
+  float* vv = vel + (size_t)k * p_stride;
+  const float* gg = grad + (size_t)k * p_stride;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const float g = gg[p];
+    const float m = b1 * mm[p] + c1 * g;
+    const float v = b2 * vv[p] + c2 * g * g;
+    mm[p] = m;
+    vv[p] = v;
+    th[p] = th[p] - step * m / (sqrtf(v) * rs + ep);
+  }
+  __syncthreads();  // every thread has read the step count above
+  if (threadIdx.x == 0) desc[k].step = t;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -868,7 +879,6 @@ __global__ void k_init_scaler(ScalerState* sc, float scale) {
     sc->good_steps = 0;
     sc->skipped = 0;
     sc->device_error = 0;
-    sc->ticket = 0;
   }
 }
 
@@ -972,8 +982,7 @@ hipError_t launch_adam(int n_objects, const int32_t* object_ids, const int32_t* 
                        double beta2, double eps, int bf16, int growth_interval,
                        hipStream_t s) {
   if (n_objects <= 0) return hipSuccess;
-  const int gx = (p_stride + 255) / 256;
-  hipLaunchKernelGGL(k_adam, dim3(gx, n_objects), dim3(256), 0, s, n_objects, object_ids,
+  hipLaunchKernelGGL(k_adam, dim3(n_objects), dim3(256), 0, s, n_objects, object_ids,
                      ray_offsets, max_objects, desc, scaler, flags, theta, m, v, grad, p_stride,
                      lr, beta1, beta2, eps, bf16, growth_interval);
   return hipGetLastError();
