@@ -80,6 +80,9 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
     k_ms, k_n = objs.kernel_timing(0)
     k_samples = statistics.mean(dev_batches[i % len(dev_batches)].n_samples for i in range(timing_steps))
     scale, skipped, err = objs.step_info()
+    launch = {"tuned": bool(objs.tuned)}
+    if objs.tuned:
+        launch.update({k: objs.tuned[k] for k in ("rays_per_tile", "waves", "grid")})
     objs.close()
     return dict(
         precision=precision,
@@ -96,7 +99,72 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
         kernel_ms=k_ms,
         kernel_launches=k_n,
         kernel_samples=k_samples,
+        launch=launch,
     )
+
+
+def sweep_objects(counts, steps, precision, graph):
+    """Vectorised vs sequential training step over object counts (the paper's Sec. 4.5 ablation,
+    on synthetic scenes shaped like its workload: 120 rays x 10 samples per object, hidden 32).
+
+    Vectorised: one vmap_train_step over all objects. Sequential: one vmap_train_step per object
+    (a per-object loop of the same kernels). Returns ms per step for each count.
+    """
+    import dataclasses
+    import torch
+    import scenes
+    import paper_2302_01838_amd as vm
+    base = scenes.make_scene("tiny_k4")
+    out = []
+    for K in counts:
+        rng = np.random.default_rng(K)
+        objs_ = []
+        for k in range(K):
+            o = base.objects[k % base.n_objects]
+            objs_.append(dataclasses.replace(o, centre=rng.uniform(-2, 2, size=3),
+                                             seed=(1 << 40) + k))
+        sc = dataclasses.replace(base, objects=objs_)
+        batches = [scenes.make_batch(sc, i) for i in range(3)]
+        full = [vm.DeviceBatch(b) for b in batches]
+        per_obj = []
+        for b in batches:
+            offs = b["ray_offsets"]
+            row = []
+            for j in range(K):
+                sl = slice(offs[j], offs[j + 1])
+                sub = {f: b[f][sl] for f in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
+                sub["object_ids"] = b["object_ids"][j:j + 1]
+                sub["ray_offsets"] = np.array([0, offs[j + 1] - offs[j]], dtype=np.int32)
+                sub["S"] = b["S"]
+                row.append(vm.DeviceBatch(sub))
+            per_obj.append(row)
+        res = {"objects": K}
+        for mode in ("vectorised", "sequential"):
+            objs = vm.ObjectSet(max_objects=K, B=sc.B, hidden=32, precision=precision,
+                                max_rays=full[0].n_rays, max_samples_per_ray=sc.S)
+            for ob in sc.objects:
+                objs.add(ob.norm_centre, ob.norm_scale, hidden=32, seed=ob.seed)
+            objs.set_graph_mode(graph)
+
+            def one(i):
+                if mode == "vectorised":
+                    objs.step(full[i % 3])
+                else:
+                    for db in per_obj[i % 3]:
+                        objs.step(db)
+            for i in range(3):
+                one(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                one(i)
+            torch.cuda.synchronize()
+            res[mode + "_ms"] = 1e3 * (time.perf_counter() - t0) / steps
+            objs.close()
+        log(f"sweep K={K}: vectorised {res['vectorised_ms']:.3f} ms, "
+            f"sequential {res['sequential_ms']:.3f} ms")
+        out.append(res)
+    return out
 
 
 def cpu_baseline(scene, batches, budget_s=15.0):
@@ -131,11 +199,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--graph", type=int, default=0, help="replay the step as a hipGraph")
+    ap.add_argument("--graph", type=int, default=1, help="replay the step as a hipGraph")
     ap.add_argument("--distinct-batches", type=int, default=0,
                     help="distinct pre-generated batches (default: warmup + steps)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--sweep-objects", type=int, nargs="*", default=None,
+                    help="only run the vectorised-vs-sequential sweep over these object counts")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -148,6 +218,14 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+        return
+    if args.sweep_objects is not None:
+        counts = args.sweep_objects or [1, 10, 20, 30, 40, 50, 100, 150, 200]
+        res = sweep_objects(counts, max(1, min(args.steps, 50)), args.forms.split(",")[-1],
+                            bool(args.graph))
+        print(json.dumps({"sweep": "vectorised_vs_sequential", "precision": args.forms.split(",")[-1],
+                          "rays_per_object": 120, "samples_per_ray": 10, "hidden": 32,
+                          "results": res}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the step has no "
@@ -206,7 +284,8 @@ def main():
         "config": {"workload": "K=50 objects, rays/object U[60,600], 20 samples/ray, hidden 32, "
                                "4 hidden layers, Adam lr 1e-3",
                    "objects": scene.n_objects, "samples_per_step": dev_batches[0].n_samples,
-                   "graph": bool(args.graph), "parallelism": "single GPU"},
+                   "graph": bool(args.graph), "parallelism": "single GPU",
+                   "launch": {k: v for k, v in head.get("launch", {}).items()}},
         "object_steps_per_s": head["object_steps_per_s"],
         "forms": {k: {kk: v[kk] for kk in ("ray_samples_per_s", "object_steps_per_s", "ms_per_step",
                                            "median_event_ms", "final_loss", "first_loss",

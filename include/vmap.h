@@ -63,7 +63,7 @@ typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed
  * "Surface and Volume Rendering"). Parameters of one object are stored, in this order,
  * W_1 [H x E], b_1 [H], W_2 [H x H], b_2, ..., W_L, b_L, W_out [4 x H], b_out [4], every W
  * row-major as [out][in]; E = 2 * n_features. Supported: n_features = 16, n_hidden_layers = 4,
- * hidden in {32, 64} (FP32) or {32, 64, 128} (BF16), 1 <= max_samples_per_ray <= 64.
+ * hidden in {32, 64}, 1 <= max_samples_per_ray <= 64.
  */
 typedef struct {
   int32_t max_objects;          /* capacity of the model stack, 1..65536 */
@@ -161,6 +161,20 @@ int vmap_render(vmap_ctx* ctx, const vmap_batch* batch, float* depth_out, float*
  * [n, 3]) under object `object_id`'s model (shape query inside its bound, Sec. 3.4). */
 int vmap_query_occupancy(vmap_ctx* ctx, int32_t object_id, const float* pts_world_dev,
                          int64_t n, float* occ_out, float* rgb_out, void* stream);
+
+/*
+ * Depth-guided samples along rays (Sec. 3.3, Eqs. 1 and 2): for ray r, n_strat stratified
+ * samples t_n + (i + u) / n_strat * (t_s - t_n), i < n_strat, and S - n_strat samples
+ * t_s + sigma * z with z standard normal, where t_s = depth[r] if depth[r] > 0 and t_far[r]
+ * otherwise (invalid depth). The S values are sorted ascending into t_out [n_rays, S].
+ * Randomness: uniform j of sample i of ray r is output 2 (r S + i) + j of the SplitMix64 stream
+ * started at `seed` (top 24 bits * 2^-24; the Box-Muller u1 is (top 24 bits + 1) * 2^-24).
+ * Arithmetic in FP64, rounded once to FP32. All arrays are device pointers: t_near, t_far,
+ * depth [n_rays] FP32 in, t_out [n_rays, S] FP32 out. 1 <= S <= 64, 0 <= n_strat <= S.
+ */
+int vmap_sample_rays(vmap_ctx* ctx, int32_t n_rays, int32_t S, int32_t n_strat,
+                     const float* t_near, const float* t_far, const float* depth, float sigma,
+                     uint64_t seed, float* t_out, void* stream);
 
 /* Autograd split of the step. vmap_forward: per-object losses and renders (outputs may be
  * NULL). vmap_backward: gradient of sum_j dloss[j] * L^{object_ids[j]} with respect to the

@@ -52,7 +52,7 @@ __all__ = [
     "LAMBDA_COLOUR", "LAMBDA_OCC", "N_OUT", "layer_shapes", "n_params", "unpack",
     "splitmix64", "xavier_init", "normalise", "encode", "mlp_forward", "heads", "render",
     "render_vjp", "ray_losses", "object_forward", "object_loss_and_grad", "adam_update",
-    "ObjectState", "step", "query", "bf16_round",
+    "ObjectState", "step", "query", "bf16_round", "splitmix64_array", "depth_guided_samples",
 ]
 
 LAMBDA_COLOUR = 5.0   # lambda_1 of Eq. 7
@@ -104,6 +104,16 @@ def splitmix64(seed: int, index: np.ndarray) -> np.ndarray:
         z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
         out[j] = z ^ (z >> 31)
     return out
+
+
+def splitmix64_array(seed: int, index: np.ndarray) -> np.ndarray:
+    """``splitmix64`` for many indices at once, in numpy uint64 (arithmetic modulo 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(index, dtype=np.uint64) + np.uint64(1)) * \
+            np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
 
 
 def xavier_init(seed: int, H: int, L: int, E: int) -> np.ndarray:
@@ -257,9 +267,10 @@ def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth
                          upstream: float = 1.0, want_grad: bool = True, rnd=_identity):
     """L^k of Eq. 7 for one object and, optionally, upstream * dL^k/dtheta.
 
-    Returns (loss, grad or None, forward dict). With ``rnd`` = bf16_round the products of the
-    MLP (forward and backward) take BF16-rounded operands, except the seed dz of the output
-    layer, which stays FP64 (diagnostic mode).
+    Returns (loss, grad or None, forward dict). With ``rnd`` = bf16_round every product of the
+    MLP (forward and backward, the output layer's seed dz included) takes BF16-rounded operands;
+    bias gradients sum the rounded deltas, except the output layer's, which sums dz itself
+    (diagnostic mode).
     """
     depth = np.asarray(depth, np.float64)
     rgb = np.asarray(rgb, np.float64)
@@ -293,8 +304,10 @@ def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth
     last = len(layers) - 1
     for li in range(last, -1, -1):
         W, _ = layers[li]
-        d_op = delta if li == last else rnd(delta)
-        grads.append((d_op.T @ rnd(hs[li]), d_op.sum(0)))
+        d_op = rnd(delta)
+        # bias gradients sum the deltas as the products see them, except at the output layer,
+        # whose seed dz is summed unrounded
+        grads.append((d_op.T @ rnd(hs[li]), (delta if li == last else d_op).sum(0)))
         if li > 0:
             delta = (d_op @ rnd(W)) * (fw["pre"][li - 1] > 0.0)
     grads.reverse()
@@ -309,6 +322,33 @@ def adam_update(theta, m, v, g, step_count, lr=1e-3, beta1=0.9, beta2=0.999, eps
     m_hat = m / (1.0 - beta1 ** step_count)
     v_hat = v / (1.0 - beta2 ** step_count)
     return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+# --------------------------------------------------------------------------- sampling
+
+def depth_guided_samples(t_near, t_far, depth, S: int, n_strat: int, sigma: float, seed: int):
+    """Depth-guided samples of Sec. 3.3 (Eqs. 1 and 2), sorted per ray: [R, S] FP64.
+
+    t_s is the observed depth where it is valid (> 0) and the far bound otherwise. Sample i < N_c
+    is stratified: t_n + (i + u) / N_c * (t_s - t_n); the others are t_s + sigma * z with z
+    standard normal (Box-Muller: z = sqrt(-2 ln u1) cos(2 pi u2)). Uniform j of sample i of ray r
+    comes from output 2 (r S + i) + j of the SplitMix64 stream started at ``seed``:
+    u = top 24 bits * 2^-24, and u1 = (top 24 bits + 1) * 2^-24 so that ln u1 is finite.
+    """
+    t_near = np.asarray(t_near, np.float64)
+    t_far = np.asarray(t_far, np.float64)
+    depth = np.asarray(depth, np.float64)
+    R = t_near.shape[0]
+    t_s = np.where(depth > 0.0, depth, t_far)
+    idx = (np.arange(R)[:, None] * S + np.arange(S)[None, :]).astype(np.uint64) * np.uint64(2)
+    top0 = (splitmix64_array(seed, idx) >> np.uint64(40)).astype(np.float64)
+    top1 = (splitmix64_array(seed, idx + np.uint64(1)) >> np.uint64(40)).astype(np.float64)
+    i = np.arange(S)[None, :]
+    strat = t_near[:, None] + (i + top0 * 2.0 ** -24) / n_strat * (t_s - t_near)[:, None]
+    z = np.sqrt(-2.0 * np.log((top0 + 1.0) * 2.0 ** -24)) * np.cos(2.0 * np.pi * top1 * 2.0 ** -24)
+    near = t_s[:, None] + sigma * z
+    t = np.where(i < n_strat, strat, near)
+    return np.sort(t, axis=1)
 
 
 # --------------------------------------------------------------------------- the step

@@ -82,6 +82,8 @@ EXPORTED = {
     "vmap_train_step": (ctypes.c_int, [_P, _BATCH, _P, _P]),
     "vmap_render": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P]),
     "vmap_query_occupancy": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, _P, _P]),
+    "vmap_sample_rays": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P, ctypes.c_float, ctypes.c_uint64,
+                                        _P, _P]),
     "vmap_forward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P, _P]),
     "vmap_backward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P]),
     "vmap_adam_step": (ctypes.c_int, [_P, _BATCH, _P]),
@@ -174,10 +176,17 @@ class ObjectSet:
                  max_hidden: Optional[int] = None, rays_per_tile: int = 0, lr: float = 1e-3,
                  betas=(0.9, 0.999), eps: float = 1e-8, lambda_colour: float = 5.0,
                  lambda_occ: float = 10.0, loss_scale_init: float = 4096.0,
-                 scale_growth_interval: int = 2000, device=None):
+                 scale_growth_interval: int = 2000, device=None, autotune: bool = True):
         torch = _torch()
         self.lib = load_library()
         self.device = device or torch.device("cuda", torch.cuda.current_device())
+        # launch shape from the autotuner's cache when none is given
+        self.tuned = None
+        if rays_per_tile == 0 and autotune:
+            from .tune import lookup
+            self.tuned = lookup(hidden, max_samples_per_ray, precision)
+            if self.tuned:
+                rays_per_tile = int(self.tuned["rays_per_tile"])
         self.cfg = default_config(
             max_objects=max_objects, hidden=hidden, max_hidden=max_hidden or hidden,
             max_samples_per_ray=max_samples_per_ray, max_rays=max_rays,
@@ -203,6 +212,8 @@ class ObjectSet:
         self.ctx = ctx
         self.n_params: Dict[int, int] = {}
         self.p_stride = 0
+        if self.tuned:
+            self.set_launch(int(self.tuned["waves"]), int(self.tuned["grid"]))
 
     # -- helpers
     def _check(self, rc: int):
@@ -298,6 +309,20 @@ class ObjectSet:
                                                   occ.data_ptr() if n else None,
                                                   rgb.data_ptr() if n else None, _stream()))
         return occ, rgb
+
+    def sample_rays(self, t_near, t_far, depth, S: int, n_strat: int, sigma: float = 0.03,
+                    seed: int = 0):
+        """Depth-guided, sorted sample depths [R, S] on the device (Sec. 3.3, Eqs. 1-2)."""
+        torch = _torch()
+        f = lambda x: torch.as_tensor(x).to(device=self.device, dtype=torch.float32).contiguous()
+        tn, tf, d = f(t_near), f(t_far), f(depth)
+        R = tn.numel()
+        out = torch.empty(R, S, dtype=torch.float32, device=self.device)
+        ptr = lambda x: x.data_ptr() if R else None
+        self._check(self.lib.vmap_sample_rays(self.ctx, R, S, n_strat, ptr(tn), ptr(tf), ptr(d),
+                                              float(sigma), int(seed) & ((1 << 64) - 1),
+                                              ptr(out), _stream()))
+        return out
 
     # -- state I/O and diagnostics
     def get_state(self, k: int, which: int = STATE_PARAMS) -> np.ndarray:

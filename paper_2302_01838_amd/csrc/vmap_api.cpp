@@ -29,7 +29,7 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, tile_loss, partial, total;
+  size_t tile_start, flags, t_next, batch, tile_loss, partial, total;
   int max_tiles;
 };
 
@@ -91,6 +91,8 @@ WorkLayout work_layout(const vmap_config* c) {
   size_t off = 0;
   w.tile_start = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
   w.flags = off; off = align256(off + (size_t)c->max_objects * 4);
+  w.t_next = off; off = align256(off + (size_t)c->max_objects * 4);
+  w.batch = off; off = align256(off + sizeof(BatchDev));
   w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.partial = off; off = align256(off + (size_t)w.max_tiles * ps * 4);
   w.total = off;
@@ -135,6 +137,12 @@ struct vmap_ctx {
   };
   std::map<std::vector<int64_t>, GraphEntry> graphs;
   hipStream_t capture_stream = nullptr;
+  // pinned host ring of batch descriptors copied to the workspace before each graph replay
+  static constexpr int kRing = 64;
+  BatchDev* ring = nullptr;
+  hipEvent_t ring_ev[kRing] = {};
+  bool ring_used[kRing] = {};
+  int ring_next = 0;
 
   ObjDesc* desc() { return reinterpret_cast<ObjDesc*>(state + sl.desc); }
   ScalerState* scaler() { return reinterpret_cast<ScalerState*>(state + sl.scaler); }
@@ -145,6 +153,8 @@ struct vmap_ctx {
   float* grad() { return reinterpret_cast<float*>(state + sl.grad); }
   int32_t* tile_start() { return reinterpret_cast<int32_t*>(work + wl.tile_start); }
   int32_t* flags() { return reinterpret_cast<int32_t*>(work + wl.flags); }
+  int32_t* t_next() { return reinterpret_cast<int32_t*>(work + wl.t_next); }
+  BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
   float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
   float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
 
@@ -212,6 +222,7 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.tile_start = c->tile_start();
   a.partial = c->partial();
   a.tile_loss = c->tile_loss();
+  a.flags = c->flags();
   a.lambda_c = (float)c->cfg.lambda_colour;
   a.lambda_o = (float)c->cfg.lambda_occ;
   return a;
@@ -228,10 +239,50 @@ hipEvent_t pooled_event(vmap_ctx* c) {
   return e;
 }
 
+hipError_t enqueue_worklist(vmap_ctx* c, const vmap_batch* b, hipStream_t s,
+                            const BatchDev* bd = nullptr) {
+  return launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
+                         c->cfg.max_objects, c->desc(), c->tile_start(), c->flags(), c->t_next(),
+                         bd, s);
+}
+
+OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* grad_out,
+                      const BatchDev* bd = nullptr) {
+  OptArgs a{};
+  a.bd = bd;
+  a.n_objects = b->n_objects;
+  a.ids = b->object_ids;
+  a.offs = b->ray_offsets;
+  a.tile_start = c->tile_start();
+  a.partial = c->partial();
+  a.tile_loss = c->tile_loss();
+  a.t_next = c->t_next();
+  a.p_stride = c->p_stride;
+  a.max_objects = c->cfg.max_objects;
+  a.desc = c->desc();
+  a.scaler = c->scaler();
+  a.flags = c->flags();
+  a.theta = c->theta();
+  a.m = c->m();
+  a.v = c->v();
+  a.grad = c->grad();
+  a.grad_out = grad_out;
+  a.loss_out = loss_out;
+  a.lr = c->cfg.lr;
+  a.beta1 = c->cfg.beta1;
+  a.beta2 = c->cfg.beta2;
+  a.eps = c->cfg.eps;
+  a.bf16 = c->cfg.precision == VMAP_BF16;
+  a.growth = c->cfg.scale_growth_interval;
+  return a;
+}
+
 // Enqueue the tile kernel for every width group.
 int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss, float* d_out,
-                  float* rgb_out, float* occ_out, hipStream_t s, bool allow_timing) {
+                  float* rgb_out, float* occ_out, hipStream_t s, bool allow_timing,
+                  const BatchDev* bd = nullptr) {
   StepArgs a = make_step_args(c, b);
+  a.bd = bd;
   a.dloss = dloss;
   a.out_depth = d_out;
   a.out_rgb = rgb_out;
@@ -264,22 +315,14 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
   return VMAP_OK;
 }
 
-int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing) {
-  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
-                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing,
+                  const BatchDev* bd = nullptr) {
+  hipError_t e = enqueue_worklist(c, b, s, bd);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
-  int rc = enqueue_tiles(c, b, MODE_TRAIN, nullptr, nullptr, nullptr, nullptr, s, allow_timing);
+  int rc = enqueue_tiles(c, b, MODE_TRAIN, nullptr, nullptr, nullptr, nullptr, s, allow_timing, bd);
   if (rc) return rc;
-  const int bf = c->cfg.precision == VMAP_BF16;
-  e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
-                    c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), bf, c->grad(), nullptr,
-                    c->flags(), loss_out, 1, s);
-  if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
-  e = launch_adam(b->n_objects, b->object_ids, b->ray_offsets, c->cfg.max_objects, c->desc(),
-                  c->scaler(), c->flags(), c->theta(), c->m(), c->v(), c->grad(), c->p_stride,
-                  c->cfg.lr, c->cfg.beta1, c->cfg.beta2, c->cfg.eps, bf,
-                  c->cfg.scale_growth_interval, s);
-  if (e != hipSuccess) return c->hip_fail(e, "adam launch");
+  e = launch_optimizer(OPT_REDUCE_ADAM, make_opt_args(c, b, loss_out, nullptr, bd), s);
+  if (e != hipSuccess) return c->hip_fail(e, "gradient/Adam launch");
   return VMAP_OK;
 }
 
@@ -349,7 +392,7 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   c->p_stride = pad_params(n_params_of(cfg->max_hidden));
   c->rays_per_tile = default_rays_per_tile(cfg);
   c->objs.resize(cfg->max_objects);
-  hipGetDevice(&c->device);
+  (void)hipGetDevice(&c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = launch_fill_zero(state_dev, sl.total, s);
   if (e == hipSuccess) e = launch_fill_zero(workspace_dev, wl.total, s);
@@ -416,14 +459,39 @@ int vmap_train_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, void* str
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!c->graph_mode) return enqueue_train(c, b, loss_out, s, true);
-  // graph replay: one executable graph per batch shape and buffer set
-  std::vector<int64_t> key = {b->n_objects, b->n_rays_total, b->samples_per_ray,
-                              (int64_t)(intptr_t)b->object_ids, (int64_t)(intptr_t)b->ray_offsets,
-                              (int64_t)(intptr_t)b->rays_o, (int64_t)(intptr_t)b->rays_d,
-                              (int64_t)(intptr_t)b->t, (int64_t)(intptr_t)b->depth,
-                              (int64_t)(intptr_t)b->rgb, (int64_t)(intptr_t)b->mask,
-                              (int64_t)(intptr_t)loss_out, c->waves, c->grid_blocks,
-                              (int64_t)widths_present(c).size()};
+  // Graph replay. The graph is captured once per batch shape; the batch's buffers reach its
+  // kernels through a device descriptor refreshed by one copy from a pinned host ring per call.
+  if (!c->ring) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->ring), sizeof(BatchDev) * vmap_ctx::kRing, 0);
+    if (e != hipSuccess) return c->hip_fail(e, "hipHostMalloc");
+  }
+  const int slot = c->ring_next;
+  c->ring_next = (c->ring_next + 1) % vmap_ctx::kRing;
+  if (c->ring_used[slot]) {  // the copy that last read this slot must have run
+    hipError_t e = hipEventSynchronize(c->ring_ev[slot]);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+  } else {
+    hipError_t e = hipEventCreateWithFlags(&c->ring_ev[slot], hipEventDisableTiming);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventCreate");
+    c->ring_used[slot] = true;
+  }
+  BatchDev& hb = c->ring[slot];
+  hb.n_objects = b->n_objects;
+  hb.S = b->samples_per_ray;
+  hb.n_rays = b->n_rays_total;
+  hb.pad = 0;
+  hb.object_ids = b->object_ids;
+  hb.ray_offsets = b->ray_offsets;
+  hb.rays_o = b->rays_o;
+  hb.rays_d = b->rays_d;
+  hb.t = b->t;
+  hb.depth = b->depth;
+  hb.rgb = b->rgb;
+  hb.mask = b->mask;
+  hb.loss_out = loss_out;
+  std::vector<int64_t> key = {b->n_objects, b->n_rays_total, b->samples_per_ray, c->waves,
+                              c->grid_blocks, (int64_t)widths_present(c).size(),
+                              loss_out ? 1 : 0};
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     if (!c->capture_stream) {
@@ -432,23 +500,27 @@ int vmap_train_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, void* str
     }
     hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return c->hip_fail(e, "hipStreamBeginCapture");
-    rc = enqueue_train(c, b, loss_out, c->capture_stream, false);
+    rc = enqueue_train(c, b, loss_out, c->capture_stream, false, c->batch_dev());
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->capture_stream, &g);
     if (rc) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     if (e != hipSuccess) return c->hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       return c->hip_fail(e, "hipGraphInstantiate");
     }
     it = c->graphs.emplace(key, vmap_ctx::GraphEntry{g, x}).first;
   }
-  hipError_t e = hipGraphLaunch(it->second.exec, s);
+  hipError_t e = hipMemcpyAsync(c->batch_dev(), &hb, sizeof(BatchDev), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return c->hip_fail(e, "copying the batch descriptor");
+  e = hipEventRecord(c->ring_ev[slot], s);
+  if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+  e = hipGraphLaunch(it->second.exec, s);
   if (e != hipSuccess) return c->hip_fail(e, "hipGraphLaunch");
   return VMAP_OK;
 }
@@ -460,16 +532,13 @@ int vmap_forward(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* depth
   if (rc) return rc;
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
-                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+  hipError_t e = enqueue_worklist(c, b, s);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
   rc = enqueue_tiles(c, b, MODE_FWD, nullptr, depth_out, rgb_out, occ_out, s, true);
   if (rc) return rc;
   if (loss_out) {
-    e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
-                      c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), 0, c->grad(), nullptr,
-                      c->flags(), loss_out, 0, s);
-    if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
+    e = launch_optimizer(OPT_LOSS, make_opt_args(c, b, loss_out, nullptr), s);
+    if (e != hipSuccess) return c->hip_fail(e, "loss launch");
   }
   return VMAP_OK;
 }
@@ -496,16 +565,12 @@ int vmap_backward(vmap_ctx* c, const vmap_batch* b, const float* dloss, float* g
   if (!dloss && b->n_objects > 0) return c->fail(VMAP_EINVAL, "dloss must not be NULL");
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
-                                 c->cfg.max_objects, c->tile_start(), c->flags(), s);
+  hipError_t e = enqueue_worklist(c, b, s);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
   rc = enqueue_tiles(c, b, MODE_TRAIN, dloss, nullptr, nullptr, nullptr, s, true);
   if (rc) return rc;
-  const int bf = c->cfg.precision == VMAP_BF16;
-  e = launch_reduce(b->n_objects, b->object_ids, c->tile_start(), c->partial(), c->tile_loss(),
-                    c->p_stride, c->cfg.max_objects, c->desc(), c->scaler(), bf, c->grad(), grad_out,
-                    c->flags(), nullptr, 1, s);
-  if (e != hipSuccess) return c->hip_fail(e, "reduce launch");
+  e = launch_optimizer(OPT_REDUCE, make_opt_args(c, b, nullptr, grad_out), s);
+  if (e != hipSuccess) return c->hip_fail(e, "gradient launch");
   return VMAP_OK;
 }
 
@@ -515,11 +580,7 @@ int vmap_adam_step(vmap_ctx* c, const vmap_batch* b, void* stream) {
   if (rc) return rc;
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int bf = c->cfg.precision == VMAP_BF16;
-  hipError_t e = launch_adam(b->n_objects, b->object_ids, b->ray_offsets, c->cfg.max_objects, c->desc(),
-                             c->scaler(), c->flags(), c->theta(), c->m(), c->v(), c->grad(), c->p_stride,
-                             c->cfg.lr, c->cfg.beta1, c->cfg.beta2, c->cfg.eps, bf,
-                             c->cfg.scale_growth_interval, s);
+  hipError_t e = launch_optimizer(OPT_ADAM, make_opt_args(c, b, nullptr, nullptr), s);
   if (e != hipSuccess) return c->hip_fail(e, "adam launch");
   return VMAP_OK;
 }
@@ -547,6 +608,23 @@ int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, fl
   q.lds = lds_layout(c->objs[k].hidden, bf, 4);
   hipError_t e = launch_query(c->objs[k].hidden, bf, q, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return c->hip_fail(e, "query launch");
+  return VMAP_OK;
+}
+
+int vmap_sample_rays(vmap_ctx* c, int32_t n_rays, int32_t S, int32_t n_strat, const float* t_near,
+                     const float* t_far, const float* depth, float sigma, uint64_t seed,
+                     float* t_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (n_rays < 0) return c->fail(VMAP_EINVAL, "n_rays must be >= 0");
+  if (S < 1 || S > kSlots) return c->fail(VMAP_EINVAL, "S must be in [1, 64]");
+  if (n_strat < 0 || n_strat > S) return c->fail(VMAP_EINVAL, "n_strat must be in [0, S]");
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return c->fail(VMAP_EINVAL, "sigma must be finite and >= 0");
+  if (n_rays == 0) return VMAP_OK;
+  if (!t_near || !t_far || !depth || !t_out)
+    return c->fail(VMAP_EINVAL, "t_near, t_far, depth and t_out must not be NULL");
+  hipError_t e = launch_sample(n_rays, S, n_strat, t_near, t_far, depth, sigma, seed, t_out,
+                               reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return c->hip_fail(e, "sampling launch");
   return VMAP_OK;
 }
 
@@ -667,15 +745,18 @@ const char* vmap_last_error(const vmap_ctx* c) {
 void vmap_destroy(vmap_ctx* c) {
   if (!c) return;
   for (auto& kv : c->graphs) {
-    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-    if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
   }
   for (auto& t : c->timed) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  for (auto e : c->event_pool) hipEventDestroy(e);
-  if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  for (int i = 0; i < vmap_ctx::kRing; ++i)
+    if (c->ring_used[i]) (void)hipEventDestroy(c->ring_ev[i]);
+  if (c->ring) (void)hipHostFree(c->ring);
   delete c;
 }
 

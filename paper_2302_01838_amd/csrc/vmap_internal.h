@@ -37,15 +37,18 @@ struct ScalerState {
 
 // Byte offsets of the LDS regions of the tile kernel (computed identically on host and device).
 struct LdsLayout {
-  int w_off[kLayers];  // W_l, rows = H, padded row stride, permuted columns
+  int w_off[kLayers];   // W_l, rows = H, padded row stride, permuted columns
   int w_stride[kLayers];
-  int b_off;           // kLayers x H biases (FP32)
-  int wh_off;          // head weights [4][H + 4] FP32, permuted columns
-  int bh_off;          // head biases [4]
-  int B_off;           // encoding matrix [3][16] FP32
-  int scratch_off;     // per-wave staging, then the tile's gradient sum
-  int scratch_wave;    // bytes per wave
-  int loss_off;        // one float
+  int wt_off[kLayers];  // BF16 only: W_l^T for l >= 1 (rows = inputs), stride H + 8
+  int b_off;            // kLayers x H biases (FP32)
+  int wh_off;           // head weights [4][H + 4] FP32, permuted columns (FP32 mode)
+  int whb_off;          // BF16: head weights [4][H + 8] BF16, permuted columns
+  int whtb_off;         // BF16: head weights transposed [H][4] BF16
+  int bh_off;           // head biases [4]
+  int B_off;            // encoding matrix [3][16] FP32
+  int scratch_off;      // per-wave staging, then the tile's gradient sum
+  int scratch_wave;     // bytes per wave
+  int loss_off;         // one float
   int total;
 };
 
@@ -53,6 +56,13 @@ __host__ __device__ constexpr int round_up(int x, int a) { return (x + a - 1) / 
 
 __host__ __device__ constexpr int n_params_of(int H) {
   return (H * kEnc + H) + (kLayers - 1) * (H * H + H) + (kOut * H + kOut);
+}
+
+// Per-wave staging: the output-layer seeds dz (FP32 [32][4], or BF16 [4][40]) and two transposed
+// tiles (delta and activations): FP32 [32 samples][H + 4], BF16 [H features][40].
+__host__ __device__ constexpr int dz_tile_bytes(bool bf16) { return bf16 ? 4 * 40 * 2 : 32 * kOut * 4; }
+__host__ __device__ constexpr int tr_tile_bytes(int H, bool bf16) {
+  return bf16 ? H * 40 * 2 : 32 * (H + 4) * 4;
 }
 
 // Every offset except `total` is independent of the wave count, so kernels evaluate the layout at
@@ -68,19 +78,25 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
     L.w_off[l] = off;
     off = round_up(off + H * (K + pad) * es, 16);
   }
+  for (int l = 0; l < kLayers; ++l) {
+    L.wt_off[l] = off;
+    if (bf16 && l > 0) off = round_up(off + H * (H + 8) * 2, 16);
+  }
   L.b_off = off;
   off = round_up(off + kLayers * H * 4, 16);
   L.wh_off = off;
-  off = round_up(off + kOut * (H + 4) * 4, 16);
+  if (!bf16) off = round_up(off + kOut * (H + 4) * 4, 16);
+  L.whb_off = off;
+  if (bf16) off = round_up(off + kOut * (H + 8) * 2, 16);
+  L.whtb_off = off;
+  if (bf16) off = round_up(off + H * kOut * 2, 16);
   L.bh_off = off;
   off = round_up(off + kOut * 4, 16);
   L.B_off = off;
   off = round_up(off + 3 * kFeatures * 4, 16);
   L.loss_off = off;
   off = round_up(off + 16, 16);
-  // staging per wave: delta and activation tiles plus dz [32][4]
-  const int tile_bytes = bf16 ? (H * 40 * 2) : (32 * (H + 4) * 4);
-  L.scratch_wave = round_up(2 * tile_bytes + 32 * kOut * 4, 16);
+  L.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16), 16);
   L.scratch_off = off;
   int scratch = nwaves * L.scratch_wave;
   const int red = n_params_of(H) * 4;
@@ -89,6 +105,24 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   L.total = off;
   return L;
 }
+
+// A batch's shape and buffers in device memory. Graph replays of the training step read the batch
+// from here (refreshed by one small copy per call) instead of from their captured arguments.
+struct BatchDev {
+  int32_t n_objects;
+  int32_t S;
+  int32_t n_rays;
+  int32_t pad;
+  const int32_t* object_ids;
+  const int32_t* ray_offsets;
+  const float* rays_o;
+  const float* rays_d;
+  const float* t;
+  const float* depth;
+  const float* rgb;
+  const float* mask;
+  float* loss_out;
+};
 
 struct StepArgs {
   // batch
@@ -116,12 +150,14 @@ struct StepArgs {
   float* partial;             // [tiles][p_stride]
   float* tile_loss;           // [tiles]
   const float* dloss;         // [n_objects] upstream weights (backward) or NULL
+  int32_t* flags;             // [max_objects] non-finite partial flags
   float* out_depth;
   float* out_rgb;
   float* out_occ;
   float lambda_c;
   float lambda_o;
   int use_scale;              // multiply seeds by the loss scale (BF16 training)
+  const BatchDev* bd;         // if not NULL, the batch fields above are read from here
   LdsLayout lds;
 };
 
@@ -138,30 +174,51 @@ struct QueryArgs {
   LdsLayout lds;
 };
 
+// Arguments of the gradient / optimiser kernels.
+struct OptArgs {
+  int n_objects;
+  const int32_t* ids;
+  const int32_t* offs;        // ray offsets of the batch
+  const int32_t* tile_start;
+  const float* partial;
+  const float* tile_loss;
+  const int32_t* t_next;      // per batch object, from k_worklist
+  int p_stride;
+  int max_objects;
+  ObjDesc* desc;
+  ScalerState* scaler;
+  int32_t* flags;
+  float* theta;
+  float* m;
+  float* v;
+  float* grad;
+  float* grad_out;
+  float* loss_out;
+  double lr, beta1, beta2, eps;
+  int bf16;
+  int growth;
+  const BatchDev* bd;         // if not NULL, n_objects, ids, offs and loss_out come from here
+};
+
 // Kernel launchers (vmap_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int max_objects, int32_t* tile_start,
-                           int32_t* flags, hipStream_t s);
+                           int rays_per_tile, int max_objects, const ObjDesc* desc,
+                           int32_t* tile_start, int32_t* flags, int32_t* t_next,
+                           const BatchDev* bd, hipStream_t s);
 hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,
                         hipStream_t s);
-hipError_t launch_reduce(int n_objects, const int32_t* object_ids, const int32_t* tile_start,
-                         const float* partial, const float* tile_loss, int p_stride,
-                         int max_objects, const ObjDesc* desc, const ScalerState* scaler,
-                         int unscale, float* grad, float* grad_out, int32_t* flags,
-                         float* loss_out, int want_grad, hipStream_t s);
-hipError_t launch_adam(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                       int max_objects, ObjDesc* desc, ScalerState* scaler,
-                       const int32_t* flags, float* theta, float* m, float* v,
-                       const float* grad, int p_stride, double lr, double beta1,
-                       double beta2, double eps, int bf16, int growth_interval,
-                       hipStream_t s);
+enum OptKind { OPT_LOSS = 0, OPT_REDUCE = 1, OPT_ADAM = 2, OPT_REDUCE_ADAM = 3 };
+hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s);
 hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,
                               const ObjDesc& d, ObjDesc* desc, float* theta, float* m,
                               float* v, float* grad, int p_stride, int use_rng,
                               hipStream_t s);
 hipError_t launch_query(int H, bool bf16, const QueryArgs& q, hipStream_t s);
 hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s);
+hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, const float* t_far,
+                         const float* depth, float sigma, uint64_t seed, float* t_out,
+                         hipStream_t s);
 int tiles_supported(int H, bool bf16);
 
 }  // namespace vmapi

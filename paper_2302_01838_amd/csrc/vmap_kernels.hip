@@ -47,6 +47,7 @@ namespace vmapi {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Accumulator row held in register r (0..15) by lanes of half h (0, 1) of a 32x32 MFMA tile.
 // The same map orders the K axis: K slot (h, r) of a block carries feature rowof(r, h).
@@ -90,7 +91,8 @@ struct Acts<H, true> {
 };
 
 // ---------------------------------------------------------------------------------------------
-// Weight staging: object k's parameters -> LDS (permuted columns; BF16 in BF16 mode).
+// Weight staging: object k's parameters -> LDS (permuted columns; BF16 in BF16 mode, plus the
+// transposed copies that the backward's input-gradient products read as A operands).
 
 template <int H, bool BF>
 __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem) {
@@ -106,16 +108,28 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem)
     const int ws = L.w_stride[l];
     for (int e = tid; e < H * K; e += nt) {
       const int row = e / K, col = e - row * K;
-      W[row * ws + (col & ~31) + colpos(col & 31)] = (WT)th[off + e];
+      const WT w = (WT)th[off + e];
+      W[row * ws + (col & ~31) + colpos(col & 31)] = w;
+      if constexpr (BF) {
+        if (l > 0) {  // W^T[col][row], rows of the transpose permuted like the forward's K axis
+          __bf16* Wt = reinterpret_cast<__bf16*>(smem + L.wt_off[l]);
+          Wt[col * (H + 8) + (row & ~31) + colpos(row & 31)] = w;
+        }
+      }
     }
     off += H * K;
     for (int e = tid; e < H; e += nt) bias[l * H + e] = th[off + e];
     off += H;
   }
-  float* Wh = reinterpret_cast<float*>(smem + L.wh_off);
   for (int e = tid; e < kOut * H; e += nt) {
     const int c = e / H, col = e - c * H;
-    Wh[c * (H + 4) + (col & ~31) + colpos(col & 31)] = round_w<BF>(th[off + e]);
+    if constexpr (BF) {
+      const __bf16 w = (__bf16)th[off + e];
+      reinterpret_cast<__bf16*>(smem + L.whb_off)[c * (H + 8) + (col & ~31) + colpos(col & 31)] = w;
+      reinterpret_cast<__bf16*>(smem + L.whtb_off)[col * kOut + c] = w;
+    } else {
+      reinterpret_cast<float*>(smem + L.wh_off)[c * (H + 4) + (col & ~31) + colpos(col & 31)] = th[off + e];
+    }
   }
   off += kOut * H;
   float* bh = reinterpret_cast<float*>(smem + L.bh_off);
@@ -124,10 +138,11 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem)
 
 // ---------------------------------------------------------------------------------------------
 // Forward of one 32-sample pass for the calling wave. xt: this lane's normalised point (the
-// sample of column n = lane & 31; both lane halves hold the same point). Fills acts and
-// returns the four head outputs z (identical in both halves).
+// sample of column n = lane & 31; both lane halves hold the same point). Fills the activations
+// and, with WITH_HEAD, returns the four output pre-activations z of sample n (valid in both lane
+// halves).
 
-template <int H, bool BF>
+template <int H, bool BF, bool WITH_HEAD>
 __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
                                              Acts<H, BF>& A, float z[4]) {
   constexpr int MT = H / 32;
@@ -159,7 +174,7 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
     for (int mo = 0; mo < MT; ++mo) {
       f32x16 acc;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = bias[l * H + mo * 32 + rowof(r, hf)];
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         if constexpr (BF) {
@@ -179,30 +194,77 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
         }
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) A.set(l + 1, mo, r, fmaxf(acc[r], 0.0f));
+      for (int r = 0; r < 16; ++r)
+        A.set(l + 1, mo, r, fmaxf(acc[r] + bias[l * H + mo * 32 + rowof(r, hf)], 0.0f));
     }
   }
-  // output layer (4 x H) on the VALU: each half sums its 16 features per block, then the halves
-  // are added (the same two addends in both halves, so both hold the same value)
-  const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+  if constexpr (!WITH_HEAD) return;
   const float* bh = reinterpret_cast<const float*>(smem + L.bh_off);
+  if constexpr (BF) {
+    // output layer on MFMA: A = W_out with its four rows padded to 32 (zero rows held in
+    // registers, not in LDS); sample n's outputs land in rows 0..3 of lane n (half 0)
+    f32x16 acc;
 #pragma unroll
-  for (int c = 0; c < kOut; ++c) {
-    float s = 0.f;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const __bf16* wh = reinterpret_cast<const __bf16*>(smem + L.whb_off);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * A.get(kLayers, mt, r);
-    s += __shfl_xor(s, 32);
-    z[c] = s + bh[c];
+      for (int jj = 0; jj < 2; ++jj) {
+        bf16x8 wa = {};
+        if (n < kOut) wa = *reinterpret_cast<const bf16x8*>(wh + n * (H + 8) + mt * 32 + 16 * hf + 8 * jj);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, A.v[kLayers][mt][jj], acc, 0, 0, 0);
+      }
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) z[c] = __shfl(acc[c], n) + bh[c];
+  } else {
+    // output layer on the VALU: each half sums its 16 features per block, then the halves are
+    // added (the same two addends in both halves, so both hold the same value)
+    const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) {
+      float s = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * A.get(kLayers, mt, r);
+      s += __shfl_xor(s, 32);
+      z[c] = s + bh[c];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // The step's tile kernel.
 
+__device__ __forceinline__ void read_batch(StepArgs& a) {
+  if (const BatchDev* b = a.bd) {
+    a.n_objects = b->n_objects;
+    a.S = b->S;
+    a.object_ids = b->object_ids;
+    a.ray_offsets = b->ray_offsets;
+    a.rays_o = b->rays_o;
+    a.rays_d = b->rays_d;
+    a.t = b->t;
+    a.depth = b->depth;
+    a.rgb = b->rgb;
+    a.mask = b->mask;
+  }
+}
+
+__device__ __forceinline__ void read_batch(OptArgs& a) {
+  if (const BatchDev* b = a.bd) {
+    a.n_objects = b->n_objects;
+    a.ids = b->object_ids;
+    a.offs = b->ray_offsets;
+    a.loss_out = b->loss_out;
+  }
+}
+
 template <int H, bool BF, int MODE>
-__global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
+__global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(const StepArgs a_in) {
+  StepArgs a = a_in;
+  read_batch(a);
   constexpr int MT = H / 32;
   constexpr bool TRAIN = (MODE == MODE_TRAIN);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -248,6 +310,7 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
     }
 
     f32x16 accW[kLayers][MT][MT];
+    f32x4 accWh[H / 16];  // BF16: output-layer weight gradient, 16x16 blocks (rows 0..3 used)
     float accH[kOut][MT];
     float accDb[kLayers][MT];
     float accDbH[kOut];
@@ -268,6 +331,10 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) accH[c][mt] = 0.f;
       }
+#pragma unroll
+      for (int b = 0; b < H / 16; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) accWh[b][i] = 0.f;
     }
     float wave_loss = 0.f;
 
@@ -303,7 +370,7 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
         Acts<H, BF> tmp;
         float xt[3], z[kOut];
         point(p, xt);
-        forward_pass<H, BF>(xt, smem, tmp, z);
+        forward_pass<H, BF, true>(xt, smem, tmp, z);
 #pragma unroll
         for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
       }
@@ -394,17 +461,16 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
       for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
 
       // ---------------- MLP backward, one pass of 32 samples at a time
-      float* dzl = reinterpret_cast<float*>(scr);
-      unsigned char* dtile = scr + 32 * kOut * 4;
-      unsigned char* htile = dtile + (BF ? H * 40 * 2 : 32 * (H + 4) * 4);
-      const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+      unsigned char* dzt = scr;
+      unsigned char* dtile = scr + dz_tile_bytes(BF);
+      unsigned char* htile = dtile + tr_tile_bytes(H, BF);
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
         Acts<H, BF> act;
         {  // recompute the activations of this pass
           float xt[3], z[kOut];
           point(p, xt);
-          forward_pass<H, BF>(xt, smem, act, z);
+          forward_pass<H, BF, false>(xt, smem, act, z);
         }
         float dz[kOut];
 #pragma unroll
@@ -413,7 +479,10 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
         wave_lds_sync();
         if (hf == 0) {
 #pragma unroll
-          for (int c = 0; c < kOut; ++c) dzl[n * kOut + c] = dz[c];
+          for (int c = 0; c < kOut; ++c) {
+            if constexpr (BF) reinterpret_cast<__bf16*>(dzt)[c * 40 + n] = (__bf16)dz[c];
+            else reinterpret_cast<float*>(dzt)[n * kOut + c] = dz[c];
+          }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -426,30 +495,69 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
               reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[kLayers][mt][r];
           }
         wave_lds_sync();
-        // output-layer weight gradient: lane owns feature mt*32 + n, half hf takes 16 samples
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-          for (int s2 = 0; s2 < 16; ++s2) {
-            const int s = 16 * hf + s2;
-            float hv;
-            if constexpr (BF) hv = (float)reinterpret_cast<const __bf16*>(htile)[(mt * 32 + n) * 40 + s];
-            else hv = reinterpret_cast<const float*>(htile)[s * (H + 4) + mt * 32 + n];
-#pragma unroll
-            for (int c = 0; c < kOut; ++c) accH[c][mt] += dzl[s * kOut + c] * hv;
-          }
-        }
-        // delta of the last hidden layer: (W_out^T dz) masked by ReLU'
         float dl[MT][16];
+        if constexpr (BF) {
+          // output-layer weight gradient on MFMA 16x16x32: rows = the four outputs (padded to 16),
+          // columns = 16 features, K = the pass's 32 samples
+          const int m16 = lane & 15, kg = lane >> 4;
+          bf16x8 da = {};
+          if (m16 < kOut) da = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(dzt) + m16 * 40 + 8 * kg);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            float s = 0.f;
-#pragma unroll
-            for (int c = 0; c < kOut; ++c) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * dz[c];
-            dl[mt][r] = (act.get(kLayers, mt, r) > 0.f) ? s : 0.f;
+          for (int b = 0; b < H / 16; ++b) {
+            const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
+                reinterpret_cast<const __bf16*>(htile) + (b * 16 + m16) * 40 + 8 * kg);
+            accWh[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da, hb, accWh[b], 0, 0, 0);
           }
+          // delta of the last hidden layer: W_out^T dz on MFMA (K = 4 outputs padded to 16)
+          bf16x8 dzb = {};
+          if (hf == 0) {
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) dzb[c] = (__bf16)dz[c];
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            bf16x8 wa = {};
+            if (hf == 0) {
+              const __bf16* wt = reinterpret_cast<const __bf16*>(smem + L.whtb_off) + (mt * 32 + n) * kOut;
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) wa[c] = wt[c];
+            }
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dzb, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float hv = (float)reinterpret_cast<const __bf16*>(htile)[(mt * 32 + rowof(r, hf)) * 40 + n];
+              dl[mt][r] = (hv > 0.f) ? acc[r] : 0.f;
+            }
+          }
+        } else {
+          // output-layer weight gradient: lane owns feature mt*32 + n, half hf takes 16 samples
+          const float* dzl = reinterpret_cast<const float*>(dzt);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) {
+              const int s = 16 * hf + s2;
+              const float hv = reinterpret_cast<const float*>(htile)[s * (H + 4) + mt * 32 + n];
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) accH[c][mt] += dzl[s * kOut + c] * hv;
+            }
+          }
+          // delta of the last hidden layer: (W_out^T dz) masked by ReLU'
+          const float* Wh = reinterpret_cast<const float*>(smem + L.wh_off);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              float s = 0.f;
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * dz[c];
+              const float hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mt * 32 + rowof(r, hf)];
+              dl[mt][r] = (hv > 0.f) ? s : 0.f;
+            }
+        }
 #pragma unroll
         for (int l = kLayers - 1; l >= 0; --l) {
           const int KB = (l == 0) ? 1 : MT;
@@ -519,15 +627,15 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
 #pragma unroll
             for (int ko = 0; ko < MT; ++ko) {
               if constexpr (BF) {
-                const __bf16* W = reinterpret_cast<const __bf16*>(smem + L.w_off[l]);
+                // A = W_l^T from its transposed copy: 8 consecutive BF16 per lane
+                const __bf16* Wt = reinterpret_cast<const __bf16*>(smem + L.wt_off[l]) +
+                                   (mi * 32 + n) * (H + 8) + ko * 32 + 16 * hf;
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
-                  bf16x8 wa, db;
+                  const bf16x8 wa = *reinterpret_cast<const bf16x8*>(Wt + 8 * jj);
+                  bf16x8 db;
 #pragma unroll
-                  for (int e = 0; e < 8; ++e) {
-                    wa[e] = W[(ko * 32 + rowof(8 * jj + e, hf)) * ws + col];
-                    db[e] = (__bf16)dl[ko][8 * jj + e];
-                  }
+                  for (int e = 0; e < 8; ++e) db[e] = (__bf16)dl[ko][8 * jj + e];
                   acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, db, acc, 0, 0, 0);
                 }
               } else {
@@ -539,7 +647,12 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
               }
             }
 #pragma unroll
-            for (int r = 0; r < 16; ++r) nd[mi][r] = (act.get(l, mi, r) > 0.f) ? acc[r] : 0.f;
+            for (int r = 0; r < 16; ++r) {
+              float hv;
+              if constexpr (BF) hv = (float)reinterpret_cast<const __bf16*>(htile)[(mi * 32 + rowof(r, hf)) * 40 + n];
+              else hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mi * 32 + rowof(r, hf)];
+              nd[mi][r] = (hv > 0.f) ? acc[r] : 0.f;
+            }
           }
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
@@ -598,7 +711,17 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
             }
             off += H;
           }
-          if (hf == 0) {
+          if constexpr (BF) {
+            if (lane < 16) {
+#pragma unroll
+              for (int c = 0; c < kOut; ++c)
+#pragma unroll
+                for (int b = 0; b < H / 16; ++b) {
+                  const int idx = off + c * H + b * 16 + lane;
+                  red[idx] = (first ? 0.f : red[idx]) + accWh[b][c];
+                }
+            }
+          } else if (hf == 0) {
 #pragma unroll
             for (int c = 0; c < kOut; ++c)
 #pragma unroll
@@ -617,9 +740,22 @@ __global__ void __launch_bounds__(256) k_step_tiles(const StepArgs a) {
       __syncthreads();
     }
     if constexpr (TRAIN) {
+      // unscale (exact: the scale is a power of two) and flag a non-finite partial
       const int P = n_params_of(H);
+      const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
       float* dst = a.partial + (size_t)tile * a.p_stride;
-      for (int e = tid; e < P; e += blockDim.x) dst[e] = red[e];
+      int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 4);
+      if (tid == 0) *any_bad = 0;
+      __syncthreads();
+      int bad = 0;
+      for (int e = tid; e < P; e += blockDim.x) {
+        const float g = red[e] * inv;
+        bad |= !isfinite(g);
+        dst[e] = g;
+      }
+      if (bad) *any_bad = 1;  // every writer stores the same value
+      __syncthreads();
+      if (tid == 0 && *any_bad) atomicOr(&a.flags[k], 1);
     }
     if (tid == 0) a.tile_loss[tile] = lsum[0];
     __syncthreads();
@@ -650,7 +786,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
       }
       Acts<H, BF> act;
       float z[kOut];
-      forward_pass<H, BF>(xt, smem, act, z);
+      forward_pass<H, BF, true>(xt, smem, act, z);
       if (i < qa.n && hf == 0) {
         qa.occ[i] = sigm(z[3]);
         if (qa.rgb) {
@@ -664,13 +800,22 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
 
 // ---------------------------------------------------------------------------------------------
 // Tile offsets per batch object (exclusive scan of ceil(rays / rays_per_tile)); clears the
-// non-finite flags of the batch's objects.
+// non-finite flags of the batch's objects and records each object's next Adam step count, so
+// that the optimiser kernels read it from here while one of their blocks advances the count.
 
-__global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t* __restrict__ ids,
-                                                   const int32_t* __restrict__ offs, int rpt,
-                                                   int max_objects, int32_t* __restrict__ tile_start,
-                                                   int32_t* __restrict__ flags) {
+__global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t* ids,
+                                                   const int32_t* offs, int rpt,
+                                                   int max_objects, const ObjDesc* __restrict__ desc,
+                                                   int32_t* __restrict__ tile_start,
+                                                   int32_t* __restrict__ flags,
+                                                   int32_t* __restrict__ t_next,
+                                                   const BatchDev* __restrict__ bd) {
   __shared__ int part[1024];
+  if (bd) {
+    n_objects = bd->n_objects;
+    ids = bd->object_ids;
+    offs = bd->ray_offsets;
+  }
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (n_objects + nt - 1) / nt;
   const int j0 = min(tid * per, n_objects), j1 = min(j0 + per, n_objects);
@@ -679,7 +824,10 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
     const int nr = offs[j + 1] - offs[j];
     local += (nr > 0) ? (nr + rpt - 1) / rpt : 0;
     const int k = ids[j];
-    if (k >= 0 && k < max_objects) flags[k] = 0;
+    const bool valid = k >= 0 && k < max_objects;
+    if (valid) flags[k] = 0;
+    // step count after this batch's update, read by the optimiser kernels
+    t_next[j] = (valid && desc[k].registered) ? desc[k].step + 1 : 0;
   }
   part[tid] = local;
   __syncthreads();
@@ -699,127 +847,172 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
 }
 
 // ---------------------------------------------------------------------------------------------
-// Per-object gradient: sum of the object's tile partials in tile order, unscaled.
+// Per-object gradient and optimiser. Tile partials are already unscaled by the tile kernel, which
+// also flagged objects with a non-finite partial. Three kernels share the pieces below:
+//   k_reduce      — loss and gradient per object (forward/backward split),
+//   k_adam        — Adam from the stored gradient (after k_reduce),
+//   k_reduce_adam — both in one pass (the training step).
+// The optimiser kernels take each object's next step count from the work-list kernel; block
+// (0, j) writes it back, block (0, 0) updates the loss scaler from the flags. No block reads what
+// another block of the same launch writes, so no device-scope fence is needed.
 
-__global__ void __launch_bounds__(256) k_reduce(int n_objects, const int32_t* __restrict__ ids,
-                                                const int32_t* __restrict__ tile_start,
-                                                const float* __restrict__ partial,
-                                                const float* __restrict__ tile_loss, int p_stride,
-                                                int max_objects, const ObjDesc* __restrict__ desc,
-                                                const ScalerState* __restrict__ scaler, int unscale,
-                                                float* __restrict__ grad, float* __restrict__ grad_out,
-                                                int32_t* __restrict__ flags, float* __restrict__ loss_out,
-                                                int want_grad) {
-  const int j = blockIdx.y;
-  const int k = ids[j];
-  const bool valid = k >= 0 && k < max_objects && desc[k].registered;
-  const int t0 = tile_start[j], t1 = tile_start[j + 1];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
-    float s = 0.f;
-    if (valid)
-      for (int t = t0; t < t1; ++t) s += tile_loss[t];
-    loss_out[j] = s;
-  }
-  if (!want_grad || !valid) return;
-  const int P = desc[k].n_params;
-  const float inv = unscale ? 1.0f / scaler->scale : 1.0f;
-  bool bad = false;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < p_stride; p += gridDim.x * blockDim.x) {
-    float g = 0.f;
-    if (p < P) {
-      // loads are issued eight at a time, then added in tile order
-      int t = t0;
-      for (; t + 8 <= t1; t += 8) {
-        float x[8];
+// Sum of an object's tile partials at parameter p, in tile order; loads are issued eight at a
+// time and added in order.
+__device__ __forceinline__ float tile_sum(const float* __restrict__ partial, int p_stride, int t0,
+                                          int t1, int p) {
+  float g = 0.f;
+  int t = t0;
+  for (; t + 8 <= t1; t += 8) {
+    float x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
+    for (int u = 0; u < 8; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) g += x[u];
-      }
-      for (; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
-      g *= inv;
-      bad |= !isfinite(g);
-    }
-    grad[(size_t)k * p_stride + p] = g;
-    if (grad_out) grad_out[(size_t)j * p_stride + p] = g;
+    for (int u = 0; u < 8; ++u) g += x[u];
   }
-  if (bad) atomicOr(&flags[k], 1);
+  for (; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
+  return g;
 }
 
-// ---------------------------------------------------------------------------------------------
-// Adam, one block per batch object: the block updates all of the object's parameters and then
-// advances its step count, so no other block reads or writes that count. Block 0 also updates
-// the loss scaler from the non-finite flags, which the reduction kernel finished writing. No
-// device-scope fence is needed: every cross-block dependency crosses a kernel boundary.
 
-__global__ void __launch_bounds__(256) k_adam(int n_objects, const int32_t* __restrict__ ids,
-                                              const int32_t* __restrict__ offs, int max_objects,
-                                              ObjDesc* __restrict__ desc, ScalerState* __restrict__ sc,
-                                              const int32_t* __restrict__ flags, float* __restrict__ theta,
-                                              float* __restrict__ mom, float* __restrict__ vel,
-                                              const float* __restrict__ grad, int p_stride, double lr,
-                                              double beta1, double beta2, double eps, int bf16,
-                                              int growth) {
-  __shared__ float coef[2];
+__device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
+  return k >= 0 && k < a.max_objects && a.desc[k].registered;
+}
+
+// Block (0, 0): count the batch objects with rays whose gradient was not finite; BF16 scaler.
+__device__ void scaler_update(const OptArgs& a) {
   __shared__ int red[256];
-  const int j = blockIdx.x;
-  const int k = ids[j];
-  const bool valid = k >= 0 && k < max_objects && desc[k].registered;
-  const bool active = valid && (offs[j + 1] > offs[j]) && flags[k] == 0;
-  if (j == 0) {
-    // loss scaler: count the batch objects with rays whose gradient was not finite
-    int skipped = 0;
-    for (int jj = threadIdx.x; jj < n_objects; jj += blockDim.x) {
-      const int kk = ids[jj];
-      if (kk >= 0 && kk < max_objects && desc[kk].registered && offs[jj + 1] > offs[jj] && flags[kk])
-        ++skipped;
-    }
-    red[threadIdx.x] = skipped;
+  int skipped = 0;
+  for (int jj = threadIdx.x; jj < a.n_objects; jj += blockDim.x) {
+    const int kk = a.ids[jj];
+    if (obj_valid(a, kk) && a.offs[jj + 1] > a.offs[jj] && a.flags[kk]) ++skipped;
+  }
+  red[threadIdx.x] = skipped;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const int total = red[0];
-      sc->skipped = total;
-      if (bf16) {
-        if (total > 0) {
-          sc->scale *= 0.5f;
-          sc->good_steps = 0;
-        } else if (++sc->good_steps >= growth) {
-          sc->scale *= 2.0f;
-          sc->good_steps = 0;
-        }
+  }
+  if (threadIdx.x == 0) {
+    const int total = red[0];
+    a.scaler->skipped = total;
+    if (a.bf16) {
+      if (total > 0) {
+        a.scaler->scale *= 0.5f;
+        a.scaler->good_steps = 0;
+      } else if (++a.scaler->good_steps >= a.growth) {
+        a.scaler->scale *= 2.0f;
+        a.scaler->good_steps = 0;
       }
     }
   }
-  if (!active) return;
-  const int t = desc[k].step + 1;
+}
+
+struct AdamCoef {
+  float step, rs, b1, c1, b2, c2, eps;
+};
+
+// Bias-corrected step size and 1/sqrt(bias correction of v) in FP64, then rounded once.
+__device__ AdamCoef adam_coef(const OptArgs& a, int t) {
+  __shared__ float sh[2];
   if (threadIdx.x == 0) {
-    const double bc1 = 1.0 - pow(beta1, (double)t), bc2 = 1.0 - pow(beta2, (double)t);
-    coef[0] = (float)(lr / bc1);
-    coef[1] = (float)(1.0 / sqrt(bc2));
+    const double bc1 = 1.0 - pow(a.beta1, (double)t), bc2 = 1.0 - pow(a.beta2, (double)t);
+    sh[0] = (float)(a.lr / bc1);
+    sh[1] = (float)(1.0 / sqrt(bc2));
   }
   __syncthreads();
-  const float step = coef[0], rs = coef[1];
-  const float b1 = (float)beta1, c1 = (float)(1.0 - beta1), b2 = (float)beta2, c2 = (float)(1.0 - beta2);
-  const float ep = (float)eps;
-  const int P = desc[k].n_params;
-  float* th = theta + (size_t)k * p_stride;
-  float* mm = mom + (size_t)k * p_stride;
-  float* vv = vel + (size_t)k * p_stride;
-  const float* gg = grad + (size_t)k * p_stride;
-  for (int p = threadIdx.x; p < P; p += blockDim.x) {
-    const float g = gg[p];
-    const float m = b1 * mm[p] + c1 * g;
-    const float v = b2 * vv[p] + c2 * g * g;
-    mm[p] = m;
-    vv[p] = v;
-    th[p] = th[p] - step * m / (sqrtf(v) * rs + ep);
+  return AdamCoef{sh[0], sh[1], (float)a.beta1, (float)(1.0 - a.beta1), (float)a.beta2,
+                  (float)(1.0 - a.beta2), (float)a.eps};
+}
+
+__device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th, float& m, float& v) {
+  m = c.b1 * m + c.c1 * g;
+  v = c.b2 * v + c.c2 * g * g;
+  th = th - c.step * m / (sqrtf(v) * c.rs + c.eps);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const OptArgs a_in, int want_grad) {
+  OptArgs a = a_in;
+  read_batch(a);
+  const int j = blockIdx.y;
+  const int k = a.ids[j];
+  const bool valid = obj_valid(a, k);
+  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
+    float s = 0.f;
+    if (valid)
+      for (int t = t0; t < t1; ++t) s += a.tile_loss[t];
+    a.loss_out[j] = s;
   }
-  __syncthreads();  // every thread has read the step count above
-  if (threadIdx.x == 0) desc[k].step = t;
+  if (!want_grad || !valid) return;
+  const int P = a.desc[k].n_params;
+  bool bad = false;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.p_stride) {
+    const float g = (p < P) ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
+    bad = !isfinite(g);
+    a.grad[(size_t)k * a.p_stride + p] = g;
+    if (a.grad_out) a.grad_out[(size_t)j * a.p_stride + p] = g;
+  }
+  if (bad) atomicOr(&a.flags[k], 1);
+}
+
+__global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
+  OptArgs a = a_in;
+  read_batch(a);
+  const int j = blockIdx.y;
+  if (blockIdx.x == 0 && j == 0) scaler_update(a);
+  const int k = a.ids[j];
+  if (!obj_valid(a, k) || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
+  const int t = a.t_next[j];
+  const AdamCoef c = adam_coef(a, t);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.desc[k].n_params) {
+    const size_t i = (size_t)k * a.p_stride + p;
+    float th = a.theta[i], m = a.m[i], v = a.v[i];
+    adam_elem(c, a.grad[i], th, m, v);
+    a.theta[i] = th;
+    a.m[i] = m;
+    a.v[i] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
+}
+
+// Training step: gradient and update in one pass. A non-finite gradient element (possible only
+// if finite tile partials overflow when added) leaves its parameter unchanged and flags the
+// object for the skip count.
+__global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
+  OptArgs a = a_in;
+  read_batch(a);
+  const int j = blockIdx.y;
+  if (blockIdx.x == 0 && j == 0) scaler_update(a);
+  const int k = a.ids[j];
+  const bool valid = obj_valid(a, k);
+  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
+    float s = 0.f;
+    if (valid)
+      for (int t = t0; t < t1; ++t) s += a.tile_loss[t];
+    a.loss_out[j] = s;
+  }
+  if (!valid || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
+  const int t = a.t_next[j];
+  const AdamCoef c = adam_coef(a, t);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.desc[k].n_params) {
+    const size_t i = (size_t)k * a.p_stride + p;
+    const float g = tile_sum(a.partial, a.p_stride, t0, t1, p);
+    a.grad[i] = g;
+    if (isfinite(g)) {
+      float th = a.theta[i], m = a.m[i], v = a.v[i];
+      adam_elem(c, g, th, m, v);
+      a.theta[i] = th;
+      a.m[i] = m;
+      a.v[i] = v;
+    } else {
+      atomicOr(&a.flags[k], 1);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -869,6 +1062,63 @@ __global__ void __launch_bounds__(256) k_init(int k, uint64_t seed, InitBounds i
   grad[i] = 0.f;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Depth-guided sampling (Sec. 3.3, Eqs. 1 and 2). A group of P lanes (P = S rounded up to a power
+// of two) holds one ray: lane i < S draws sample i — stratified in [t_n, t_s] for i < n_strat,
+// N(t_s, sigma^2) otherwise — in FP64 from counter-based SplitMix64 uniforms, and the group sorts
+// its S values with a bitonic network over lane shuffles (padding lanes carry +inf).
+
+__global__ void __launch_bounds__(256) k_sample(int n_rays, int S, int P, int n_strat,
+                                                const float* __restrict__ t_near,
+                                                const float* __restrict__ t_far,
+                                                const float* __restrict__ depth, float sigma,
+                                                uint64_t seed, float* __restrict__ t_out) {
+  const int lane = threadIdx.x & 63;
+  const int groups_per_wave = kWave / P;
+  const int wave_global = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int i = lane & (P - 1);
+  const int r = wave_global * groups_per_wave + lane / P;
+  float v = INFINITY;
+  if (r < n_rays && i < S) {
+    const double tn = t_near[r], tf = t_far[r], d = depth[r];
+    const double ts = (d > 0.0) ? d : tf;
+    const uint64_t idx = ((uint64_t)r * (uint64_t)S + (uint64_t)i) * 2ull;
+    const double top0 = (double)(splitmix64_at(seed, idx) >> 40);
+    double t;
+    if (i < n_strat) {
+      t = tn + ((double)i + top0 * 0x1p-24) / (double)n_strat * (ts - tn);
+    } else {
+      const double top1 = (double)(splitmix64_at(seed, idx + 1ull) >> 40);
+      const double z = sqrt(-2.0 * log((top0 + 1.0) * 0x1p-24)) * cos(6.283185307179586477 * top1 * 0x1p-24);
+      t = ts + (double)sigma * z;
+    }
+    v = (float)t;
+  }
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const float other = __shfl_xor(v, j);
+      const bool ascending = (i & k) == 0;
+      const bool lower = (i & j) == 0;
+      v = (lower == ascending) ? fminf(v, other) : fmaxf(v, other);
+    }
+  }
+  if (r < n_rays && i < S) t_out[(size_t)r * S + i] = v;
+}
+
+hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, const float* t_far,
+                         const float* depth, float sigma, uint64_t seed, float* t_out,
+                         hipStream_t s) {
+  if (n_rays <= 0) return hipSuccess;
+  int P = 1;
+  while (P < S) P <<= 1;
+  const int rays_per_wave = kWave / P;
+  const long long waves = (n_rays + rays_per_wave - 1) / rays_per_wave;
+  const int blocks = (int)((waves + 3) / 4);
+  hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(256), 0, s, n_rays, S, P, n_strat, t_near,
+                     t_far, depth, sigma, seed, t_out);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -885,16 +1135,21 @@ __global__ void k_init_scaler(ScalerState* sc, float scale) {
 // ---------------------------------------------------------------------------------------------
 // Launchers.
 
+// Raise a kernel's dynamic-LDS limit to what a launch needs (once per size increase). Asking for
+// the whole 160 KB fails when the kernel also holds static LDS.
+static hipError_t allow_lds(const void* fn, int bytes, int* allowed) {
+  if (bytes <= *allowed || bytes <= 64 * 1024) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) *allowed = bytes;
+  return e;
+}
+
 template <int H, bool BF, int MODE>
 static hipError_t launch_tiles_t(const StepArgs& a, int nwaves, int grid, hipStream_t s) {
-  static bool attr_done = false;
+  static int allowed = 0;
   auto fn = k_step_tiles<H, BF, MODE>;
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_done = true;
-  }
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(fn), a.lds.total, &allowed);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(nwaves * kWave), a.lds.total, s, a);
   return hipGetLastError();
 }
@@ -922,14 +1177,10 @@ hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwave
 
 template <int H, bool BF>
 static hipError_t launch_query_t(const QueryArgs& q, hipStream_t s) {
-  static bool attr_done = false;
+  static int allowed = 0;
   auto fn = k_query<H, BF>;
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_done = true;
-  }
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(fn), q.lds.total, &allowed);
+  if (e != hipSuccess) return e;
   const int nw = 4;
   int64_t chunks = (q.n + kSlots - 1) / kSlots;
   int grid = (int)std::min<int64_t>((chunks + nw - 1) / nw, 2048);
@@ -955,36 +1206,21 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int max_objects, int32_t* tile_start,
-                           int32_t* flags, hipStream_t s) {
+                           int rays_per_tile, int max_objects, const ObjDesc* desc,
+                           int32_t* tile_start, int32_t* flags, int32_t* t_next,
+                           const BatchDev* bd, hipStream_t s) {
   hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, object_ids, ray_offsets,
-                     rays_per_tile, max_objects, tile_start, flags);
+                     rays_per_tile, max_objects, desc, tile_start, flags, t_next, bd);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int n_objects, const int32_t* object_ids, const int32_t* tile_start,
-                         const float* partial, const float* tile_loss, int p_stride,
-                         int max_objects, const ObjDesc* desc, const ScalerState* scaler,
-                         int unscale, float* grad, float* grad_out, int32_t* flags,
-                         float* loss_out, int want_grad, hipStream_t s) {
-  if (n_objects <= 0) return hipSuccess;
-  const int gx = want_grad ? (p_stride + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_reduce, dim3(gx, n_objects), dim3(256), 0, s, n_objects, object_ids,
-                     tile_start, partial, tile_loss, p_stride, max_objects, desc, scaler, unscale,
-                     grad, grad_out, flags, loss_out, want_grad);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                       int max_objects, ObjDesc* desc, ScalerState* scaler,
-                       const int32_t* flags, float* theta, float* m, float* v,
-                       const float* grad, int p_stride, double lr, double beta1,
-                       double beta2, double eps, int bf16, int growth_interval,
-                       hipStream_t s) {
-  if (n_objects <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adam, dim3(n_objects), dim3(256), 0, s, n_objects, object_ids,
-                     ray_offsets, max_objects, desc, scaler, flags, theta, m, v, grad, p_stride,
-                     lr, beta1, beta2, eps, bf16, growth_interval);
+hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
+  if (a.n_objects <= 0) return hipSuccess;
+  const dim3 grid((a.p_stride + 255) / 256, a.n_objects);
+  if (kind == OPT_REDUCE) hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, 1);
+  else if (kind == OPT_LOSS) hipLaunchKernelGGL(k_reduce, dim3(1, a.n_objects), dim3(256), 0, s, a, 0);
+  else if (kind == OPT_ADAM) hipLaunchKernelGGL(k_adam, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_reduce_adam, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -418,3 +418,41 @@ def test_grid_size_does_not_change_results(precision):
     for loss, th in out[1:]:
         assert np.array_equal(loss, out[0][0])
         assert all(np.array_equal(a, b) for a, b in zip(th, out[0][1]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_graph_replay_over_changing_batches(precision):
+    """One captured graph serves batches of the same shape in different buffers."""
+    sc = _scaled(scenes.make_scene("k50_uneven"), 10)
+    dbs = [vm.DeviceBatch(scenes.make_batch(sc, step)) for step in range(4)]
+    objs, _ = make_pair(sc, precision)
+    objs_g, _ = make_pair(sc, precision)
+    objs_g.set_graph_mode(True)
+    for db in dbs:
+        l1 = objs.step(db).cpu().numpy()
+        l2 = objs_g.step(db).cpu().numpy()
+        assert np.array_equal(l1, l2)
+    torch.cuda.synchronize()
+    for k in range(sc.n_objects):
+        for w in (vm.STATE_PARAMS, vm.STATE_ADAM_M, vm.STATE_ADAM_V):
+            assert np.array_equal(objs.get_state(k, w), objs_g.get_state(k, w))
+        assert objs.get_state(k, vm.STATE_STEP) == objs_g.get_state(k, vm.STATE_STEP) == 4
+
+
+@pytest.mark.parametrize("S,n_strat", [(10, 5), (20, 10), (1, 1), (1, 0), (33, 16), (64, 32)])
+def test_depth_guided_sampling_matches_oracle(S, n_strat):
+    """On-device Eqs. 1-2 against the oracle's sampler: same counter-based uniforms, FP64
+    arithmetic on both sides, FP32 output; sorted per ray."""
+    rng = np.random.default_rng(S)
+    R = 3001
+    tn = rng.uniform(0.3, 1.0, R).astype(np.float32)
+    tf = (tn + rng.uniform(0.5, 3.0, R)).astype(np.float32)
+    depth = np.where(rng.uniform(size=R) < 0.8, rng.uniform(tn + 0.1, tf), 0.0).astype(np.float32)
+    sc = scenes.make_scene("tiny_k4")
+    objs = vm.ObjectSet(max_objects=1, B=sc.B, hidden=32, max_rays=16, max_samples_per_ray=8)
+    seed = 0x1234_5678_9ABC + S
+    t = objs.sample_rays(tn, tf, depth, S, n_strat, sigma=0.03, seed=seed).cpu().numpy()
+    ref = oracle.depth_guided_samples(tn, tf, depth, S, n_strat, 0.03, seed)
+    assert np.all(np.diff(t, axis=1) >= 0)
+    np.testing.assert_allclose(t, ref, rtol=2.5e-7, atol=0)
+    _report(f"sampling S={S} n_strat={n_strat}", max_rel=float(np.max(np.abs(t - ref) / np.abs(ref))))

@@ -503,3 +503,45 @@ def test_query_matches_forward_samples():
     occ, rgb = oracle.query(th, 32, 4, sc.B, ob.norm_centre, ob.norm_scale, pts.reshape(-1, 3))
     np.testing.assert_allclose(occ, fw["o"].ravel(), rtol=1e-12)
     np.testing.assert_allclose(rgb, fw["c"].reshape(-1, 3), rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------- sampling
+
+def test_splitmix64_array_matches_scalar_definition():
+    idx = np.array([0, 1, 2, 1000, 2 ** 40 + 3], dtype=np.uint64)
+    for seed in (0, 1234567, 2 ** 64 - 1):
+        np.testing.assert_array_equal(oracle.splitmix64_array(seed, idx),
+                                      oracle.splitmix64(seed, idx.astype(np.int64)))
+
+
+def test_depth_guided_samples_properties():
+    """Eq. 1: each stratified sample lies in its own stratum of [t_n, t_s]; Eq. 2: the surface
+    samples have mean t_s and spread sigma; t_s falls back to t_f for invalid depth."""
+    rng = np.random.default_rng(0)
+    R, S, Nc, sigma = 4000, 20, 10, 0.03
+    tn = rng.uniform(0.5, 1.0, R)
+    tf = tn + rng.uniform(1.0, 3.0, R)
+    depth = np.where(rng.uniform(size=R) < 0.8, rng.uniform(tn + 0.2, tf), 0.0)
+    t = oracle.depth_guided_samples(tn, tf, depth, S, Nc, sigma, seed=42)
+    assert t.shape == (R, S) and np.all(np.diff(t, axis=1) >= 0)
+    # rebuild the unsorted samples to check each stratum
+    ts = np.where(depth > 0, depth, tf)
+    idx = (np.arange(R)[:, None] * S + np.arange(S)[None, :]).astype(np.uint64) * np.uint64(2)
+    u = (oracle.splitmix64_array(42, idx) >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    for i in range(Nc):
+        lo = tn + i / Nc * (ts - tn)
+        hi = tn + (i + 1) / Nc * (ts - tn)
+        x = tn + (i + u[:, i]) / Nc * (ts - tn)
+        assert np.all(x >= lo - 1e-12) and np.all(x <= hi + 1e-12)
+        # each stratified value appears among the sorted samples of its ray
+        assert np.all(np.min(np.abs(t - x[:, None]), axis=1) < 1e-12)
+    # surface samples: the S - Nc values not matched to strata, z-scored
+    strat = np.stack([tn + (i + u[:, i]) / Nc * (ts - tn) for i in range(Nc)], 1)
+    z = []
+    for r in range(R):
+        rest = list(t[r])
+        for x in strat[r]:
+            rest.pop(int(np.argmin(np.abs(np.array(rest) - x))))
+        z.extend((np.array(rest) - ts[r]) / sigma)
+    z = np.array(z)
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1.0) < 0.02
