@@ -63,7 +63,9 @@ typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed
  * "Surface and Volume Rendering"). Parameters of one object are stored, in this order,
  * W_1 [H x E], b_1 [H], W_2 [H x H], b_2, ..., W_L, b_L, W_out [4 x H], b_out [4], every W
  * row-major as [out][in]; E = 2 * n_features. Supported: n_features = 16, n_hidden_layers = 4,
- * hidden in {32, 64}, 1 <= max_samples_per_ray <= 64.
+ * hidden in {32, 64} in both precisions and 128 in VMAP_BF16 (the background
+ * model's width, Sec. 4, Implementation Details), 1 <= max_samples_per_ray <= 64. Objects of
+ * different widths may share a stack and a batch (max_hidden bounds them).
  */
 typedef struct {
   int32_t max_objects;          /* capacity of the model stack, 1..65536 */
@@ -118,7 +120,9 @@ typedef struct {
 size_t vmap_state_bytes(const vmap_config* cfg);
 
 /* Bytes of the caller-owned device workspace for batches of up to config.max_rays rays and
- * config.max_objects objects. Returns 0 for an invalid config. Host only. */
+ * config.max_objects objects: tile partial gradients, work lists and, when max_hidden = 128,
+ * one BF16 weight image per object slot (the training kernel reads wide weights from device
+ * memory). Returns 0 for an invalid config. Host only. */
 size_t vmap_workspace_bytes(const vmap_config* cfg);
 
 /* Number of parameters of one object of width `hidden` under cfg (no padding). Host only. */

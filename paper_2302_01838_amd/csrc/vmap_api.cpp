@@ -29,14 +29,12 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, t_next, batch, tile_loss, partial, total;
+  size_t tile_start, flags, t_next, batch, tile_loss, partial, wimage, total;
+  size_t wimage_stride;
   int max_tiles;
 };
 
-bool hidden_ok(int H, int precision) {
-  if (precision == VMAP_BF16) return H == 32 || H == 64;
-  return H == 32 || H == 64;
-}
+bool hidden_ok(int H, int precision) { return tiles_supported(H, precision == VMAP_BF16) != 0; }
 
 const char* check_config(const vmap_config* c) {
   if (!c) return "config is NULL";
@@ -44,7 +42,8 @@ const char* check_config(const vmap_config* c) {
   if (c->n_features != kFeatures) return "n_features must be 16";
   if (c->n_hidden_layers != kLayers) return "n_hidden_layers must be 4";
   if (c->precision != VMAP_FP32 && c->precision != VMAP_BF16) return "precision must be VMAP_FP32 or VMAP_BF16";
-  if (!hidden_ok(c->hidden, c->precision)) return "hidden width not supported (32 or 64)";
+  if (!hidden_ok(c->hidden, c->precision))
+    return "hidden width not supported (32 or 64; 128 in BF16)";
   if (c->max_hidden < c->hidden || !hidden_ok(c->max_hidden, c->precision))
     return "max_hidden must be a supported width >= hidden";
   if (c->max_samples_per_ray < 1 || c->max_samples_per_ray > kSlots) return "max_samples_per_ray must be in [1, 64]";
@@ -95,6 +94,10 @@ WorkLayout work_layout(const vmap_config* c) {
   w.batch = off; off = align256(off + sizeof(BatchDev));
   w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.partial = off; off = align256(off + (size_t)w.max_tiles * ps * 4);
+  // weight images of wide objects (weights read from device memory by the tile kernel)
+  const bool bf = c->precision == VMAP_BF16;
+  w.wimage_stride = weights_global(c->max_hidden) ? (size_t)image_bytes(c->max_hidden, bf) : 0;
+  w.wimage = off; off = align256(off + (size_t)c->max_objects * w.wimage_stride);
   w.total = off;
   return w;
 }
@@ -157,6 +160,7 @@ struct vmap_ctx {
   BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
   float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
   float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
+  unsigned char* wimage() { return wl.wimage_stride ? work + wl.wimage : nullptr; }
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -225,6 +229,8 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.flags = c->flags();
   a.lambda_c = (float)c->cfg.lambda_colour;
   a.lambda_o = (float)c->cfg.lambda_occ;
+  a.wimage = c->wimage();
+  a.wimage_stride = (int64_t)c->wl.wimage_stride;
   return a;
 }
 
@@ -303,8 +309,9 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
   }
   for (int H : widths_present(c)) {
     a.hidden = H;
-    a.lds = lds_layout(H, bf, c->waves);
-    hipError_t e = launch_tiles(H, bf, mode, a, c->waves, grid, s);
+    hipError_t e = launch_stage_images(H, bf, a, -1, s);
+    if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
+    e = launch_tiles(H, bf, mode, a, c->waves, grid, s);
     if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
   }
   if (timed) {
@@ -378,10 +385,11 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
     }
   }
   const bool bf = cfg->precision == VMAP_BF16;
-  const LdsLayout L = lds_layout(cfg->max_hidden, bf, 4);
-  if (L.total > 160 * 1024) {
-    g_init_error = "model too large for the 160 KB LDS of a workgroup";
-    return VMAP_ENOTSUP;
+  for (int H = 32; H <= cfg->max_hidden; H *= 2) {
+    if (tiles_supported(H, bf) && tile_lds_bytes(H, bf, 4) > 160 * 1024) {
+      g_init_error = "model too large for the 160 KB LDS of a workgroup";
+      return VMAP_ENOTSUP;
+    }
   }
   vmap_ctx* c = new vmap_ctx();
   c->cfg = *cfg;
@@ -605,8 +613,23 @@ int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, fl
   q.occ = occ_out;
   q.rgb = rgb_out;
   const bool bf = c->cfg.precision == VMAP_BF16;
-  q.lds = lds_layout(c->objs[k].hidden, bf, 4);
-  hipError_t e = launch_query(c->objs[k].hidden, bf, q, reinterpret_cast<hipStream_t>(stream));
+  const int H = c->objs[k].hidden;
+  q.wimage = c->wimage();
+  q.wimage_stride = (int64_t)c->wl.wimage_stride;
+  q.max_objects = c->cfg.max_objects;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (weights_global(H)) {
+    StepArgs a{};
+    a.max_objects = c->cfg.max_objects;
+    a.theta = c->theta();
+    a.p_stride = c->p_stride;
+    a.desc = c->desc();
+    a.wimage = c->wimage();
+    a.wimage_stride = (int64_t)c->wl.wimage_stride;
+    hipError_t e = launch_stage_images(H, bf, a, k, s);
+    if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
+  }
+  hipError_t e = launch_query(H, bf, q, s);
   if (e != hipSuccess) return c->hip_fail(e, "query launch");
   return VMAP_OK;
 }

@@ -106,6 +106,43 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   return L;
 }
 
+// Wide models (H >= 128) keep their weights in a per-object image in device memory with the byte
+// layout of the LDS staging above (offsets below B_off), since weights and BF16 transposes do not
+// fit in LDS next to the cooperative kernel's staging tiles.
+__host__ __device__ constexpr bool weights_global(int H) { return H >= 128; }
+__host__ __device__ constexpr int image_bytes(int H, bool bf16) {
+  return round_up(lds_layout(H, bf16, 1).B_off, 256);
+}
+
+// LDS of the cooperative tile kernel (H >= 64): the weights as in lds_layout unless they live in
+// the device image, then the encoding matrix, the tile's loss / output-bias sums and a flag, and
+// four waves' staging tiles, which the waves read from each other.
+struct CoopLayout {
+  int B_off;
+  int loss_off;     // float loss, float head-bias gradient [4], int non-finite flag
+  int scratch_off;
+  int scratch_wave;
+  int total;
+};
+__host__ __device__ constexpr CoopLayout coop_layout(int H, bool bf16) {
+  CoopLayout C{};
+  int off = weights_global(H) ? 0 : lds_layout(H, bf16, 1).B_off;
+  C.B_off = off;
+  off = round_up(off + 3 * kFeatures * 4, 16);
+  C.loss_off = off;
+  off = round_up(off + 32, 16);
+  C.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16), 16);
+  C.scratch_off = off;
+  off += 4 * C.scratch_wave;
+  C.total = off;
+  return C;
+}
+
+// Offset of layer l's weights in an object's parameter vector (l = kLayers: the output layer).
+__host__ __device__ constexpr int layer_param_off(int H, int l) {
+  return l == 0 ? 0 : (H * kEnc + H) + (l - 1) * (H * H + H);
+}
+
 // A batch's shape and buffers in device memory. Graph replays of the training step read the batch
 // from here (refreshed by one small copy per call) instead of from their captured arguments.
 struct BatchDev {
@@ -158,7 +195,8 @@ struct StepArgs {
   float lambda_o;
   int use_scale;              // multiply seeds by the loss scale (BF16 training)
   const BatchDev* bd;         // if not NULL, the batch fields above are read from here
-  LdsLayout lds;
+  unsigned char* wimage;      // weight images of wide objects, [max_objects][wimage_stride]
+  int64_t wimage_stride;
 };
 
 struct QueryArgs {
@@ -171,7 +209,9 @@ struct QueryArgs {
   const float* B;
   float* occ;
   float* rgb;
-  LdsLayout lds;
+  unsigned char* wimage;      // as in StepArgs (wide objects)
+  int64_t wimage_stride;
+  int max_objects;
 };
 
 // Arguments of the gradient / optimiser kernels.
@@ -220,5 +260,9 @@ hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, co
                          const float* depth, float sigma, uint64_t seed, float* t_out,
                          hipStream_t s);
 int tiles_supported(int H, bool bf16);
+int tile_lds_bytes(int H, bool bf16, int nwaves);
+int tile_waves(int H, int requested);
+// Weight images of wide objects: those of the batch (single < 0) or of object `single`.
+hipError_t launch_stage_images(int H, bool bf16, const StepArgs& a, int single, hipStream_t s);
 
 }  // namespace vmapi

@@ -74,6 +74,22 @@ __device__ __forceinline__ float round_w(float x) {
   return x;
 }
 
+// Reads of a wide object's weight image in device memory through a buffer resource: the lane
+// part of an offset sits in one VGPR and the block's constant part in an SGPR or the immediate,
+// so unrolled loops need no 64-bit address per load.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const unsigned char* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ bf16x8 img_b128(__amdgpu_buffer_rsrc_t r, int lane_off, int off) {
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, off, 0));
+}
+__device__ __forceinline__ f32x4 img_f4(__amdgpu_buffer_rsrc_t r, int lane_off, int off) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, off, 0));
+}
+__device__ __forceinline__ float img_f1(__amdgpu_buffer_rsrc_t r, int lane_off, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, off, 0));
+}
+
 // Activations of one 32-sample pass: NL + 1 layers (encoding first), H/32 blocks, D layout.
 template <int H, bool BF>
 struct Acts;
@@ -90,15 +106,31 @@ struct Acts<H, true> {
   __device__ __forceinline__ void set(int l, int b, int r, float x) { v[l][b][r >> 3][r & 7] = (__bf16)x; }
 };
 
+// Back-propagated deltas of one 32-sample pass in the accumulator layout. In BF16 mode they only
+// ever enter products and LDS staging rounded to BF16, so they are kept rounded.
+template <int H, bool BF>
+struct Deltas;
+template <int H>
+struct Deltas<H, false> {
+  float v[H / 32][16];
+  __device__ __forceinline__ void set(int b, int r, float x) { v[b][r] = x; }
+};
+template <int H>
+struct Deltas<H, true> {
+  bf16x8 v[H / 32][2];
+  __device__ __forceinline__ void set(int b, int r, float x) { v[b][r >> 3][r & 7] = (__bf16)x; }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Weight staging: object k's parameters -> LDS (permuted columns; BF16 in BF16 mode, plus the
-// transposed copies that the backward's input-gradient products read as A operands).
+// transposed copies that the backward's input-gradient products read as A operands). Threads
+// tid, tid + nt, ... of the caller share the work; the destination may also be a weight image in
+// device memory (wide models).
 
 template <int H, bool BF>
-__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem) {
+__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem, int tid, int nt) {
   constexpr LdsLayout L = lds_layout(H, BF, 1);
   using WT = typename std::conditional<BF, __bf16, float>::type;
-  const int tid = threadIdx.x, nt = blockDim.x;
   int off = 0;
   float* bias = reinterpret_cast<float*>(smem + L.b_off);
 #pragma unroll
@@ -133,24 +165,24 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem)
   }
   off += kOut * H;
   float* bh = reinterpret_cast<float*>(smem + L.bh_off);
-  if (tid < kOut) bh[tid] = th[off + tid];
+  for (int e = tid; e < kOut; e += nt) bh[e] = th[off + e];
 }
 
 // ---------------------------------------------------------------------------------------------
 // Forward of one 32-sample pass for the calling wave. xt: this lane's normalised point (the
-// sample of column n = lane & 31; both lane halves hold the same point). Fills the activations
+// sample of column n = lane & 31; both lane halves hold the same point); Bm: the encoding matrix. Fills the activations
 // and, with WITH_HEAD, returns the four output pre-activations z of sample n (valid in both lane
 // halves).
 
 template <int H, bool BF, bool WITH_HEAD>
 __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
-                                             Acts<H, BF>& A, float z[4]) {
+                                             const float* Bm, Acts<H, BF>& A, float z[4]) {
   constexpr int MT = H / 32;
   constexpr LdsLayout L = lds_layout(H, BF, 1);
-  // Weights are re-read from LDS on every pass instead of being held in registers across passes.
+  // Weights are re-read on every pass instead of being held in registers across passes. `smem`
+  // is the weight base: the LDS staging, or a wide object's image in device memory.
   asm volatile("" ::: "memory");
   const int lane = threadIdx.x & 63, n = lane & 31, hf = lane >> 5;
-  const float* Bm = reinterpret_cast<const float*>(smem + L.B_off);
   // Gaussian Fourier features: register r of block 0 holds feature rowof(r, hf):
   // r = 0..3 sin(phi[4hf + r]), 4..7 sin(phi[8 + 4hf + r - 4]), 8..15 the cosines.
 #pragma unroll
@@ -165,6 +197,51 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
       A.set(0, 0, 8 + 4 * g + i, c);
     }
   }
+  if constexpr (weights_global(H)) {
+    static_assert(BF, "weights in device memory: BF16 only");
+    const __amdgpu_buffer_rsrc_t rs = image_rsrc(smem, image_bytes(H, BF));
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+      const int KB = (l == 0) ? 1 : MT;
+      const int ws = L.w_stride[l];
+      const int lw = (n * ws + 16 * hf) * 2;
+#pragma unroll
+      for (int mo = 0; mo < MT; ++mo) {
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const bf16x8 wa = img_b128(rs, lw, L.w_off[l] + (mo * 32 * ws + kb * 32 + 8 * jj) * 2);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, A.v[l][kb][jj], acc, 0, 0, 0);
+          }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {  // rows 8g + 4hf + i
+          const f32x4 b4 = img_f4(rs, 16 * hf, L.b_off + (l * H + mo * 32 + 8 * g) * 4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) A.set(l + 1, mo, 4 * g + i, fmaxf(acc[4 * g + i] + b4[i], 0.0f));
+        }
+      }
+    }
+    if constexpr (!WITH_HEAD) return;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int lw = (min(n, kOut - 1) * (H + 8) + 16 * hf) * 2;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        bf16x8 wa = img_b128(rs, lw, L.whb_off + (mt * 32 + 8 * jj) * 2);
+        if (n >= kOut) wa = bf16x8{};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, A.v[kLayers][mt][jj], acc, 0, 0, 0);
+      }
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) z[c] = __shfl(acc[c], n) + img_f1(rs, 0, L.bh_off + 4 * c);
+    return;
+  } else {
   const float* bias = reinterpret_cast<const float*>(smem + L.b_off);
 #pragma unroll
   for (int l = 0; l < kLayers; ++l) {
@@ -232,6 +309,7 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
       z[c] = s + bh[c];
     }
   }
+  }  // weights in LDS
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -261,6 +339,98 @@ __device__ __forceinline__ void read_batch(OptArgs& a) {
   }
 }
 
+// Rendering (Eq. 3), the masked L1 losses (Eqs. 4-7) and, in training, their adjoint for one
+// sub-tile of the calling wave: lane = sample slot, zs = the slot's head pre-activations (r, g, b,
+// occupancy). Adds the sub-tile's loss to `loss`; forward mode writes the rendered outputs;
+// training returns dL/dz of the slot in dzs (zero on slots at or past nslots).
+template <bool TRAIN>
+__device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int nslots, float wseed,
+                                               const float zs[kOut], float dzs[kOut], float& loss) {
+  const int lane = threadIdx.x & 63;
+  const int S = a.S;
+  const float lc = a.lambda_c, lo = a.lambda_o;
+  const bool valid = lane < nslots;
+  const int jr = valid ? lane / S : 0;
+  const int si = valid ? lane - jr * S : 0;
+  const int ray = r0 + jr;
+  float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f}, tt = 0.f;
+  if (valid) {
+    o = sigm(zs[3]);
+    q = sigm(-zs[3]);  // 1 - o, without cancellation
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
+    tt = a.t[(size_t)r0 * S + lane];
+  }
+  // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift
+  float Pin = q;
+  for (int off = 1; off < S; off <<= 1) {
+    const float u = __shfl_up(Pin, off);
+    if (si >= off) Pin *= u;
+  }
+  float Pex = __shfl_up(Pin, 1);
+  if (si == 0) Pex = 1.f;
+  const float Tw = o * Pex;  // termination probability T_i
+  float sO = Tw, sD = Tw * tt, sC0 = Tw * c3[0], sC1 = Tw * c3[1], sC2 = Tw * c3[2];
+  for (int off = 1; off < S; off <<= 1) {
+    const float u0 = __shfl_up(sO, off), u1 = __shfl_up(sD, off), u2 = __shfl_up(sC0, off),
+                u3 = __shfl_up(sC1, off), u4 = __shfl_up(sC2, off);
+    if (si >= off) { sO += u0; sD += u1; sC0 += u2; sC1 += u3; sC2 += u4; }
+  }
+  const int last = jr * S + S - 1;
+  const float Oh = __shfl(sO, last), Dh = __shfl(sD, last);
+  const float Ch[3] = {__shfl(sC0, last), __shfl(sC1, last), __shfl(sC2, last)};
+  const float Pend = __shfl(Pin, last);
+
+  float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+    // rendering without targets (forward mode, NULL target buffers) evaluates the loss terms
+    // against zero targets; that loss is not reported
+    const bool tg = TRAIN || a.depth != nullptr;
+    const float D = tg ? a.depth[ray] : 0.f, M = tg ? a.mask[ray] : 0.f;
+    const float rD = Dh - D;
+    float rC[3] = {Ch[0], Ch[1], Ch[2]};
+    if (tg) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rC[c] -= a.rgb[3 * ray + c];
+    }
+    const float rho = (M == 1.0f) ? -Pend : (Oh - M);
+    if (si == 0) {
+      loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
+      if constexpr (!TRAIN) {
+        if (a.out_depth) a.out_depth[ray] = Dh;
+        if (a.out_occ) a.out_occ[ray] = Oh;
+        if (a.out_rgb) { a.out_rgb[3 * ray] = Ch[0]; a.out_rgb[3 * ray + 1] = Ch[1]; a.out_rgb[3 * ray + 2] = Ch[2]; }
+      }
+    }
+    if constexpr (TRAIN) {
+      const float aD = wseed * M * sgnf(rD);
+      const float aO = wseed * lo * sgnf(rho);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) aC[c] = wseed * lc * M * sgnf(rC[c]);
+      g = aD * tt + aC[0] * c3[0] + aC[1] * c3[1] + aC[2] * c3[2] + aO;
+    }
+  }
+  if constexpr (!TRAIN) return;
+
+  // adjoint of rendering: reverse affine scan Q_i = o_i g_i + (1 - o_i) Q_{i+1}
+  float Aq = q, Bq = o * g;
+  for (int off = 1; off < S; off <<= 1) {
+    const float A2 = __shfl_down(Aq, off), B2 = __shfl_down(Bq, off);
+    if (si + off < S) { Bq = Bq + Aq * B2; Aq = Aq * A2; }
+  }
+  float Snext = __shfl_down(Bq, 1);
+  if (si == S - 1) Snext = 0.f;
+  if (valid) {
+    const float dO = Pex * (g - Snext);
+    dzs[3] = dO * o * q;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dzs[c] = Tw * aC[c] * c3[c] * cq[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) dzs[c] = 0.f;
+  }
+}
+
 template <int H, bool BF, int MODE>
 __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(const StepArgs a_in) {
   StepArgs a = a_in;
@@ -274,9 +444,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   const int S = a.S;
   const int rpw = kSlots / S;
   const int n_tiles = a.tile_start[a.n_objects];
-  const float lc = a.lambda_c, lo = a.lambda_o;
 
-  if (tid < 3 * kFeatures) reinterpret_cast<float*>(smem + L.B_off)[tid] = a.B[tid];
+  float* Bl = reinterpret_cast<float*>(smem + L.B_off);
+  if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
   int staged = -1;
 
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -297,7 +467,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
     if (k != staged) {
       __syncthreads();
-      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem);
+      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, tid, blockDim.x);
       staged = k;
     }
     __syncthreads();
@@ -370,93 +540,14 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         Acts<H, BF> tmp;
         float xt[3], z[kOut];
         point(p, xt);
-        forward_pass<H, BF, true>(xt, smem, tmp, z);
+        forward_pass<H, BF, true>(xt, smem, Bl, tmp, z);
 #pragma unroll
         for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
       }
 
-      // ---------------- rendering along each ray: lane = slot
-      const bool valid = lane < nslots;
-      const int jr = valid ? lane / S : 0;
-      const int si = valid ? lane - jr * S : 0;
-      const int ray = r0 + jr;
-      float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f}, tt = 0.f;
-      if (valid) {
-        o = sigm(zs[3]);
-        q = sigm(-zs[3]);  // 1 - o, without cancellation
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
-        tt = a.t[(size_t)r0 * S + lane];
-      }
-      // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift
-      float Pin = q;
-      for (int off = 1; off < S; off <<= 1) {
-        const float u = __shfl_up(Pin, off);
-        if (si >= off) Pin *= u;
-      }
-      float Pex = __shfl_up(Pin, 1);
-      if (si == 0) Pex = 1.f;
-      const float Tw = o * Pex;  // termination probability T_i
-      float sO = Tw, sD = Tw * tt, sC0 = Tw * c3[0], sC1 = Tw * c3[1], sC2 = Tw * c3[2];
-      for (int off = 1; off < S; off <<= 1) {
-        const float u0 = __shfl_up(sO, off), u1 = __shfl_up(sD, off), u2 = __shfl_up(sC0, off),
-                    u3 = __shfl_up(sC1, off), u4 = __shfl_up(sC2, off);
-        if (si >= off) { sO += u0; sD += u1; sC0 += u2; sC1 += u3; sC2 += u4; }
-      }
-      const int last = jr * S + S - 1;
-      const float Oh = __shfl(sO, last), Dh = __shfl(sD, last);
-      const float Ch[3] = {__shfl(sC0, last), __shfl(sC1, last), __shfl(sC2, last)};
-      const float Pend = __shfl(Pin, last);
-
-      float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
-      if (valid) {
-        // rendering without targets (forward mode, NULL target buffers) evaluates the loss terms
-        // against zero targets; that loss is not reported
-        const bool tg = TRAIN || a.depth != nullptr;
-        const float D = tg ? a.depth[ray] : 0.f, M = tg ? a.mask[ray] : 0.f;
-        const float rD = Dh - D;
-        float rC[3] = {Ch[0], Ch[1], Ch[2]};
-        if (tg) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) rC[c] -= a.rgb[3 * ray + c];
-        }
-        const float rho = (M == 1.0f) ? -Pend : (Oh - M);
-        if (si == 0) {
-          wave_loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
-          if constexpr (!TRAIN) {
-            if (a.out_depth) a.out_depth[ray] = Dh;
-            if (a.out_occ) a.out_occ[ray] = Oh;
-            if (a.out_rgb) { a.out_rgb[3 * ray] = Ch[0]; a.out_rgb[3 * ray + 1] = Ch[1]; a.out_rgb[3 * ray + 2] = Ch[2]; }
-          }
-        }
-        if constexpr (TRAIN) {
-          const float aD = wseed * M * sgnf(rD);
-          const float aO = wseed * lo * sgnf(rho);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) aC[c] = wseed * lc * M * sgnf(rC[c]);
-          g = aD * tt + aC[0] * c3[0] + aC[1] * c3[1] + aC[2] * c3[2] + aO;
-        }
-      }
-      if constexpr (!TRAIN) continue;
-
-      // ---------------- adjoint of rendering: reverse affine scan Q_i = o_i g_i + (1 - o_i) Q_{i+1}
-      float Aq = q, Bq = o * g;
-      for (int off = 1; off < S; off <<= 1) {
-        const float A2 = __shfl_down(Aq, off), B2 = __shfl_down(Bq, off);
-        if (si + off < S) { Bq = Bq + Aq * B2; Aq = Aq * A2; }
-      }
-      float Snext = __shfl_down(Bq, 1);
-      if (si == S - 1) Snext = 0.f;
       float dzs[kOut];
-      if (valid) {
-        const float dO = Pex * (g - Snext);
-        dzs[3] = dO * o * q;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dzs[c] = Tw * aC[c] * c3[c] * cq[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < kOut; ++c) dzs[c] = 0.f;
-      }
+      render_subtile<TRAIN>(a, r0, nslots, wseed, zs, dzs, wave_loss);
+      if constexpr (!TRAIN) continue;
 #pragma unroll
       for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
 
@@ -470,7 +561,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         {  // recompute the activations of this pass
           float xt[3], z[kOut];
           point(p, xt);
-          forward_pass<H, BF, false>(xt, smem, act, z);
+          forward_pass<H, BF, false>(xt, smem, Bl, act, z);
         }
         float dz[kOut];
 #pragma unroll
@@ -763,16 +854,541 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 }
 
 // ---------------------------------------------------------------------------------------------
+// Tile kernel for wide models (H = 64, 128): the four waves of a workgroup split every weight
+// gradient by rows. Each wave runs the forward, rendering, adjoint and delta chain of its own
+// sub-tile as k_step_tiles does, stages delta_l and h_{l-1} in LDS, and after a workgroup barrier
+// computes its quarter of the rows of dW_l (and db_l) over the 128 samples of all four waves, on
+// v_mfma_f32_16x16x32_bf16 (BF16) or v_mfma_f32_16x16x4f32 (FP32). A wave thus holds a quarter of
+// the weight-gradient accumulators, and the tile needs no cross-wave reduction: the waves' slices
+// are disjoint. For H = 128 the weights and their BF16 transposes do not fit in LDS beside the
+// staging tiles: they are read from the object's weight image in device memory (the byte layout
+// of the LDS staging, written by k_stage_image for this step), and each wave accumulates its
+// gradient slice in the tile's partial in device memory, layer by layer, not in registers.
+
+template <int H, bool BF, int MODE>
+__global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
+  static_assert(H == 64 || H == 128, "cooperative tile kernel: H = 64 or 128");
+  StepArgs a = a_in;
+  read_batch(a);
+  constexpr int MT = H / 32;
+  constexpr bool TRAIN = (MODE == MODE_TRAIN);
+  constexpr bool GW = weights_global(H);
+  constexpr bool RMW = GW;          // gradient slices accumulate in the partial
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
+  constexpr CoopLayout C = coop_layout(H, BF);
+  constexpr int RW = H / 4;         // weight-gradient rows of one wave
+  constexpr int RB = RW / 16;       // ... in 16-row blocks
+  constexpr int NBH = H / 16;       // 16-column blocks of a hidden layer's input
+  constexpr int HB = H / 64;        // 16-column blocks of the output layer's dW of one wave
+  constexpr int FW = H / 4;         // FP32 output layer: features of one wave
+  constexpr int TB = dz_tile_bytes(BF), TT = tr_tile_bytes(H, BF);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = lane & 31, hf = lane >> 5;
+  const int m16 = lane & 15, kg = lane >> 4;
+  const int S = a.S;
+  const int rpw = kSlots / S;
+  const int n_tiles = a.tile_start[a.n_objects];
+  float* Bl = reinterpret_cast<float*>(smem + C.B_off);
+  if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
+  unsigned char* const scr0 = smem + C.scratch_off;
+  int staged = -1;
+
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    int jlo = 0, jhi = a.n_objects;
+    while (jhi - jlo > 1) {
+      const int mid = (jlo + jhi) >> 1;
+      if (a.tile_start[mid] <= tile) jlo = mid; else jhi = mid;
+    }
+    const int j = jlo;
+    // uniform by construction: the weight-image and partial buffer resources live in SGPRs
+    const int k = __builtin_amdgcn_readfirstlane(a.object_ids[j]);
+    if (k < 0 || k >= a.max_objects || !a.desc[k].registered) {
+      if (tid == 0) atomicOr(&a.scaler->device_error, 1);
+      continue;
+    }
+    if (a.desc[k].hidden != H) continue;
+    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * a.rays_per_tile;
+    const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
+    const unsigned char* wb = smem;
+    if constexpr (GW) {
+      wb = a.wimage + (size_t)k * a.wimage_stride;
+    } else if (k != staged) {
+      __syncthreads();
+      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, tid, blockDim.x);
+      staged = k;
+    }
+    __syncthreads();
+    const double cx = a.desc[k].centre[0], cy = a.desc[k].centre[1], cz = a.desc[k].centre[2];
+    const double inv_s = a.desc[k].inv_scale;
+    float wseed = 1.0f;
+    if constexpr (TRAIN) {
+      if (a.dloss) wseed = a.dloss[j];
+      if (a.use_scale) wseed *= a.scaler->scale;
+    }
+    const float inv = (TRAIN && a.use_scale) ? 1.0f / a.scaler->scale : 1.0f;
+    float* dst = a.partial + (size_t)tile * a.p_stride;
+    // the tile's partial as a buffer: lane offsets in one VGPR, block offsets as constants
+    const __amdgpu_buffer_rsrc_t prs =
+        __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, n_params_of(H) * 4, 0x00020000);
+
+    f32x4 accW[RMW ? 1 : kLayers][RB][NBH];  // this wave's rows of dW_l (16x16 blocks)
+    float accDb[kLayers][RB];                // lane sums of this wave's rows of db_l
+    f32x4 accWh[HB];                         // BF16: this wave's columns of the output layer's dW
+    float accH[kOut];                        // FP32: the same, one feature per lane group
+    float accDbH[kOut];
+    if constexpr (TRAIN) {
+      if constexpr (!RMW) {
+#pragma unroll
+        for (int l = 0; l < kLayers; ++l)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NBH; ++cb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) accW[l][rb][cb][i] = 0.f;
+      }
+#pragma unroll
+      for (int l = 0; l < kLayers; ++l)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) accDb[l][rb] = 0.f;
+#pragma unroll
+      for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) accWh[bb][i] = 0.f;
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) { accH[c] = 0.f; accDbH[c] = 0.f; }
+    }
+    float wave_loss = 0.f;
+    int bad = 0;
+
+    unsigned char* dzt = scr0 + wave * C.scratch_wave;
+    unsigned char* dtile = dzt + TB;
+    unsigned char* htile = dtile + TT;
+    const int nrays = ray_hi - ray_lo;
+    const int nsub = (nrays + rpw - 1) / rpw;
+    const int rounds = (nsub + 3) / 4;
+
+    // Every wave runs every round (a wave without a sub-tile carries zero seeds), since the
+    // weight-gradient products of a round read all four waves' staging tiles.
+    for (int rd = 0; rd < rounds; ++rd) {
+      asm volatile("" ::: "memory");
+      const int sub = rd * 4 + wave;
+      const int r0 = ray_lo + sub * rpw;
+      const int nr = (sub < nsub) ? min(rpw, ray_hi - r0) : 0;
+      const int nslots = nr * S;
+
+      auto point = [&](int p, float xt[3]) {
+        const int slot = 32 * p + n;
+        xt[0] = xt[1] = xt[2] = 0.f;
+        if (slot < nslots) {
+          const int ray = r0 + slot / S;
+          const double tt = (double)a.t[(size_t)r0 * S + slot];
+          const float* o3 = a.rays_o + 3 * (size_t)ray;
+          const float* d3 = a.rays_d + 3 * (size_t)ray;
+          xt[0] = (float)(((double)o3[0] + tt * (double)d3[0] - cx) * inv_s);
+          xt[1] = (float)(((double)o3[1] + tt * (double)d3[1] - cy) * inv_s);
+          xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - cz) * inv_s);
+        }
+      };
+      float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
+      if (nslots > 0) {
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+          Acts<H, BF> tmp;
+          float xt[3], z[kOut];
+          point(p, xt);
+          forward_pass<H, BF, true>(xt, wb, Bl, tmp, z);
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
+        }
+      }
+      float dzs[kOut];
+      render_subtile<TRAIN>(a, r0, nslots, wseed, zs, dzs, wave_loss);
+      if constexpr (!TRAIN) continue;
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
+
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+        const bool first = (rd == 0 && p == 0), last = (rd == rounds - 1 && p == 1);
+        Acts<H, BF> act;
+        {
+          float xt[3], z[kOut];
+          point(p, xt);
+          forward_pass<H, BF, false>(xt, wb, Bl, act, z);
+        }
+        float dz[kOut];
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) dz[c] = __shfl(dzs[c], 32 * p + n);
+        __syncthreads();  // every wave is done reading the staging tiles
+        if (hf == 0) {
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) {
+            if constexpr (BF) reinterpret_cast<__bf16*>(dzt)[c * 40 + n] = (__bf16)dz[c];
+            else reinterpret_cast<float*>(dzt)[n * kOut + c] = dz[c];
+          }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int f = mt * 32 + rowof(r, hf);
+            if constexpr (BF)
+              reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[kLayers][mt][r >> 3][r & 7];
+            else
+              reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[kLayers][mt][r];
+          }
+        __syncthreads();
+        // output layer: this wave's columns of dW over the four waves' samples
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) {
+          const unsigned char* dz2 = scr0 + w2 * C.scratch_wave;
+          const unsigned char* h2 = dz2 + TB + TT;
+          if constexpr (BF) {
+            bf16x8 da = {};
+            if (m16 < kOut)
+              da = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(dz2) + m16 * 40 + 8 * kg);
+#pragma unroll
+            for (int bb = 0; bb < HB; ++bb) {
+              const int b = wave * HB + bb;
+              const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
+                  reinterpret_cast<const __bf16*>(h2) + (b * 16 + m16) * 40 + 8 * kg);
+              accWh[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da, hb, accWh[bb], 0, 0, 0);
+            }
+          } else {
+            constexpr int G = 64 / FW, SG = 32 / G;
+            const int f = wave * FW + (lane % FW), g = lane / FW;
+#pragma unroll
+            for (int s2 = 0; s2 < SG; ++s2) {
+              const int s = g * SG + s2;
+              const float hv = reinterpret_cast<const float*>(h2)[s * (H + 4) + f];
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) accH[c] += reinterpret_cast<const float*>(dz2)[s * kOut + c] * hv;
+            }
+          }
+        }
+        // delta of the last hidden layer, own samples: (W_out^T dz) masked by ReLU'
+        Deltas<H, BF> dl;
+        if constexpr (BF) {
+          bf16x8 dzb = {};
+          if (hf == 0) {
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) dzb[c] = (__bf16)dz[c];
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            bf16x8 wa = {};
+            if constexpr (GW) {
+              const uint2 w4 = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(
+                  image_rsrc(wb, image_bytes(H, BF)), n * kOut * 2, L.whtb_off + mt * 32 * kOut * 2, 0));
+              if (hf == 0) {
+                wa[0] = __builtin_bit_cast(__bf16, (unsigned short)(w4.x & 0xffff));
+                wa[1] = __builtin_bit_cast(__bf16, (unsigned short)(w4.x >> 16));
+                wa[2] = __builtin_bit_cast(__bf16, (unsigned short)(w4.y & 0xffff));
+                wa[3] = __builtin_bit_cast(__bf16, (unsigned short)(w4.y >> 16));
+              }
+            } else if (hf == 0) {
+              const __bf16* wt = reinterpret_cast<const __bf16*>(wb + L.whtb_off) + (mt * 32 + n) * kOut;
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) wa[c] = wt[c];
+            }
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dzb, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float hv = (float)reinterpret_cast<const __bf16*>(htile)[(mt * 32 + rowof(r, hf)) * 40 + n];
+              dl.set(mt, r, (hv > 0.f) ? acc[r] : 0.f);
+            }
+          }
+        } else {
+          const float* Wh = reinterpret_cast<const float*>(wb + L.wh_off);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              float s = 0.f;
+#pragma unroll
+              for (int c = 0; c < kOut; ++c) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * dz[c];
+              const float hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mt * 32 + rowof(r, hf)];
+              dl.set(mt, r, (hv > 0.f) ? s : 0.f);
+            }
+        }
+#pragma unroll
+        for (int l = kLayers - 1; l >= 0; --l) {
+          const int K = (l == 0) ? kEnc : H;
+          const int KB = K / 32, NB = K / 16;
+          const int off = layer_param_off(H, l);
+          __syncthreads();  // every wave is done reading the staging tiles
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int f = mt * 32 + rowof(r, hf);
+              if constexpr (BF) reinterpret_cast<__bf16*>(dtile)[f * 40 + n] = dl.v[mt][r >> 3][r & 7];
+              else reinterpret_cast<float*>(dtile)[n * (H + 4) + f] = dl.v[mt][r];
+            }
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int f = kb * 32 + rowof(r, hf);
+              if constexpr (BF)
+                reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[l][kb][r >> 3][r & 7];
+              else
+                reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[l][kb][r];
+            }
+          // this wave's rows of dW_l: D lane holds row 16 rb + 4 kg + i, column 16 cb + m16
+          f32x4 acc[RB][NBH];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NBH; ++cb) {
+              if (cb >= NB) continue;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if constexpr (RMW) {
+                  // row wave RW + 16 rb + 4 kg + i, column 16 cb + m16
+                  const int lo = ((wave * RW + 4 * kg) * K + m16) * 4;
+                  const int co = (off + (rb * 16 + i) * K + cb * 16) * 4;
+                  acc[rb][cb][i] =
+                      first ? 0.f : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(prs, lo, co, 0));
+                } else {
+                  acc[rb][cb][i] = accW[RMW ? 0 : l][rb][cb][i];
+                }
+              }
+            }
+          __syncthreads();  // every wave's tiles are staged
+#pragma unroll
+          for (int w2 = 0; w2 < 4; ++w2) {
+            const unsigned char* d2 = scr0 + w2 * C.scratch_wave + TB;
+            const unsigned char* h2 = d2 + TT;
+            if constexpr (BF) {
+              bf16x8 da[RB];
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb) {
+                da[rb] = *reinterpret_cast<const bf16x8*>(
+                    reinterpret_cast<const __bf16*>(d2) + (wave * RW + rb * 16 + m16) * 40 + 8 * kg);
+                float s = 0.f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s += (float)da[rb][e];
+                accDb[l][rb] += s;
+              }
+#pragma unroll
+              for (int cb = 0; cb < NBH; ++cb) {
+                if (cb >= NB) continue;
+                const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
+                    reinterpret_cast<const __bf16*>(h2) + (cb * 16 + m16) * 40 + 8 * kg);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                  acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da[rb], hb, acc[rb][cb], 0, 0, 0);
+              }
+            } else {
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk) {
+                const int s = 4 * kk + kg;
+                float da[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                  da[rb] = reinterpret_cast<const float*>(d2)[s * (H + 4) + wave * RW + rb * 16 + m16];
+                  accDb[l][rb] += da[rb];
+                }
+#pragma unroll
+                for (int cb = 0; cb < NBH; ++cb) {
+                  if (cb >= NB) continue;
+                  const float hb = reinterpret_cast<const float*>(h2)[s * (H + 4) + cb * 16 + m16];
+#pragma unroll
+                  for (int rb = 0; rb < RB; ++rb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(da[rb], hb, acc[rb][cb], 0, 0, 0);
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NBH; ++cb) {
+              if (cb >= NB) continue;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if constexpr (RMW) {
+                  const int lo = ((wave * RW + 4 * kg) * K + m16) * 4;
+                  const int co = (off + (rb * 16 + i) * K + cb * 16) * 4;
+                  float v = acc[rb][cb][i];
+                  if (last) {
+                    v *= inv;
+                    bad |= !isfinite(v);
+                  }
+                  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), prs, lo, co, 0);
+                } else {
+                  accW[RMW ? 0 : l][rb][cb][i] = acc[rb][cb][i];
+                }
+              }
+            }
+          if (l == 0) break;
+          // delta_{l-1} = (W_l^T delta_l) masked by ReLU' of layer l-1, own samples
+          const int ws = L.w_stride[l];
+          Deltas<H, BF> nd;
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi) {
+            f32x16 acc2;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc2[r] = 0.f;
+            const int col = mi * 32 + colpos(n);
+#pragma unroll
+            for (int ko = 0; ko < MT; ++ko) {
+              if constexpr (BF) {
+                const __bf16* Wt = reinterpret_cast<const __bf16*>(wb + L.wt_off[l]) +
+                                   (mi * 32 + n) * (H + 8) + ko * 32 + 16 * hf;
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                  bf16x8 wa;
+                  if constexpr (GW)
+                    wa = img_b128(image_rsrc(wb, image_bytes(H, BF)), (n * (H + 8) + 16 * hf) * 2,
+                                  L.wt_off[l] + (mi * 32 * (H + 8) + ko * 32 + 8 * jj) * 2);
+                  else
+                    wa = *reinterpret_cast<const bf16x8*>(Wt + 8 * jj);
+                  acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dl.v[ko][jj], acc2, 0, 0, 0);
+                }
+              } else {
+                const float* W = reinterpret_cast<const float*>(wb + L.w_off[l]);
+#pragma unroll
+                for (int qq = 0; qq < 16; ++qq)
+                  acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(W[(ko * 32 + rowof(qq, hf)) * ws + col],
+                                                              dl.v[ko][qq], acc2, 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              float hv;
+              if constexpr (BF) hv = (float)reinterpret_cast<const __bf16*>(htile)[(mi * 32 + rowof(r, hf)) * 40 + n];
+              else hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mi * 32 + rowof(r, hf)];
+              nd.set(mi, r, (hv > 0.f) ? acc2[r] : 0.f);
+            }
+          }
+          dl = nd;
+        }
+      }
+    }  // rounds
+
+    // ---------------- tile result: loss and output-layer bias combined in wave order, every
+    // wave writes its own gradient slices
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) wave_loss += __shfl_xor(wave_loss, off);
+    if constexpr (TRAIN) {
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) accDbH[c] += __shfl_xor(accDbH[c], off);
+        if constexpr (!BF) {
+#pragma unroll
+          for (int off = FW; off < 64; off <<= 1) accH[c] += __shfl_xor(accH[c], off);
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < kLayers; ++l)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          accDb[l][rb] += __shfl_xor(accDb[l][rb], 16);
+          accDb[l][rb] += __shfl_xor(accDb[l][rb], 32);
+        }
+    }
+    float* lsum = reinterpret_cast<float*>(smem + C.loss_off);
+    int* any_bad = reinterpret_cast<int*>(smem + C.loss_off + 20);
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w && lane == 0) {
+        lsum[0] = (w == 0 ? 0.f : lsum[0]) + wave_loss;
+        if constexpr (TRAIN) {
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) lsum[1 + c] = (w == 0 ? 0.f : lsum[1 + c]) + accDbH[c];
+          if (w == 0) *any_bad = 0;
+        }
+      }
+      __syncthreads();
+    }
+    if constexpr (TRAIN) {
+      auto put = [&](int idx, float g) {
+        g *= inv;
+        bad |= !isfinite(g);
+        dst[idx] = g;
+      };
+#pragma unroll
+      for (int l = 0; l < kLayers; ++l) {
+        const int K = (l == 0) ? kEnc : H;
+        const int NB = K / 16;
+        const int off = layer_param_off(H, l);
+        if constexpr (!RMW) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NBH; ++cb) {
+              if (cb >= NB) continue;
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                put(off + (wave * RW + rb * 16 + 4 * kg + i) * K + cb * 16 + m16, accW[RMW ? 0 : l][rb][cb][i]);
+            }
+        }
+        if (kg == 0) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) put(off + H * K + wave * RW + rb * 16 + m16, accDb[l][rb]);
+        }
+      }
+      const int offh = layer_param_off(H, kLayers);
+      if constexpr (BF) {
+        if (lane < 16) {
+#pragma unroll
+          for (int bb = 0; bb < HB; ++bb)
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) put(offh + c * H + (wave * HB + bb) * 16 + lane, accWh[bb][c]);
+        }
+      } else if (lane < FW) {
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) put(offh + c * H + wave * FW + lane, accH[c]);
+      }
+      if (wave == 0 && lane < kOut) put(offh + kOut * H + lane, lsum[1 + lane]);
+      if (bad) *any_bad = 1;  // every writer stores the same value
+      __syncthreads();
+      if (tid == 0 && *any_bad) atomicOr(&a.flags[k], 1);
+    }
+    if (tid == 0) a.tile_loss[tile] = lsum[0];
+    __syncthreads();
+  }
+}
+
+// Weight images of wide objects for one step: block (x, j) stages a share of batch object j's
+// parameters (or of object `single`).
+template <int H, bool BF>
+__global__ void __launch_bounds__(256) k_stage_image(const StepArgs a_in, int single) {
+  StepArgs a = a_in;
+  read_batch(a);
+  int k = single;
+  if (single < 0) {
+    if ((int)blockIdx.y >= a.n_objects) return;
+    k = a.object_ids[blockIdx.y];
+  }
+  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
+  stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, a.wimage + (size_t)k * a.wimage_stride,
+                       blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Shape query of one object: forward only, 64 points per wave iteration.
 
 template <int H, bool BF>
 __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  constexpr LdsLayout L = lds_layout(H, BF, 1);
+  constexpr bool GW = weights_global(H);
+  constexpr int B_off = GW ? coop_layout(H, BF).B_off : lds_layout(H, BF, 1).B_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int n = lane & 31, hf = lane >> 5;
-  if (tid < 3 * kFeatures) reinterpret_cast<float*>(smem + L.B_off)[tid] = qa.B[tid];
-  stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem);
+  float* Bl = reinterpret_cast<float*>(smem + B_off);
+  if (tid < 3 * kFeatures) Bl[tid] = qa.B[tid];
+  const unsigned char* wb = smem;
+  if constexpr (GW) wb = qa.wimage + (size_t)qa.k * qa.wimage_stride;
+  else stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem, tid, blockDim.x);
   __syncthreads();
   const ObjDesc d = qa.desc[qa.k];
   for (int64_t chunk = (int64_t)blockIdx.x * nw + wave; chunk * kSlots < qa.n; chunk += (int64_t)gridDim.x * nw) {
@@ -786,7 +1402,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
       }
       Acts<H, BF> act;
       float z[kOut];
-      forward_pass<H, BF, true>(xt, smem, act, z);
+      forward_pass<H, BF, true>(xt, wb, Bl, act, z);
       if (i < qa.n && hf == 0) {
         qa.occ[i] = sigm(z[3]);
         if (qa.rgb) {
@@ -1147,16 +1763,33 @@ static hipError_t allow_lds(const void* fn, int bytes, int* allowed) {
 template <int H, bool BF, int MODE>
 static hipError_t launch_tiles_t(const StepArgs& a, int nwaves, int grid, hipStream_t s) {
   static int allowed = 0;
-  auto fn = k_step_tiles<H, BF, MODE>;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(fn), a.lds.total, &allowed);
+  const void* fn;
+  int bytes;
+  if constexpr (H == 32) {
+    fn = reinterpret_cast<const void*>(k_step_tiles<H, BF, MODE>);
+    bytes = lds_layout(H, BF, nwaves).total;
+  } else {
+    fn = reinterpret_cast<const void*>(k_step_coop<H, BF, MODE>);
+    bytes = coop_layout(H, BF).total;
+    nwaves = 4;
+  }
+  hipError_t e = allow_lds(fn, bytes, &allowed);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(nwaves * kWave), a.lds.total, s, a);
+  if constexpr (H == 32)
+    hipLaunchKernelGGL((k_step_tiles<H, BF, MODE>), dim3(grid), dim3(nwaves * kWave), bytes, s, a);
+  else
+    hipLaunchKernelGGL((k_step_coop<H, BF, MODE>), dim3(grid), dim3(nwaves * kWave), bytes, s, a);
   return hipGetLastError();
 }
 
 int tiles_supported(int H, bool bf16) {
-  (void)bf16;
-  return H == 32 || H == 64;
+  return H == 32 || H == 64 || (H == 128 && bf16);
+}
+
+int tile_waves(int H, int requested) { return H == 32 ? requested : 4; }
+
+int tile_lds_bytes(int H, bool bf16, int nwaves) {
+  return H == 32 ? lds_layout(H, bf16, nwaves).total : coop_layout(H, bf16).total;
 }
 
 hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,
@@ -1171,21 +1804,33 @@ hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwave
   VMAP_TILES(32, true)
   VMAP_TILES(64, false)
   VMAP_TILES(64, true)
+  VMAP_TILES(128, true)
 #undef VMAP_TILES
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_images(int H, bool bf16, const StepArgs& a, int single, hipStream_t s) {
+  if (!weights_global(H)) return hipSuccess;
+  if (H != 128 || !bf16 || !a.wimage) return hipErrorInvalidValue;
+  const int ny = single >= 0 ? 1 : a.n_objects;
+  if (ny <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_stage_image<128, true>), dim3(16, ny), dim3(256), 0, s, a, single);
+  return hipGetLastError();
 }
 
 template <int H, bool BF>
 static hipError_t launch_query_t(const QueryArgs& q, hipStream_t s) {
   static int allowed = 0;
   auto fn = k_query<H, BF>;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(fn), q.lds.total, &allowed);
+  const int bytes = weights_global(H) ? coop_layout(H, BF).B_off + 3 * kFeatures * 4
+                                      : lds_layout(H, BF, 1).B_off + 3 * kFeatures * 4;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(fn), bytes, &allowed);
   if (e != hipSuccess) return e;
   const int nw = 4;
   int64_t chunks = (q.n + kSlots - 1) / kSlots;
   int grid = (int)std::min<int64_t>((chunks + nw - 1) / nw, 2048);
   if (grid < 1) return hipSuccess;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(nw * kWave), q.lds.total, s, q);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(nw * kWave), bytes, s, q);
   return hipGetLastError();
 }
 
@@ -1194,6 +1839,7 @@ hipError_t launch_query(int H, bool bf16, const QueryArgs& q, hipStream_t s) {
   if (H == 32 && bf16) return launch_query_t<32, true>(q, s);
   if (H == 64 && !bf16) return launch_query_t<64, false>(q, s);
   if (H == 64 && bf16) return launch_query_t<64, true>(q, s);
+  if (H == 128 && bf16) return launch_query_t<128, true>(q, s);
   return hipErrorInvalidValue;
 }
 

@@ -25,9 +25,9 @@ import pytest
 
 import oracle
 import scenes
-from vmap_testlib import away_from_kinks, make_pair, relerr, remap_batch, tol
+from vmap_testlib import (BF16_VS_BF16_ORACLE, check_step, make_pair, relerr, remap_batch, report,
+                          same_state, scaled, snapshot, step_errors, subbatch, tol, away_from_kinks)
 
-BF16_VS_BF16_ORACLE = 2e-3
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -38,20 +38,9 @@ if not torch.cuda.is_available():  # collected on CPU hosts, never run there
 import paper_2302_01838_amd as vm  # noqa: E402
 
 
-def _report(name, **errs):
-    print(f"[parity] {name}: " + ", ".join(f"{k}={v:.3e}" for k, v in errs.items()), flush=True)
-
-
-def _scaled(scene, factor=10):
-    """The scene with every object's ray count divided by ``factor`` (at least 1)."""
-    sc = dataclasses.replace(scene, objects=[dataclasses.replace(o, n_rays=max(1, o.n_rays // factor))
-                                             for o in scene.objects])
-    return sc
-
-
 SCENES = {
     "tiny_k4": lambda: scenes.make_scene("tiny_k4"),
-    "k50_div10": lambda: _scaled(scenes.make_scene("k50_uneven"), 10),
+    "k50_div10": lambda: scaled(scenes.make_scene("k50_uneven"), 10),
 }
 
 
@@ -89,7 +78,7 @@ def test_query_parity(precision, n):
         o_ref, c_ref = oracle.query(st.theta, st.H, st.L, sc.B, st.centre, st.scale, pts)
         e1 = relerr(occ.cpu().numpy(), o_ref)
         e2 = relerr(rgb.cpu().numpy(), c_ref)
-        _report(f"query {precision} n={n} k={k}", occ=e1, rgb=e2)
+        report(f"query {precision} n={n} k={k}", occ=e1, rgb=e2)
         assert e1 <= tol(precision) and e2 <= tol(precision)
 
 
@@ -114,7 +103,7 @@ def test_forward_parity(precision, scene_name):
         worst["depth"] = max(worst["depth"], relerr(depth.cpu().numpy()[sl], rend["D"][sl]))
         worst["rgb"] = max(worst["rgb"], relerr(rgb.cpu().numpy()[sl], rend["C"][sl]))
         worst["occ"] = max(worst["occ"], relerr(occ.cpu().numpy()[sl], rend["O"][sl]))
-    _report(f"forward {precision} {scene_name}", **worst)
+    report(f"forward {precision} {scene_name}", **worst)
     for v in worst.values():
         assert v <= tol(precision)
     # rendering without targets gives the same renders, bit for bit
@@ -147,7 +136,7 @@ def test_backward_parity(precision, scene_name):
         if precision == "bf16":
             worst_b16 = max(worst_b16, relerr(grad[j, :P], g_b16[int(k)]))
         assert not np.any(grad[j, P:]), "padding of the gradient slot must stay zero"
-    _report(f"backward {precision} {scene_name} (near-kink rays dropped={dropped})",
+    report(f"backward {precision} {scene_name} (near-kink rays dropped={dropped})",
             grad_vs_fp64=worst, grad_vs_bf16_oracle=worst_b16)
     if precision == "fp32":
         assert worst <= 1e-5
@@ -157,81 +146,17 @@ def test_backward_parity(precision, scene_name):
 
 # ------------------------------------------------------------------------------------ full step
 
-def _step_errors(objs, states, batch, precision, B):
-    """One library step against the oracle on the batch without its near-kink rays. Returns
-    (errors vs FP64, errors vs the oracle's BF16 mode or None, sign-unstable gradient count,
-    oracle states after the step)."""
-    batch, dropped = away_from_kinks(states, batch, B,
-                                     rnd=oracle.bf16_round if precision == "bf16" else None)
-    print(f"[parity] near-kink rays dropped: {dropped}", flush=True)
-    db = vm.DeviceBatch(batch)
-    loss = objs.step(db)
-    torch.cuda.synchronize()
-    st = {k: v.copy() for k, v in states.items()}
-    l_ref, g_ref, _ = oracle.step(st, batch, B)
-    st16 = g16 = None
-    if precision == "bf16":
-        st16 = {k: v.copy() for k, v in states.items()}
-        _, g16, _ = oracle.step(st16, batch, B, rnd=oracle.bf16_round)
-    errs = dict(loss=0.0, theta=0.0, theta_stable=0.0, m=0.0, v=0.0, grad=0.0)
-    errs16 = dict(m=0.0, v=0.0, grad=0.0) if precision == "bf16" else None
-    unstable = 0
-    lr = objs.cfg.lr
-    for j, k in enumerate(batch["object_ids"]):
-        k = int(k)
-        errs["loss"] = max(errs["loss"], relerr(loss[j].item(), l_ref[j]))
-        th = objs.get_state(k, vm.STATE_PARAMS)
-        m = objs.get_state(k, vm.STATE_ADAM_M)
-        v = objs.get_state(k, vm.STATE_ADAM_V)
-        g = objs.get_state(k, vm.STATE_GRAD)
-        errs["theta"] = max(errs["theta"], relerr(th, st[k].theta))
-        errs["m"] = max(errs["m"], relerr(m, st[k].m))
-        errs["v"] = max(errs["v"], relerr(v, st[k].v))
-        errs["grad"] = max(errs["grad"], relerr(g, g_ref[k]))
-        # Adam's first step moves each parameter by about lr * sign(g). An element whose FP64
-        # gradient lies within 10x the largest elementwise gradient error of its object is
-        # "sign-unstable": its update direction is decided by rounding. Those elements are held
-        # to the Adam bound (at most 2 lr apart); all others to the tolerance.
-        gerr = np.max(np.abs(g.astype(np.float64) - g_ref[k]))
-        uns = np.abs(g_ref[k]) < 10.0 * gerr
-        if st[k].t == 1 and precision == "fp32":
-            unstable += int(np.sum(uns))
-            stable = ~uns
-            errs["theta_stable"] = max(errs["theta_stable"], relerr(th[stable], st[k].theta[stable]))
-            assert np.all(np.abs(th[uns] - st[k].theta[uns]) <= 2.0 * lr * (1 + 1e-5))
-        else:
-            errs["theta_stable"] = max(errs["theta_stable"], relerr(th, st[k].theta))
-        if errs16 is not None:
-            errs16["m"] = max(errs16["m"], relerr(m, st16[k].m))
-            errs16["v"] = max(errs16["v"], relerr(v, st16[k].v))
-            errs16["grad"] = max(errs16["grad"], relerr(g, g16[k]))
-        assert objs.get_state(k, vm.STATE_STEP) == st[k].t
-    return errs, errs16, unstable, st
-
-
-def _check_step(errs, errs16, precision):
-    if precision == "fp32":
-        for key, v in errs.items():
-            if key != "theta":  # theta: the sign-unstable elements are bounded separately
-                assert v <= 1e-5, key
-    else:
-        for key in ("loss", "theta"):
-            assert errs[key] <= 2e-2
-        for v in errs16.values():
-            assert v <= BF16_VS_BF16_ORACLE
-
-
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("scene_name", list(SCENES))
 def test_train_step_parity(precision, scene_name):
     sc = SCENES[scene_name]()
     objs, states = make_pair(sc, precision)
     batch = scenes.make_batch(sc, 0)
-    errs, errs16, unstable, _ = _step_errors(objs, states, batch, precision, sc.B)
-    _report(f"step {precision} {scene_name} (sign-unstable={unstable})", **errs)
+    errs, errs16, unstable, _ = step_errors(objs, states, batch, precision, sc.B)
+    report(f"step {precision} {scene_name} (sign-unstable={unstable})", **errs)
     if errs16:
-        _report(f"step {precision} {scene_name} vs bf16 oracle", **errs16)
-    _check_step(errs, errs16, precision)
+        report(f"step {precision} {scene_name} vs bf16 oracle", **errs16)
+    check_step(errs, errs16, precision)
 
 
 def test_full_size_k50_fp32_step():
@@ -240,19 +165,19 @@ def test_full_size_k50_fp32_step():
     sc = scenes.make_scene("k50_uneven")
     objs, states = make_pair(sc, "fp32")
     batch = scenes.make_batch(sc, 3)
-    errs, _, unstable, _ = _step_errors(objs, states, batch, "fp32", sc.B)
-    _report(f"step fp32 k50 full (sign-unstable={unstable})", **errs)
-    _check_step(errs, None, "fp32")
+    errs, _, unstable, _ = step_errors(objs, states, batch, "fp32", sc.B)
+    report(f"step fp32 k50 full (sign-unstable={unstable})", **errs)
+    check_step(errs, None, "fp32")
 
 
 def test_full_size_k50_bf16_step():
     sc = scenes.make_scene("k50_uneven")
     objs, states = make_pair(sc, "bf16")
     batch = scenes.make_batch(sc, 3)
-    errs, errs16, unstable, _ = _step_errors(objs, states, batch, "bf16", sc.B)
-    _report("step bf16 k50 full", **errs)
-    _report("step bf16 k50 full vs bf16 oracle", **errs16)
-    _check_step(errs, errs16, "bf16")
+    errs, errs16, unstable, _ = step_errors(objs, states, batch, "bf16", sc.B)
+    report("step bf16 k50 full", **errs)
+    report("step bf16 k50 full vs bf16 oracle", **errs16)
+    check_step(errs, errs16, "bf16")
 
 
 # ------------------------------------------------------------------------------------ edge cases
@@ -263,9 +188,9 @@ def test_samples_per_ray_edges(S):
     sc = dataclasses.replace(base, S=S, n_strat=max(1, S // 2))
     objs, states = make_pair(sc, "fp32")
     batch = scenes.make_batch(sc, 0, n_rays={0: 1, 1: 7, 2: 64, 3: 33})
-    errs, _, unstable, _ = _step_errors(objs, states, batch, "fp32", sc.B)
-    _report(f"step fp32 S={S}", **errs)
-    _check_step(errs, None, "fp32")
+    errs, _, unstable, _ = step_errors(objs, states, batch, "fp32", sc.B)
+    report(f"step fp32 S={S}", **errs)
+    check_step(errs, None, "fp32")
 
 
 def test_empty_batch_is_a_no_op():
@@ -281,70 +206,50 @@ def test_empty_batch_is_a_no_op():
 
 # ------------------------------------------------------------------------------------ invariants
 
-def _snapshot(objs, ids):
-    return {k: [objs.get_state(k, w) for w in (vm.STATE_PARAMS, vm.STATE_ADAM_M, vm.STATE_ADAM_V)]
-            + [objs.get_state(k, vm.STATE_STEP)] for k in ids}
-
-
-def _same(a, b):
-    return all(np.array_equal(x, y) for x, y in zip(a, b))
-
-
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_bitwise_invariants(precision):
-    sc = _scaled(scenes.make_scene("k50_uneven"), 10)
+    sc = scaled(scenes.make_scene("k50_uneven"), 10)
     ids = list(range(6))
     batch = scenes.make_batch(sc, 0, object_ids=ids)
-    sub = lambda js: _subbatch(batch, js)
+    sub = lambda js: subbatch(batch, js)
     # reference: one step of all six objects
     objs, _ = make_pair(sc, precision, ids=ids)
     l_all = objs.step(vm.DeviceBatch(batch)).cpu().numpy()
-    ref = _snapshot(objs, ids)
+    ref = snapshot(objs, ids)
     # determinism: the same step again from the same start
     objs2, _ = make_pair(sc, precision, ids=ids)
     l2 = objs2.step(vm.DeviceBatch(batch)).cpu().numpy()
     assert np.array_equal(l2, l_all)
-    s2 = _snapshot(objs2, ids)
-    assert all(_same(ref[k], s2[k]) for k in ids)
+    s2 = snapshot(objs2, ids)
+    assert all(same_state(ref[k], s2[k]) for k in ids)
     # permutation of the batch's objects permutes the results
     perm = [3, 0, 5, 1, 4, 2]
     objs3, _ = make_pair(sc, precision, ids=ids)
     l3 = objs3.step(vm.DeviceBatch(sub(perm))).cpu().numpy()
     assert np.array_equal(l3, l_all[perm])
-    s3 = _snapshot(objs3, ids)
-    assert all(_same(ref[k], s3[k]) for k in ids)
+    s3 = snapshot(objs3, ids)
+    assert all(same_state(ref[k], s3[k]) for k in ids)
     # batch split: {0,1,2} then {3,4,5}
     objs4, _ = make_pair(sc, precision, ids=ids)
     la = objs4.step(vm.DeviceBatch(sub([0, 1, 2]))).cpu().numpy()
     lb = objs4.step(vm.DeviceBatch(sub([3, 4, 5]))).cpu().numpy()
     assert np.array_equal(np.concatenate([la, lb]), l_all)
-    s4 = _snapshot(objs4, ids)
-    assert all(_same(ref[k], s4[k]) for k in ids)
+    s4 = snapshot(objs4, ids)
+    assert all(same_state(ref[k], s4[k]) for k in ids)
     # zero rays: object 2 is paused, the others are unaffected
     objs5, _ = make_pair(sc, precision, ids=ids)
-    before = _snapshot(objs5, [2])[2]
+    before = snapshot(objs5, [2])[2]
     zb = scenes.make_batch(sc, 0, object_ids=ids, n_rays={2: 0})
     l5 = objs5.step(vm.DeviceBatch(zb)).cpu().numpy()
     assert l5[2] == 0.0
-    s5 = _snapshot(objs5, ids)
-    assert _same(before, s5[2]) and s5[2][3] == 0
+    s5 = snapshot(objs5, ids)
+    assert same_state(before, s5[2]) and s5[2][3] == 0
     for k in (0, 1, 3, 4, 5):
-        assert _same(ref[k], s5[k])
-
-
-def _subbatch(batch, js):
-    offs = batch["ray_offsets"]
-    rows = np.concatenate([np.arange(offs[j], offs[j + 1]) for j in js]).astype(np.int64)
-    counts = [offs[j + 1] - offs[j] for j in js]
-    out = {k: batch[k][rows] for k in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
-    out["object_ids"] = batch["object_ids"][list(js)]
-    out["ray_offsets"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
-    out["S"] = batch["S"]
-    return out
+        assert same_state(ref[k], s5[k])
 
 
 def test_graph_replay_matches_plain_launches():
-    sc = _scaled(scenes.make_scene("k50_uneven"), 10)
+    sc = scaled(scenes.make_scene("k50_uneven"), 10)
     batch = scenes.make_batch(sc, 0)
     db = vm.DeviceBatch(batch)
     objs, _ = make_pair(sc, "bf16")
@@ -399,9 +304,9 @@ def test_launch_shapes(rpt, waves, grid):
     objs, states = make_pair(sc, "fp32", rays_per_tile=rpt)
     objs.set_launch(waves, grid)
     batch = scenes.make_batch(sc, 0)
-    errs, _, unstable, _ = _step_errors(objs, states, batch, "fp32", sc.B)
-    _report(f"step fp32 rays_per_tile={rpt} waves={waves} grid={grid}", **errs)
-    _check_step(errs, None, "fp32")
+    errs, _, unstable, _ = step_errors(objs, states, batch, "fp32", sc.B)
+    report(f"step fp32 rays_per_tile={rpt} waves={waves} grid={grid}", **errs)
+    check_step(errs, None, "fp32")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -423,7 +328,7 @@ def test_grid_size_does_not_change_results(precision):
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_graph_replay_over_changing_batches(precision):
     """One captured graph serves batches of the same shape in different buffers."""
-    sc = _scaled(scenes.make_scene("k50_uneven"), 10)
+    sc = scaled(scenes.make_scene("k50_uneven"), 10)
     dbs = [vm.DeviceBatch(scenes.make_batch(sc, step)) for step in range(4)]
     objs, _ = make_pair(sc, precision)
     objs_g, _ = make_pair(sc, precision)
@@ -455,4 +360,4 @@ def test_depth_guided_sampling_matches_oracle(S, n_strat):
     ref = oracle.depth_guided_samples(tn, tf, depth, S, n_strat, 0.03, seed)
     assert np.all(np.diff(t, axis=1) >= 0)
     np.testing.assert_allclose(t, ref, rtol=2.5e-7, atol=0)
-    _report(f"sampling S={S} n_strat={n_strat}", max_rel=float(np.max(np.abs(t - ref) / np.abs(ref))))
+    report(f"sampling S={S} n_strat={n_strat}", max_rel=float(np.max(np.abs(t - ref) / np.abs(ref))))

@@ -45,6 +45,21 @@ def test_sizes_and_params(lib):
     assert lib.vmap_object_params(ctypes.byref(cfg64), 64) == 14852
 
 
+def test_wide_models_bf16_only(lib):
+    """Hidden 128 (the background model's width) runs in BF16 only; its weight images add
+    max_objects x image bytes to the workspace."""
+    c16 = vm.default_config(max_objects=8, hidden=32, max_rays=4096, max_samples_per_ray=20,
+                            precision=vm.VMAP_BF16)
+    small = lib.vmap_workspace_bytes(ctypes.byref(c16))
+    c16.max_hidden = 128
+    assert lib.vmap_object_params(ctypes.byref(c16), 128) == 54276
+    wide = lib.vmap_workspace_bytes(ctypes.byref(c16))
+    assert wide > small + 8 * 200_000
+    c32 = vm.default_config(max_objects=8, hidden=32, max_hidden=128)
+    assert lib.vmap_state_bytes(ctypes.byref(c32)) == 0
+    assert lib.vmap_object_params(ctypes.byref(vm.default_config(hidden=32)), 128) == 0
+
+
 @pytest.mark.parametrize("field,value", [("max_objects", 0), ("n_features", 8),
                                          ("n_hidden_layers", 3), ("hidden", 48),
                                          ("max_samples_per_ray", 65), ("precision", 7),
