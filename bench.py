@@ -28,10 +28,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "k50_uneven"
-# Algorithmic FLOPs per sample of one training step at H = 32, four hidden layers, E = 32, four
-# outputs: forward 4,224 MACs, backward 7,424 MACs (all weight gradients, input gradients of
-# layers 2..5), 2 FLOPs per MAC. No recomputation, padding or encoding/rendering work counted.
-FLOP_PER_SAMPLE_H32 = 2 * (4224 + 7424)
+WORKLOAD_TEXT = {
+    "k50_uneven": "K=50 objects, rays/object U[60,600], 20 samples/ray, hidden 32, 4 hidden "
+                  "layers, Adam lr 1e-3",
+    "room50_background": "K=50 objects (hidden 32, rays lognormal(5,1) in [16,4096]) + hidden-128 "
+                         "background (1,200 rays), 20 samples/ray, 6x6x3 m room, BF16",
+    "stress_k256": "K=256 objects, hidden 64, rays/object U[256,4096], 32 samples/ray, "
+                   "10x10x3 m room, all objects joined, BF16",
+}
+
+
+def flop_per_sample(H: int) -> int:
+    """Algorithmic FLOPs of one training step per sample for width H, four hidden layers, E = 32,
+    four outputs: forward 32H + 3H^2 + 4H MACs; backward all weight gradients (the same count)
+    plus input gradients of layers 2..5 (3H^2 + 4H); 2 FLOPs per MAC. H = 32: 23,296. No
+    recomputation, padding, encoding or rendering work counted."""
+    fwd = 32 * H + 3 * H * H + 4 * H
+    return 2 * (fwd + fwd + 3 * H * H + 4 * H)
+
+
+FLOP_PER_SAMPLE_H32 = flop_per_sample(32)
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}
 
 
@@ -39,16 +55,31 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def first_full_step(scene):
+    """First step at which every object of the scene has joined."""
+    return max(o.join_step for o in scene.objects)
+
+
 def gen_batches(scene, n):
     import scenes
-    return [scenes.make_batch(scene, step) for step in range(n)]
+    s0 = first_full_step(scene)
+    return [scenes.make_batch(scene, s0 + step) for step in range(n)]
+
+
+def batch_flops(scene, db) -> float:
+    """Algorithmic FLOPs of one step over a device batch (per-object widths)."""
+    offs = np.asarray(db.ray_offsets)
+    ids = np.asarray(db.object_ids)
+    return float(sum(flop_per_sample(scene.objects[int(k)].hidden) * int(offs[j + 1] - offs[j]) * db.S
+                     for j, k in enumerate(ids)))
 
 
 def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
     import torch
     import paper_2302_01838_amd as vm
     nrays = max(db.n_rays for db in dev_batches)
-    objs = vm.ObjectSet(max_objects=scene.n_objects, B=scene.B, hidden=32, precision=precision,
+    objs = vm.ObjectSet(max_objects=scene.n_objects, B=scene.B, hidden=scene.objects[0].hidden,
+                        max_hidden=max(o.hidden for o in scene.objects), precision=precision,
                         max_rays=nrays, max_samples_per_ray=scene.S)
     for ob in scene.objects:
         objs.add(ob.norm_centre, ob.norm_scale, hidden=ob.hidden, seed=ob.seed)
@@ -79,6 +110,8 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
     torch.cuda.synchronize()
     k_ms, k_n = objs.kernel_timing(0)
     k_samples = statistics.mean(dev_batches[i % len(dev_batches)].n_samples for i in range(timing_steps))
+    k_flops = statistics.mean(batch_flops(scene, dev_batches[i % len(dev_batches)])
+                              for i in range(timing_steps))
     scale, skipped, err = objs.step_info()
     launch = {"tuned": bool(objs.tuned)}
     if objs.tuned:
@@ -99,6 +132,7 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
         kernel_ms=k_ms,
         kernel_launches=k_n,
         kernel_samples=k_samples,
+        kernel_flops=k_flops,
         launch=launch,
     )
 
@@ -167,7 +201,7 @@ def sweep_objects(counts, steps, precision, graph):
     return out
 
 
-def cpu_baseline(scene, batches, budget_s=15.0):
+def cpu_baseline(scene, batches, budget_s=15.0, workload=WORKLOAD):
     """The FP64 oracle (numpy; OpenBLAS threads as configured) on consecutive steps."""
     import oracle
     try:
@@ -179,19 +213,30 @@ def cpu_baseline(scene, batches, budget_s=15.0):
                                     o.norm_centre, o.norm_scale)
               for k, o in enumerate(scene.objects)}
     t0 = time.perf_counter()
-    n = samples = 0
-    while n < len(batches):
+    n = samples = obj_steps = 0
+    done = False
+    while n < len(batches) and not done:
         b = batches[n]
-        oracle.step(states, b, scene.B)
-        samples += b["t"].size
+        offs = b["ray_offsets"]
+        for j, k in enumerate(b["object_ids"]):
+            sl = slice(offs[j], offs[j + 1])
+            sub = {f: b[f][sl] for f in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
+            sub["object_ids"] = b["object_ids"][j:j + 1]
+            sub["ray_offsets"] = np.array([0, offs[j + 1] - offs[j]], dtype=np.int32)
+            sub["S"] = b["S"]
+            oracle.step(states, sub, scene.B)
+            samples += sub["t"].size
+            obj_steps += int(offs[j + 1] > offs[j])
+            if time.perf_counter() - t0 > budget_s:
+                done = True
+                break
         n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
     dt = time.perf_counter() - t0
     return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
-                sample=f"{n} consecutive training steps of the {WORKLOAD} workload "
-                       f"({samples} samples) from the initial models, FP64 numpy",
-                seconds=dt, object_steps_per_s=n * scene.n_objects / dt)
+                sample=f"{obj_steps} object-steps ({samples} samples) of the {workload} workload, "
+                       f"objects in batch order over consecutive steps from the initial models, "
+                       f"FP64 numpy",
+                seconds=dt, object_steps_per_s=obj_steps / dt)
 
 
 def main():
@@ -203,7 +248,10 @@ def main():
     ap.add_argument("--distinct-batches", type=int, default=0,
                     help="distinct pre-generated batches (default: warmup + steps)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated precisions (default fp32,bf16; bf16 with hidden 128)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
+                    help="k50_uneven is the headline workload; the others are reported in the docs")
     ap.add_argument("--sweep-objects", type=int, nargs="*", default=None,
                     help="only run the vectorised-vs-sequential sweep over these object counts")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -219,6 +267,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 5}), flush=True)
         return
+    if args.forms is None:
+        args.forms = "bf16" if args.workload != WORKLOAD else "fp32,bf16"
     if args.sweep_objects is not None:
         counts = args.sweep_objects or [1, 10, 20, 30, 40, 50, 100, 150, 200]
         res = sweep_objects(counts, max(1, min(args.steps, 50)), args.forms.split(",")[-1],
@@ -238,9 +288,9 @@ def main():
     import paper_2302_01838_amd as vm
 
     vm.load_library()
-    scene = scenes.make_scene(WORKLOAD)
+    scene = scenes.make_scene(args.workload)
     n_batches = args.distinct_batches or (args.warmup + args.steps)
-    log(f"generating {n_batches} batches of {WORKLOAD}")
+    log(f"generating {n_batches} batches of {args.workload}")
     batches = gen_batches(scene, n_batches)
     dev_batches = [vm.DeviceBatch(b) for b in batches]
     torch.cuda.synchronize()
@@ -260,14 +310,14 @@ def main():
     if "bf16" in forms and "fp32" in forms:
         matched = abs(forms["bf16"]["final_loss"] - forms["fp32"]["final_loss"]) <= \
             2e-2 * abs(forms["fp32"]["final_loss"])
-    flops = FLOP_PER_SAMPLE_H32 * head["kernel_samples"]
+    flops = head["kernel_flops"]
     achieved = flops / (head["kernel_ms"] * 1e-3) if head["kernel_ms"] > 0 else 0.0
     roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK[prec], traffic=None,
-                    kernel="k_step_tiles (fused encode+MLP+render+loss+backward)",
+                    kernel="tile kernels (fused encode+MLP+render+loss+backward)",
                     kernel_avg_ms=head["kernel_ms"], flop_per_launch=flops)
     log(f"cpu baseline: oracle for up to {args.cpu_budget:.0f} s")
-    cpu = cpu_baseline(scene, batches, args.cpu_budget)
+    cpu = cpu_baseline(scene, batches, args.cpu_budget, args.workload)
     out = {
         "metric": "object-steps/s and ray-samples/s at K=50, BF16 vs FP32, at matched final loss",
         "value": head["ray_samples_per_s"],
@@ -281,8 +331,7 @@ def main():
         "vs_baseline": None,
         "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": "K=50 objects, rays/object U[60,600], 20 samples/ray, hidden 32, "
-                               "4 hidden layers, Adam lr 1e-3",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "objects": scene.n_objects, "samples_per_step": dev_batches[0].n_samples,
                    "graph": bool(args.graph), "parallelism": "single GPU",
                    "launch": {k: v for k, v in head.get("launch", {}).items()}},

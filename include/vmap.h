@@ -161,6 +161,28 @@ int vmap_train_step(vmap_ctx* ctx, const vmap_batch* batch, float* loss_out_dev,
 int vmap_render(vmap_ctx* ctx, const vmap_batch* batch, float* depth_out, float* rgb_out,
                 float* occ_out, void* stream);
 
+/*
+ * Scene rendering from the object models (Sec. 3.4, "Compositional Scene Rendering"): each of
+ * n_rays world-frame rays (device rays_o, rays_d [n_rays, 3], unit directions) is intersected
+ * with the bound [c - s, c + s]^3 of every listed object (object_ids, device [n_objects],
+ * registered ids) by the slab method; a ray that meets a bound after t_min is sampled at the
+ * midpoints of S equal parts of its [entry, exit] interval and rendered with that object's
+ * model (Eq. 3). Each ray then takes, among the objects it met, the one with the nearest
+ * rendered depth whose rendered occupancy is >= occ_threshold (equal depths keep the earlier
+ * listed object). Outputs (device): depth_out [n_rays] (0 where no object qualifies), and if not
+ * NULL rgb_out [n_rays, 3], occ_out [n_rays], id_out [n_rays] (object id or -1), n_pairs_out [1]
+ * (the number of (ray, object) pairs found). At most max_pairs pairs are rendered (0 <= max_pairs
+ * <= config.max_rays); pairs beyond it are dropped and bit 1 of the device error reported by
+ * vmap_step_info is set. scratch (device, 256-byte aligned, vmap_scene_scratch_bytes bytes,
+ * caller-owned) holds the pairs. Returns VMAP_EINVAL / VMAP_ECAPACITY for bad arguments.
+ */
+size_t vmap_scene_scratch_bytes(int32_t n_rays, int32_t n_objects, int32_t max_pairs, int32_t S);
+int vmap_render_scene(vmap_ctx* ctx, int32_t n_rays, const float* rays_o, const float* rays_d,
+                      int32_t n_objects, const int32_t* object_ids, int32_t S, float t_min,
+                      float occ_threshold, int32_t max_pairs, void* scratch, size_t scratch_bytes,
+                      float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                      int32_t* n_pairs_out, void* stream);
+
 /* Occupancy [n] and, if rgb_out is not NULL, colour [n, 3] of n world-frame points (device
  * [n, 3]) under object `object_id`'s model (shape query inside its bound, Sec. 3.4). */
 int vmap_query_occupancy(vmap_ctx* ctx, int32_t object_id, const float* pts_world_dev,
@@ -200,7 +222,8 @@ int vmap_set_state(vmap_ctx* ctx, int32_t object_id, int32_t which, const void* 
                    size_t bytes, void* stream);
 
 /* Loss scale, objects skipped by the last step (non-finite gradients) and the device error
- * flag (non-zero after a batch named an invalid object). Synchronises `stream`. */
+ * flags (bit 0: a batch named an invalid object; bit 1: a scene render found more pairs than
+ * its max_pairs). Sticky until the context is destroyed. Synchronises `stream`. */
 int vmap_step_info(vmap_ctx* ctx, float* loss_scale, int32_t* skipped, int32_t* device_error,
                    void* stream);
 

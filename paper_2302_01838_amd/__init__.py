@@ -82,6 +82,10 @@ EXPORTED = {
     "vmap_train_step": (ctypes.c_int, [_P, _BATCH, _P, _P]),
     "vmap_render": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P]),
     "vmap_query_occupancy": (ctypes.c_int, [_P, _I, _P, ctypes.c_int64, _P, _P, _P]),
+    "vmap_scene_scratch_bytes": (ctypes.c_size_t, [_I, _I, _I, _I]),
+    "vmap_render_scene": (ctypes.c_int, [_P, _I, _P, _P, _I, _P, _I, ctypes.c_float,
+                                         ctypes.c_float, _I, _P, ctypes.c_size_t, _P, _P, _P,
+                                         _P, _P, _P]),
     "vmap_sample_rays": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P, ctypes.c_float, ctypes.c_uint64,
                                         _P, _P]),
     "vmap_forward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P, _P]),
@@ -298,6 +302,37 @@ class ObjectSet:
                                          rgb.data_ptr() if R else None,
                                          occ.data_ptr() if R else None, _stream()))
         return depth, rgb, occ
+
+    def render_scene(self, rays_o, rays_d, object_ids=None, S: int = 32, t_min: float = 0.0,
+                     occ_threshold: float = 0.5, max_pairs: Optional[int] = None):
+        """Scene render from the object models (Sec. 3.4): per ray the nearest object (by
+        rendered depth) whose rendered occupancy reaches ``occ_threshold``. Returns depth [R],
+        rgb [R, 3], occupancy [R], object id [R] (-1: none) and the number of (ray, object)
+        pairs found (a device scalar)."""
+        torch = _torch()
+        f = lambda x: torch.as_tensor(x).to(device=self.device, dtype=torch.float32).contiguous()
+        ro, rd = f(rays_o), f(rays_d)
+        R = ro.shape[0]
+        if object_ids is None:
+            object_ids = [k for k in range(self.cfg.max_objects) if k in self.n_params]
+        ids = torch.as_tensor(np.asarray(object_ids, np.int32)).to(self.device)
+        n = int(ids.numel())
+        if max_pairs is None:
+            max_pairs = min(R * n, self.cfg.max_rays)
+        nbytes = self.lib.vmap_scene_scratch_bytes(R, n, max_pairs, S)
+        scratch = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=self.device)
+        base = (scratch.data_ptr() + 255) // 256 * 256
+        depth = torch.zeros(R, dtype=torch.float32, device=self.device)
+        rgb = torch.zeros(R, 3, dtype=torch.float32, device=self.device)
+        occ = torch.zeros(R, dtype=torch.float32, device=self.device)
+        kid = torch.full((R,), -1, dtype=torch.int32, device=self.device)
+        npairs = torch.zeros(1, dtype=torch.int32, device=self.device)
+        ptr = lambda t: t.data_ptr() if t.numel() else None
+        self._check(self.lib.vmap_render_scene(
+            self.ctx, R, ptr(ro), ptr(rd), n, ptr(ids), S, float(t_min), float(occ_threshold),
+            int(max_pairs), base, nbytes, ptr(depth), ptr(rgb), ptr(occ), ptr(kid), ptr(npairs),
+            _stream()))
+        return depth, rgb, occ, kid, npairs
 
     def query(self, k: int, pts):
         torch = _torch()

@@ -333,6 +333,28 @@ int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t
   return VMAP_OK;
 }
 
+struct SceneLayout {
+  size_t counts, offsets, map, pair_o, pair_d, pair_t, pair_depth, pair_rgb, pair_occ, bd, total;
+};
+
+SceneLayout scene_layout(int64_t n_rays, int64_t n_objects, int64_t max_pairs, int64_t S) {
+  SceneLayout L{};
+  const int64_t nblk = (n_rays + 255) / 256;
+  size_t off = 0;
+  L.counts = off; off = align256(off + (size_t)(n_objects * nblk) * 4);
+  L.offsets = off; off = align256(off + (size_t)(n_objects + 1) * 4);
+  L.map = off; off = align256(off + (size_t)(n_objects * n_rays) * 4);
+  L.pair_o = off; off = align256(off + (size_t)max_pairs * 12);
+  L.pair_d = off; off = align256(off + (size_t)max_pairs * 12);
+  L.pair_t = off; off = align256(off + (size_t)(max_pairs * S) * 4);
+  L.pair_depth = off; off = align256(off + (size_t)max_pairs * 4);
+  L.pair_rgb = off; off = align256(off + (size_t)max_pairs * 12);
+  L.pair_occ = off; off = align256(off + (size_t)max_pairs * 4);
+  L.bd = off; off = align256(off + sizeof(BatchDev));
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -564,6 +586,84 @@ int vmap_render(vmap_ctx* c, const vmap_batch* b, float* depth_out, float* rgb_o
   rb.mask = nullptr;
   b = &rb;
   return vmap_forward(c, b, nullptr, depth_out, rgb_out, occ_out, stream);
+}
+
+size_t vmap_scene_scratch_bytes(int32_t n_rays, int32_t n_objects, int32_t max_pairs, int32_t S) {
+  if (n_rays < 0 || n_objects < 0 || max_pairs < 0 || S < 1 || S > kSlots) return 0;
+  return scene_layout(n_rays, n_objects, max_pairs, S).total;
+}
+
+int vmap_render_scene(vmap_ctx* c, int32_t n_rays, const float* rays_o, const float* rays_d,
+                      int32_t n_objects, const int32_t* object_ids, int32_t S, float t_min,
+                      float occ_threshold, int32_t max_pairs, void* scratch, size_t scratch_bytes,
+                      float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                      int32_t* n_pairs_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  if (n_rays < 0) return c->fail(VMAP_EINVAL, "n_rays must be >= 0");
+  if (n_objects < 0 || n_objects > c->cfg.max_objects)
+    return c->fail(VMAP_EINVAL, "n_objects must be in [0, max_objects]");
+  if (S < 1 || S > c->cfg.max_samples_per_ray)
+    return c->fail(VMAP_EINVAL, "S must be in [1, max_samples_per_ray]");
+  if (max_pairs < 0 || max_pairs > c->cfg.max_rays)
+    return c->fail(VMAP_ECAPACITY, "max_pairs must be in [0, max_rays]");
+  if (!std::isfinite(t_min) || !std::isfinite(occ_threshold))
+    return c->fail(VMAP_EINVAL, "t_min and occ_threshold must be finite");
+  if (n_rays == 0 || n_objects == 0) return VMAP_OK;
+  if (!rays_o || !rays_d || !object_ids || !scratch || !depth_out)
+    return c->fail(VMAP_EINVAL, "rays_o, rays_d, object_ids, scratch and depth_out must not be NULL");
+  if ((uintptr_t)scratch & 255) return c->fail(VMAP_EINVAL, "scratch must be 256-byte aligned");
+  if ((int64_t)n_rays * n_objects > ((int64_t)1 << 31) - 1)
+    return c->fail(VMAP_ECAPACITY, "n_rays * n_objects must stay below 2^31");
+  const SceneLayout L = scene_layout(n_rays, n_objects, max_pairs, S);
+  if (scratch_bytes < L.total) return c->fail(VMAP_ECAPACITY, "scratch smaller than vmap_scene_scratch_bytes");
+  unsigned char* sc = reinterpret_cast<unsigned char*>(scratch);
+  SceneArgs a{};
+  a.n_rays = n_rays;
+  a.n_objects = n_objects;
+  a.S = S;
+  a.max_objects = c->cfg.max_objects;
+  a.max_pairs = max_pairs;
+  a.occ_threshold = occ_threshold;
+  a.t_min = (double)t_min;
+  a.rays_o = rays_o;
+  a.rays_d = rays_d;
+  a.object_ids = object_ids;
+  a.desc = c->desc();
+  a.scaler = c->scaler();
+  a.counts = reinterpret_cast<int32_t*>(sc + L.counts);
+  a.ray_offsets = reinterpret_cast<int32_t*>(sc + L.offsets);
+  a.pair_map = reinterpret_cast<int32_t*>(sc + L.map);
+  a.pair_o = reinterpret_cast<float*>(sc + L.pair_o);
+  a.pair_d = reinterpret_cast<float*>(sc + L.pair_d);
+  a.pair_t = reinterpret_cast<float*>(sc + L.pair_t);
+  a.pair_depth = reinterpret_cast<float*>(sc + L.pair_depth);
+  a.pair_rgb = reinterpret_cast<float*>(sc + L.pair_rgb);
+  a.pair_occ = reinterpret_cast<float*>(sc + L.pair_occ);
+  a.bd = reinterpret_cast<BatchDev*>(sc + L.bd);
+  a.n_pairs_out = n_pairs_out;
+  a.depth_out = depth_out;
+  a.rgb_out = rgb_out;
+  a.occ_out = occ_out;
+  a.id_out = id_out;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_scene(0, a, s);
+  if (e != hipSuccess) return c->hip_fail(e, "scene pair launch");
+  if (max_pairs > 0) {
+    // the pairs as a batch: shape bounds on the host, contents from the device descriptor
+    vmap_batch hb{};
+    hb.n_objects = n_objects;
+    hb.n_rays_total = max_pairs;
+    hb.samples_per_ray = S;
+    hb.object_ids = object_ids;
+    hb.ray_offsets = a.ray_offsets;
+    e = enqueue_worklist(c, &hb, s, a.bd);
+    if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
+    int rc = enqueue_tiles(c, &hb, MODE_FWD, nullptr, a.pair_depth, a.pair_rgb, a.pair_occ, s, false, a.bd);
+    if (rc) return rc;
+  }
+  e = launch_scene(1, a, s);
+  if (e != hipSuccess) return c->hip_fail(e, "scene composite launch");
+  return VMAP_OK;
 }
 
 int vmap_backward(vmap_ctx* c, const vmap_batch* b, const float* dloss, float* grad_out, void* stream) {

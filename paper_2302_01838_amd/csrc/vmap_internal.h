@@ -240,6 +240,39 @@ struct OptArgs {
   const BatchDev* bd;         // if not NULL, n_objects, ids, offs and loss_out come from here
 };
 
+// Scene rendering (Sec. 3.4): rays against the bounds of a list of objects.
+struct SceneArgs {
+  int n_rays;
+  int n_objects;
+  int S;
+  int max_objects;
+  int max_pairs;
+  float occ_threshold;
+  double t_min;
+  const float* rays_o;       // [n_rays][3]
+  const float* rays_d;
+  const int32_t* object_ids; // [n_objects] (device)
+  const ObjDesc* desc;
+  ScalerState* scaler;
+  // scratch
+  int32_t* counts;           // [n_objects][blocks] hit counts, then their exclusive scan
+  int32_t* ray_offsets;      // [n_objects + 1] pairs per object (CSR)
+  int32_t* pair_map;         // [n_objects][n_rays] pair index or -1
+  float* pair_o;             // [max_pairs][3]
+  float* pair_d;
+  float* pair_t;             // [max_pairs][S]
+  float* pair_depth;         // [max_pairs] object renders of the pairs
+  float* pair_rgb;           // [max_pairs][3]
+  float* pair_occ;           // [max_pairs]
+  BatchDev* bd;              // the pairs as a batch
+  int32_t* n_pairs_out;      // optional: pairs found (device)
+  // outputs
+  float* depth_out;
+  float* rgb_out;
+  float* occ_out;
+  int32_t* id_out;
+};
+
 // Kernel launchers (vmap_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
@@ -260,6 +293,8 @@ hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, co
                          const float* depth, float sigma, uint64_t seed, float* t_out,
                          hipStream_t s);
 int tiles_supported(int H, bool bf16);
+// phase 0: pairs (count, scan, fill); phase 1: per-ray composite
+hipError_t launch_scene(int phase, const SceneArgs& a, hipStream_t s);
 int tile_lds_bytes(int H, bool bf16, int nwaves);
 int tile_waves(int H, int requested);
 // Weight images of wide objects: those of the batch (single < 0) or of object `single`.

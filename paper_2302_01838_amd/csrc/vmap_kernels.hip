@@ -170,11 +170,12 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem,
 
 // ---------------------------------------------------------------------------------------------
 // Forward of one 32-sample pass for the calling wave. xt: this lane's normalised point (the
-// sample of column n = lane & 31; both lane halves hold the same point); Bm: the encoding matrix. Fills the activations
+// sample of column n = lane & 31; both lane halves hold the same point); Bm: the encoding matrix.
+// ENC = false: the encoding is already in A.v[0] (kept from an earlier pass; xt unused). Fills the activations
 // and, with WITH_HEAD, returns the four output pre-activations z of sample n (valid in both lane
 // halves).
 
-template <int H, bool BF, bool WITH_HEAD>
+template <int H, bool BF, bool WITH_HEAD, bool ENC = true>
 __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
                                              const float* Bm, Acts<H, BF>& A, float z[4]) {
   constexpr int MT = H / 32;
@@ -185,8 +186,9 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
   const int lane = threadIdx.x & 63, n = lane & 31, hf = lane >> 5;
   // Gaussian Fourier features: register r of block 0 holds feature rowof(r, hf):
   // r = 0..3 sin(phi[4hf + r]), 4..7 sin(phi[8 + 4hf + r - 4]), 8..15 the cosines.
+  // Without ENC the caller has already placed them in A.v[0].
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < (ENC ? 2 : 0); ++g) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int f = 8 * g + 4 * hf + i;
@@ -535,6 +537,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         }
       };
       float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
+      // the encodings of both passes are kept for the recomputation in the backward
+      using Enc = typename std::remove_reference<decltype(Acts<H, BF>{}.v[0][0])>::type;
+      Enc enc0, enc1;
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
         Acts<H, BF> tmp;
@@ -543,6 +548,13 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         forward_pass<H, BF, true>(xt, smem, Bl, tmp, z);
 #pragma unroll
         for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
+        if constexpr (TRAIN) {
+#pragma unroll
+          for (int q = 0; q < (int)(sizeof(Enc) / sizeof(tmp.v[0][0][0])); ++q) {
+            if (p == 0) enc0[q] = tmp.v[0][0][q];
+            else enc1[q] = tmp.v[0][0][q];
+          }
+        }
       }
 
       float dzs[kOut];
@@ -558,10 +570,12 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
         Acts<H, BF> act;
-        {  // recompute the activations of this pass
-          float xt[3], z[kOut];
-          point(p, xt);
-          forward_pass<H, BF, false>(xt, smem, Bl, act, z);
+        {  // recompute the activations of this pass from its encoding
+#pragma unroll
+          for (int q = 0; q < (int)(sizeof(Enc) / sizeof(act.v[0][0][0])); ++q)
+            act.v[0][0][q] = (p == 0) ? enc0[q] : enc1[q];
+          float z[kOut];
+          forward_pass<H, BF, false, false>(nullptr, smem, Bl, act, z);
         }
         float dz[kOut];
 #pragma unroll
@@ -1732,6 +1746,191 @@ hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, co
   const int blocks = (int)((waves + 3) / 4);
   hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(256), 0, s, n_rays, S, P, n_strat, t_near,
                      t_far, depth, sigma, seed, t_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scene rendering from object models (Sec. 3.4): ray-box intersection per (ray, object), the
+// object renders of the rays that meet each bound, and a per-ray ranking by rendered depth.
+// The pairs are laid out as a batch (object-major, rays in image order), which the forward-mode
+// tile kernels render through a device batch descriptor; the host never reads the pair count.
+
+// Entry of ray (o, d) into the box c +- s after t_min, and exit; the ray meets the box iff
+// t1 > t0. Slab method in FP64 without contraction (the oracle's arithmetic).
+__device__ __forceinline__ void scene_slab(const float* o, const float* d, const ObjDesc& od,
+                                           double t_min, double& t0, double& t1) {
+  const double s = 1.0 / od.inv_scale;
+  t0 = -INFINITY;
+  t1 = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double lo = __dsub_rn(od.centre[a], s), hi = __dadd_rn(od.centre[a], s);
+    const double oa = (double)o[a], da = (double)d[a];
+    double near, far;
+    if (da == 0.0) {
+      const bool inside = oa >= lo && oa <= hi;
+      near = inside ? -INFINITY : INFINITY;
+      far = inside ? INFINITY : -INFINITY;
+    } else {
+      const double ta = __ddiv_rn(__dsub_rn(lo, oa), da), tb = __ddiv_rn(__dsub_rn(hi, oa), da);
+      near = fmin(ta, tb);
+      far = fmax(ta, tb);
+    }
+    t0 = fmax(t0, near);
+    t1 = fmin(t1, far);
+  }
+  t0 = fmax(t0, t_min);
+}
+
+__device__ __forceinline__ bool scene_pair_valid(const SceneArgs& a, int j, int& k) {
+  k = a.object_ids[j];
+  return k >= 0 && k < a.max_objects && a.desc[k].registered;
+}
+
+// Block (x, j): rays [256 x, 256 x + 256) against batch object j; writes the block's hit count.
+__global__ void __launch_bounds__(256) k_scene_count(const SceneArgs a) {
+  __shared__ int wsum[4];
+  const int j = blockIdx.y, r = blockIdx.x * 256 + threadIdx.x;
+  int k;
+  bool hit = false;
+  if (scene_pair_valid(a, j, k) && r < a.n_rays) {
+    double t0, t1;
+    scene_slab(a.rays_o + 3 * (size_t)r, a.rays_d + 3 * (size_t)r, a.desc[k], a.t_min, t0, t1);
+    hit = t1 > t0;
+  }
+  const unsigned long long m = __ballot(hit);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    a.counts[(size_t)j * gridDim.x + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// One block: exclusive scan of the counts (object-major), the batch's CSR offsets (clamped to
+// the pair capacity) and its device descriptor.
+__global__ void __launch_bounds__(1024) k_scene_scan(const SceneArgs a, int nblk) {
+  __shared__ int part[1024];
+  const int n = a.n_objects * nblk;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int i0 = min(tid * per, n), i1 = min(i0 + per, n);
+  int local = 0;
+  for (int i = i0; i < i1; ++i) local += a.counts[i];
+  part[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - local;
+  for (int i = i0; i < i1; ++i) {
+    const int c = a.counts[i];
+    a.counts[i] = run;
+    if (i % nblk == 0) a.ray_offsets[i / nblk] = min(run, a.max_pairs);
+    run += c;
+  }
+  if (tid == nt - 1) {
+    const int total = part[nt - 1];
+    a.ray_offsets[a.n_objects] = min(total, a.max_pairs);
+    if (a.n_pairs_out) *a.n_pairs_out = total;
+    if (total > a.max_pairs) atomicOr(&a.scaler->device_error, 2);
+    BatchDev* b = a.bd;
+    b->n_objects = a.n_objects;
+    b->S = a.S;
+    b->n_rays = min(total, a.max_pairs);
+    b->pad = 0;
+    b->object_ids = a.object_ids;
+    b->ray_offsets = a.ray_offsets;
+    b->rays_o = a.pair_o;
+    b->rays_d = a.pair_d;
+    b->t = a.pair_t;
+    b->depth = nullptr;
+    b->rgb = nullptr;
+    b->mask = nullptr;
+    b->loss_out = nullptr;
+  }
+}
+
+// Block (x, j): the pairs of its rays with batch object j, in ray order: ray, samples at the
+// midpoints of S equal parts of [t0, t1] (FP64, rounded once), and the (object, ray) -> pair map.
+__global__ void __launch_bounds__(256) k_scene_fill(const SceneArgs a) {
+  __shared__ int wsum[4];
+  const int j = blockIdx.y, r = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int k;
+  bool hit = false;
+  double t0 = 0.0, t1 = 0.0;
+  if (scene_pair_valid(a, j, k) && r < a.n_rays) {
+    scene_slab(a.rays_o + 3 * (size_t)r, a.rays_d + 3 * (size_t)r, a.desc[k], a.t_min, t0, t1);
+    hit = t1 > t0;
+  }
+  const unsigned long long m = __ballot(hit);
+  if (lane == 0) wsum[w] = __popcll(m);
+  __syncthreads();
+  int pos = a.counts[(size_t)j * gridDim.x + blockIdx.x];
+  for (int i = 0; i < w; ++i) pos += wsum[i];
+  pos += __popcll(m & ((1ull << lane) - 1ull));
+  if (r >= a.n_rays) return;
+  int p = -1;
+  if (hit && pos < a.max_pairs) {
+    p = pos;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.pair_o[3 * (size_t)p + c] = a.rays_o[3 * (size_t)r + c];
+      a.pair_d[3 * (size_t)p + c] = a.rays_d[3 * (size_t)r + c];
+    }
+    const double span = __dsub_rn(t1, t0);
+    for (int i = 0; i < a.S; ++i) {
+      const double frac = __ddiv_rn((double)i + 0.5, (double)a.S);
+      a.pair_t[(size_t)p * a.S + i] = (float)__dadd_rn(t0, __dmul_rn(frac, span));
+    }
+  }
+  a.pair_map[(size_t)j * a.n_rays + r] = p;
+}
+
+// Per ray: the nearest object (rendered depth) whose rendered occupancy reaches the threshold;
+// an equal depth keeps the earlier batch object.
+__global__ void __launch_bounds__(256) k_scene_composite(const SceneArgs a) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= a.n_rays) return;
+  float best = INFINITY, occ = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  int id = -1;
+  for (int j = 0; j < a.n_objects; ++j) {
+    const int p = a.pair_map[(size_t)j * a.n_rays + r];
+    if (p < 0) continue;
+    const float O = a.pair_occ[p], D = a.pair_depth[p];
+    if (O >= a.occ_threshold && D < best) {
+      best = D;
+      occ = O;
+      c0 = a.pair_rgb[3 * (size_t)p];
+      c1 = a.pair_rgb[3 * (size_t)p + 1];
+      c2 = a.pair_rgb[3 * (size_t)p + 2];
+      id = a.object_ids[j];
+    }
+  }
+  a.depth_out[r] = id >= 0 ? best : 0.f;
+  if (a.rgb_out) {
+    a.rgb_out[3 * (size_t)r] = c0;
+    a.rgb_out[3 * (size_t)r + 1] = c1;
+    a.rgb_out[3 * (size_t)r + 2] = c2;
+  }
+  if (a.occ_out) a.occ_out[r] = occ;
+  if (a.id_out) a.id_out[r] = id;
+}
+
+hipError_t launch_scene(int phase, const SceneArgs& a, hipStream_t s) {
+  if (a.n_rays <= 0 || a.n_objects <= 0) return hipSuccess;
+  const int nblk = (a.n_rays + 255) / 256;
+  switch (phase) {
+    case 0:
+      hipLaunchKernelGGL(k_scene_count, dim3(nblk, a.n_objects), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_scene_scan, dim3(1), dim3(1024), 0, s, a, nblk);
+      hipLaunchKernelGGL(k_scene_fill, dim3(nblk, a.n_objects), dim3(256), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(k_scene_composite, dim3(nblk), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -545,3 +545,70 @@ def test_depth_guided_samples_properties():
         z.extend((np.array(rest) - ts[r]) / sigma)
     z = np.array(z)
     assert abs(z.mean()) < 0.02 and abs(z.std() - 1.0) < 0.02
+
+
+# ------------------------------------------------------------------------ scene rendering
+
+def test_ray_box_against_brute_force():
+    """Slab entry/exit against dense point sampling of each ray (including directions with a
+    zero component, origins inside the box and rays that miss)."""
+    rng = np.random.default_rng(11)
+    ts = np.linspace(-12.0, 12.0, 240001)
+    step = ts[1] - ts[0]
+    for trial in range(120):
+        lo = rng.uniform(-1.0, 0.0, 3)
+        hi = lo + rng.uniform(0.1, 1.5, 3)
+        o = rng.uniform(-3.0, 3.0, 3) if trial % 5 else rng.uniform(lo, hi)
+        d = rng.standard_normal(3)
+        if trial % 7 == 0:
+            d[trial % 3] = 0.0
+        d /= np.linalg.norm(d)
+        t0, t1 = oracle.ray_box(o[None], d[None], lo, hi)
+        pts = o[None, :] + ts[:, None] * d[None, :]
+        inside = np.all((pts >= lo) & (pts <= hi), axis=1)
+        if inside.any():
+            assert abs(t0[0] - ts[inside][0]) <= step and abs(t1[0] - ts[inside][-1]) <= step
+        else:
+            assert t1[0] < t0[0] + step
+
+
+def _constant_model(H, colour, occ, seed=3):
+    """Parameters whose outputs are constant: zero output weights, logits in the output bias."""
+    th = oracle.xavier_init(seed, H, 4, 32).astype(np.float64)
+    logit = lambda p: np.log(p / (1.0 - p))
+    th[-(4 * H + 4):-4] = 0.0
+    th[-4:] = [logit(colour[0]), logit(colour[1]), logit(colour[2]), logit(occ)]
+    return th
+
+
+def _constant_render(o, t):
+    """Closed form of Eq. 3 for constant occupancy o at depths t: T_i = o (1 - o)^(i-1)."""
+    q = 1.0 - o
+    w = o * q ** np.arange(len(t))
+    return 1.0 - q ** len(t), float(np.sum(w * t))
+
+
+def test_render_scene_ranks_constant_occupancy_objects():
+    """Two boxes on one ray with constant outputs: the nearer one wins while its rendered
+    occupancy reaches the threshold, the farther one otherwise; a ray that meets neither box
+    gets no object."""
+    H, S = 32, 8
+    B = np.random.default_rng(1).normal(0.0, 5.0, (3, 16))
+    cA, cB = np.array([0.3, 0.6, 0.1]), np.array([0.9, 0.2, 0.5])
+    o_rays = np.array([[0.1, -0.1, -5.0], [0.0, 5.0, 0.0]])
+    d_rays = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
+    for oA, oB, winner in ((0.3, 0.4, 0), (0.02, 0.4, 1), (0.02, 0.05, -1)):
+        sA = oracle.ObjectState(_constant_model(H, cA, oA), H, 4, np.zeros(3), 0.5)
+        sB = oracle.ObjectState(_constant_model(H, cB, oB), H, 4, np.array([0.0, 0.0, 2.0]), 0.5)
+        depth, rgb, occ, k = oracle.render_scene([sA, sB], B, o_rays, d_rays, S)
+        assert k[1] == -1 and depth[1] == 0.0 and np.all(rgb[1] == 0.0)
+        assert k[0] == winner
+        if winner < 0:
+            continue
+        t0, t1 = (4.5, 5.5) if winner == 0 else (6.5, 7.5)
+        t = (t0 + (np.arange(S) + 0.5) / S * (t1 - t0)).astype(np.float32).astype(np.float64)
+        O, D = _constant_render(oA if winner == 0 else oB, t)
+        col = cA if winner == 0 else cB
+        assert abs(occ[0] - O) <= 1e-12 and abs(depth[0] - D) <= 1e-12
+        np.testing.assert_allclose(rgb[0], O * col, rtol=1e-12)
+        assert O >= 0.5
