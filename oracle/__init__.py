@@ -164,10 +164,20 @@ def normalise(rays_o, rays_d, t, centre, scale) -> np.ndarray:
     return (o + tt * d - c) / np.float64(scale)
 
 
-def encode(x: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """gamma = [sin(x B), cos(x B)] over the last axis (3 -> 2F)."""
-    phi = x @ np.asarray(B, np.float64)
-    return np.concatenate([np.sin(phi), np.cos(phi)], axis=-1)
+def encode(x: np.ndarray, B: np.ndarray, var: Optional[np.ndarray] = None) -> np.ndarray:
+    """gamma = [sin(x B), cos(x B)] over the last axis (3 -> 2F).
+
+    With ``var`` (one variance per point, same leading shape as x) the point stands for an
+    isotropic Gaussian N(x, var I) and each feature becomes its expectation under it, the
+    integrated positional encoding of the supplement's object-level encoding (after mip-NeRF
+    360): E[sin(x' b)] = sin(x b) exp(-var |b|^2 / 2), likewise for the cosine, b a column of B.
+    """
+    B = np.asarray(B, np.float64)
+    phi = x @ B
+    if var is None:
+        return np.concatenate([np.sin(phi), np.cos(phi)], axis=-1)
+    att = np.exp(-0.5 * np.asarray(var, np.float64)[..., None] * np.sum(B * B, axis=0))
+    return np.concatenate([np.sin(phi) * att, np.cos(phi) * att], axis=-1)
 
 
 def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int, rnd=_identity):
@@ -249,11 +259,16 @@ def ray_losses(O, D, C, P_end, depth, rgb, mask):
 
 # --------------------------------------------------------------------------- one object
 
-def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identity):
-    """Encode + MLP + heads + render for one object's rays. Returns a dict of intermediates."""
+def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identity, var=None):
+    """Encode + MLP + heads + render for one object's rays. Returns a dict of intermediates.
+
+    ``var`` [R, S]: per-sample variance of the sample's Gaussian in world units squared (the
+    integrated encoding), or None for point samples; the object frame divides it by s^2.
+    """
     R, S = np.shape(t)
     x = normalise(rays_o, rays_d, t, centre, scale)
-    gamma = encode(x, B)
+    vn = None if var is None else np.asarray(var, np.float64) / np.float64(scale) ** 2
+    gamma = encode(x, B, vn)
     z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L, rnd)
     c, o = heads(z)
     c = c.reshape(R, S, 3)
@@ -265,7 +280,7 @@ def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identi
 
 
 def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth, rgb, mask,
-                         upstream: float = 1.0, want_grad: bool = True, rnd=_identity):
+                         upstream: float = 1.0, want_grad: bool = True, rnd=_identity, var=None):
     """L^k of Eq. 7 for one object and, optionally, upstream * dL^k/dtheta.
 
     Returns (loss, grad or None, forward dict). With ``rnd`` = bf16_round every product of the
@@ -276,7 +291,7 @@ def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth
     depth = np.asarray(depth, np.float64)
     rgb = np.asarray(rgb, np.float64)
     mask = np.asarray(mask, np.float64)
-    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd)
+    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd, var)
     R, S = fw["o"].shape
     ld, lc, lo, rho = ray_losses(fw["O"], fw["D"], fw["C"], fw["P"][:, S], depth, rgb, mask)
     loss = float(np.sum(ld) + LAMBDA_COLOUR * np.sum(lc) + LAMBDA_OCC * np.sum(lo))
@@ -383,6 +398,7 @@ def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, bet
     ids = [int(k) for k in batch["object_ids"]]
     offs = np.asarray(batch["ray_offsets"], np.int64)
     R = int(offs[-1])
+    var = batch.get("var")
     losses = np.zeros(len(ids))
     grads = {}
     O = np.zeros(R)
@@ -398,7 +414,8 @@ def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, bet
         loss, g, fw = object_loss_and_grad(
             st.theta, st.H, st.L, B, st.centre, st.scale, batch["rays_o"][r0:r1],
             batch["rays_d"][r0:r1], batch["t"][r0:r1], batch["depth"][r0:r1],
-            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up, rnd=rnd)
+            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up, rnd=rnd,
+            var=None if var is None else var[r0:r1])
         losses[j] = loss
         grads[k] = g
         O[r0:r1], D[r0:r1], C[r0:r1] = fw["O"], fw["D"], fw["C"]

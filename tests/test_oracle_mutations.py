@@ -29,6 +29,7 @@ _orig_mlp = oracle.mlp_forward
 _orig_adam = oracle.adam_update
 _orig_encode = oracle.encode
 _orig_ray_losses = oracle.ray_losses
+_orig_render_scene = oracle.render_scene
 
 
 def _vjp_sign(o, c, t, gO, gD, gC, gPend):
@@ -58,7 +59,14 @@ def _adam_no_bias_correction(theta, m, v, g, step_count, lr=1e-3, beta1=0.9, bet
     return theta - lr * m / (np.sqrt(v) + eps), m, v
 
 
-def _encode_swapped(x, B):
+def _encode_ipe_no_half(x, B, var=None):
+    # the Gaussian's attenuation without the 1/2 of the exponent
+    if var is None:
+        return _orig_encode(x, B)
+    return _orig_encode(x, B, 2.0 * np.asarray(var))
+
+
+def _encode_swapped(x, B, var=None):
     phi = x @ np.asarray(B, np.float64)
     return np.concatenate([np.cos(phi), np.sin(phi)], axis=-1)
 
@@ -68,6 +76,22 @@ def _losses_no_colour_mask(O, D, C, P_end, depth, rgb, mask):
     return ld, np.abs(C - rgb).sum(-1), lo, rho
 
 
+def _ray_box_union(rays_o, rays_d, lo, hi):
+    # the union of the three slabs instead of their intersection
+    o = np.asarray(rays_o, np.float64)
+    d = np.asarray(rays_d, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ta = (np.asarray(lo) - o) / d
+        tb = (np.asarray(hi) - o) / d
+    return np.nanmin(np.minimum(ta, tb), axis=1), np.nanmax(np.maximum(ta, tb), axis=1)
+
+
+def _render_scene_no_threshold(*args, **kw):
+    # every object met counts as seen, whatever its rendered occupancy
+    kw["occ_threshold"] = -1.0
+    return _orig_render_scene(*args, **kw)
+
+
 MUTATIONS = {
     "render_index_off_by_one": ("render", _render_no_shift),
     "vjp_wrong_sign_of_leftover_transmittance": ("render_vjp", _vjp_sign),
@@ -75,7 +99,10 @@ MUTATIONS = {
     "relu_dropped": ("mlp_forward", _mlp_no_relu),
     "adam_without_bias_correction": ("adam_update", _adam_no_bias_correction),
     "sin_cos_swapped": ("encode", _encode_swapped),
+    "integrated_encoding_without_half": ("encode", _encode_ipe_no_half),
     "colour_loss_not_masked": ("ray_losses", _losses_no_colour_mask),
+    "ray_box_union_of_slabs": ("ray_box", _ray_box_union),
+    "scene_ranking_ignores_occupancy": ("render_scene", _render_scene_no_threshold),
 }
 
 PINS = [
@@ -90,6 +117,9 @@ PINS = [
     pins.test_adam_first_step_closed_form,
     pins.test_adam_second_step_values,
     pins.test_adam_matches_torch_optim,
+    pins.test_ray_box_against_brute_force,
+    pins.test_render_scene_ranks_constant_occupancy_objects,
+    pins.test_integrated_encoding_is_the_gaussian_expectation,
 ]
 
 

@@ -612,3 +612,22 @@ def test_render_scene_ranks_constant_occupancy_objects():
         assert abs(occ[0] - O) <= 1e-12 and abs(depth[0] - D) <= 1e-12
         np.testing.assert_allclose(rgb[0], O * col, rtol=1e-12)
         assert O >= 0.5
+
+
+# ------------------------------------------------------------------------ integrated encoding
+
+def test_integrated_encoding_is_the_gaussian_expectation():
+    """Monte Carlo: the mean of [sin(x B), cos(x B)] over x ~ N(mu, var I) matches the closed
+    form within five standard errors; var = 0 gives the point encoding bit for bit."""
+    rng = np.random.default_rng(21)
+    B = rng.normal(0.0, 5.0, (3, 16)) * 0.2
+    for mu, var in ((np.array([0.1, -0.3, 0.5]), 0.05), (np.array([-0.7, 0.2, 0.0]), 0.3)):
+        n = 400_000
+        xs = mu[None, :] + np.sqrt(var) * rng.standard_normal((n, 3))
+        phi = xs @ B
+        mc = np.concatenate([np.sin(phi), np.cos(phi)], axis=1)
+        mean, se = mc.mean(0), mc.std(0) / np.sqrt(n)
+        got = oracle.encode(mu[None, :], B, np.array([var]))[0]
+        assert np.all(np.abs(got - mean) <= 5 * se + 1e-12), np.max(np.abs(got - mean) / se)
+    x = rng.uniform(-1, 1, (50, 3))
+    assert np.array_equal(oracle.encode(x, B, np.zeros(50)), oracle.encode(x, B))
