@@ -113,6 +113,12 @@ typedef struct {
   const float* depth;         /* [R] observed depth D (used where mask = 1) */
   const float* rgb;           /* [R, 3] observed colour C (used where mask = 1) */
   const float* mask;          /* [R] instance mask M in {0, 1} (Sec. 3.3, Training Objective) */
+  const float* var;           /* [R, S] or NULL: per-sample variance (world units squared) of an
+                               * isotropic Gaussian the sample stands for; each Fourier feature is
+                               * then its expectation under it, the integrated positional
+                               * encoding (supplementary Sec. B, object-level positional
+                               * encoding): [sin, cos](x B) * exp(-var |b_f|^2 / (2 s^2)) in the
+                               * object frame. NULL: point samples. */
 } vmap_batch;
 
 /* Bytes of the caller-owned device state buffer (parameters, Adam moments, gradients,

@@ -62,7 +62,8 @@ class VmapBatch(ctypes.Structure):
                 ("samples_per_ray", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("object_ids", ctypes.c_void_p), ("ray_offsets", ctypes.c_void_p),
                 ("rays_o", ctypes.c_void_p), ("rays_d", ctypes.c_void_p), ("t", ctypes.c_void_p),
-                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
+                ("depth", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("var", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -164,9 +165,13 @@ class DeviceBatch:
         self.n_samples = self.n_rays * self.S
         self.object_ids = np.asarray(batch["object_ids"], dtype=np.int32)
         self.ray_offsets = np.asarray(batch["ray_offsets"], dtype=np.int64)
+        if batch.get("var") is not None:  # integrated encoding: per-sample variances [R, S]
+            self.tensors["var"] = torch.as_tensor(np.ascontiguousarray(batch["var"])).to(
+                device=dev, dtype=torch.float32).contiguous()
         self.c = VmapBatch(n_objects=self.n_objects, n_rays_total=self.n_rays,
                            samples_per_ray=self.S, reserved=0,
-                           **{k: self.tensors[k].data_ptr() for k in self.FIELDS})
+                           **{k: self.tensors[k].data_ptr() for k in self.FIELDS},
+                           var=self.tensors["var"].data_ptr() if "var" in self.tensors else None)
 
     def __getitem__(self, k):
         return self.tensors[k]

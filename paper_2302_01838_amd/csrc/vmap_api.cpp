@@ -218,6 +218,7 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.depth = b->depth;
   a.rgb = b->rgb;
   a.mask = b->mask;
+  a.var = b->var;
   a.theta = c->theta();
   a.p_stride = c->p_stride;
   a.desc = c->desc();
@@ -518,6 +519,7 @@ int vmap_train_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, void* str
   hb.depth = b->depth;
   hb.rgb = b->rgb;
   hb.mask = b->mask;
+  hb.var = b->var;
   hb.loss_out = loss_out;
   std::vector<int64_t> key = {b->n_objects, b->n_rays_total, b->samples_per_ray, c->waves,
                               c->grid_blocks, (int64_t)widths_present(c).size(),

@@ -159,6 +159,7 @@ struct BatchDev {
   const float* rgb;
   const float* mask;
   float* loss_out;
+  const float* var;
 };
 
 struct StepArgs {
@@ -175,6 +176,7 @@ struct StepArgs {
   const float* depth;
   const float* rgb;
   const float* mask;
+  const float* var;      // [R][S] integrated-encoding variances or NULL
   // model state
   const float* theta;
   int p_stride;

@@ -171,13 +171,16 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem,
 // ---------------------------------------------------------------------------------------------
 // Forward of one 32-sample pass for the calling wave. xt: this lane's normalised point (the
 // sample of column n = lane & 31; both lane halves hold the same point); Bm: the encoding matrix.
-// ENC = false: the encoding is already in A.v[0] (kept from an earlier pass; xt unused). Fills the activations
+// ENC = false: the encoding is already in A.v[0] (kept from an earlier pass; xt unused).
+// ipe: xt[3] holds the sample's variance in the object frame; each feature is its expectation
+// under the isotropic Gaussian (integrated positional encoding). Fills the activations
 // and, with WITH_HEAD, returns the four output pre-activations z of sample n (valid in both lane
 // halves).
 
 template <int H, bool BF, bool WITH_HEAD, bool ENC = true>
-__device__ __forceinline__ void forward_pass(const float xt[3], const unsigned char* smem,
-                                             const float* Bm, Acts<H, BF>& A, float z[4]) {
+__device__ __forceinline__ void forward_pass(const float xt[4], const unsigned char* smem,
+                                             const float* Bm, Acts<H, BF>& A, float z[4],
+                                             bool ipe = false) {
   constexpr int MT = H / 32;
   constexpr LdsLayout L = lds_layout(H, BF, 1);
   // Weights are re-read on every pass instead of being held in registers across passes. `smem`
@@ -195,6 +198,13 @@ __device__ __forceinline__ void forward_pass(const float xt[3], const unsigned c
       const float phi = xt[0] * Bm[f] + xt[1] * Bm[kFeatures + f] + xt[2] * Bm[2 * kFeatures + f];
       float s, c;
       vmap_sincosf(phi, &s, &c);
+      if (ipe) {  // expectation under N(x, v I): attenuation exp(-v |b_f|^2 / 2)
+        const float nb = Bm[f] * Bm[f] + Bm[kFeatures + f] * Bm[kFeatures + f] +
+                         Bm[2 * kFeatures + f] * Bm[2 * kFeatures + f];
+        const float att = expf(-0.5f * xt[3] * nb);
+        s *= att;
+        c *= att;
+      }
       A.set(0, 0, 4 * g + i, s);
       A.set(0, 0, 8 + 4 * g + i, c);
     }
@@ -329,6 +339,7 @@ __device__ __forceinline__ void read_batch(StepArgs& a) {
     a.depth = b->depth;
     a.rgb = b->rgb;
     a.mask = b->mask;
+    a.var = b->var;
   }
 }
 
@@ -523,9 +534,10 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       // ---------------- forward of both passes for the head outputs only. Each pass's
       // activations are recomputed right before its backward (activation recomputation), so no
       // activation is held across the rendering.
-      auto point = [&](int p, float xt[3]) {
+      // the lane's sample: normalised point and (integrated encoding) normalised variance
+      auto point = [&](int p, float xt[4]) {
         const int slot = 32 * p + n;
-        xt[0] = xt[1] = xt[2] = 0.f;
+        xt[0] = xt[1] = xt[2] = xt[3] = 0.f;
         if (slot < nslots) {
           const int ray = r0 + slot / S;
           const double tt = (double)a.t[(size_t)r0 * S + slot];
@@ -534,6 +546,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           xt[0] = (float)(((double)o3[0] + tt * (double)d3[0] - cx) * inv_s);
           xt[1] = (float)(((double)o3[1] + tt * (double)d3[1] - cy) * inv_s);
           xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - cz) * inv_s);
+          if (a.var) xt[3] = (float)((double)a.var[(size_t)r0 * S + slot] * inv_s * inv_s);
         }
       };
       float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
@@ -543,9 +556,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
         Acts<H, BF> tmp;
-        float xt[3], z[kOut];
+        float xt[4], z[kOut];
         point(p, xt);
-        forward_pass<H, BF, true>(xt, smem, Bl, tmp, z);
+        forward_pass<H, BF, true>(xt, smem, Bl, tmp, z, a.var != nullptr);
 #pragma unroll
         for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
         if constexpr (TRAIN) {
@@ -992,9 +1005,10 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
       const int nr = (sub < nsub) ? min(rpw, ray_hi - r0) : 0;
       const int nslots = nr * S;
 
-      auto point = [&](int p, float xt[3]) {
+      // the lane's sample: normalised point and (integrated encoding) normalised variance
+      auto point = [&](int p, float xt[4]) {
         const int slot = 32 * p + n;
-        xt[0] = xt[1] = xt[2] = 0.f;
+        xt[0] = xt[1] = xt[2] = xt[3] = 0.f;
         if (slot < nslots) {
           const int ray = r0 + slot / S;
           const double tt = (double)a.t[(size_t)r0 * S + slot];
@@ -1003,6 +1017,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
           xt[0] = (float)(((double)o3[0] + tt * (double)d3[0] - cx) * inv_s);
           xt[1] = (float)(((double)o3[1] + tt * (double)d3[1] - cy) * inv_s);
           xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - cz) * inv_s);
+          if (a.var) xt[3] = (float)((double)a.var[(size_t)r0 * S + slot] * inv_s * inv_s);
         }
       };
       float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
@@ -1010,9 +1025,9 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
           Acts<H, BF> tmp;
-          float xt[3], z[kOut];
+          float xt[4], z[kOut];
           point(p, xt);
-          forward_pass<H, BF, true>(xt, wb, Bl, tmp, z);
+          forward_pass<H, BF, true>(xt, wb, Bl, tmp, z, a.var != nullptr);
 #pragma unroll
           for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
         }
@@ -1028,9 +1043,9 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
         const bool first = (rd == 0 && p == 0), last = (rd == rounds - 1 && p == 1);
         Acts<H, BF> act;
         {
-          float xt[3], z[kOut];
+          float xt[4], z[kOut];
           point(p, xt);
-          forward_pass<H, BF, false>(xt, wb, Bl, act, z);
+          forward_pass<H, BF, false>(xt, wb, Bl, act, z, a.var != nullptr);
         }
         float dz[kOut];
 #pragma unroll
@@ -1409,7 +1424,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const int64_t i = chunk * kSlots + 32 * p + n;
-      float xt[3] = {0.f, 0.f, 0.f};
+      float xt[4] = {0.f, 0.f, 0.f, 0.f};
       if (i < qa.n) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) xt[c] = (float)(((double)qa.pts[3 * i + c] - d.centre[c]) * d.inv_scale);

@@ -310,12 +310,15 @@ def _samples(rng, scene: Scene, t_n, t_s):
 
 
 def make_batch(scene: Scene, step: int = 0, object_ids: Optional[List[int]] = None,
-               n_rays: Optional[Dict[int, int]] = None) -> Dict[str, np.ndarray]:
+               n_rays: Optional[Dict[int, int]] = None,
+               pixel_radius: Optional[float] = None) -> Dict[str, np.ndarray]:
     """One training batch: CSR-segmented rays of the listed objects, as FP32/int32 arrays.
 
     ``object_ids`` defaults to every object whose ``join_step <= step``. ``n_rays`` overrides
     per-object ray counts (zero allowed). Keys: object_ids [n], ray_offsets [n+1], rays_o
-    [R,3], rays_d [R,3], t [R,S], depth [R], rgb [R,3], mask [R], S.
+    [R,3], rays_d [R,3], t [R,S], depth [R], rgb [R,3], mask [R], S; with ``pixel_radius``
+    (radians) also var [R,S] = (pixel_radius t)^2, the variance of an isotropic Gaussian as wide
+    as the pixel's footprint at each sample.
     """
     if object_ids is None:
         object_ids = [k for k, ob in enumerate(scene.objects) if ob.join_step <= step]
@@ -344,9 +347,13 @@ def make_batch(scene: Scene, step: int = 0, object_ids: Optional[List[int]] = No
     t = cat(2, (0, S))
     # FP32 rounding can break the order of nearly equal samples; the step requires sorted t.
     t = np.sort(t, axis=1)
-    return dict(object_ids=np.asarray(object_ids, dtype=np.int32), ray_offsets=offs,
-                rays_o=cat(0, (0, 3)), rays_d=cat(1, (0, 3)), t=t, depth=cat(3, (0,)),
-                rgb=cat(4, (0, 3)), mask=cat(5, (0,)), S=S)
+    out = dict(object_ids=np.asarray(object_ids, dtype=np.int32), ray_offsets=offs,
+               rays_o=cat(0, (0, 3)), rays_d=cat(1, (0, 3)), t=t, depth=cat(3, (0,)),
+               rgb=cat(4, (0, 3)), mask=cat(5, (0,)), S=S)
+    if pixel_radius is not None:
+        out["var"] = (np.float64(pixel_radius) * t.astype(np.float64)) ** 2
+        out["var"] = out["var"].astype(np.float32)
+    return out
 
 
 def batch_samples(batch) -> int:

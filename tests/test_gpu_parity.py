@@ -361,3 +361,28 @@ def test_depth_guided_sampling_matches_oracle(S, n_strat):
     assert np.all(np.diff(t, axis=1) >= 0)
     np.testing.assert_allclose(t, ref, rtol=2.5e-7, atol=0)
     report(f"sampling S={S} n_strat={n_strat}", max_rel=float(np.max(np.abs(t - ref) / np.abs(ref))))
+
+
+# ------------------------------------------------------------------------ integrated encoding
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("scene_name", list(SCENES))
+def test_integrated_encoding_step_parity(precision, scene_name):
+    """Samples standing for Gaussians as wide as a 0.02 rad pixel footprint: every feature is
+    attenuated by exp(-var |b|^2 / 2) in the object frame (factors down to ~0.2 here)."""
+    sc = SCENES[scene_name]()
+    objs, states = make_pair(sc, precision)
+    batch = scenes.make_batch(sc, 0, pixel_radius=0.02)
+    errs, errs16, unstable, _ = step_errors(objs, states, batch, precision, sc.B)
+    report(f"ipe step {precision} {scene_name} (sign-unstable={unstable})", **errs)
+    if errs16:
+        report(f"ipe step {precision} {scene_name} vs bf16 oracle", **errs16)
+    check_step(errs, errs16, precision)
+    # the renders differ from the point-sample encoding's
+    objs2, _ = make_pair(sc, precision)
+    db_ipe = vm.DeviceBatch(batch)
+    plain = dict(batch)
+    plain.pop("var")
+    d1 = objs2.render(db_ipe)[0]
+    d2 = objs2.render(vm.DeviceBatch(plain))[0]
+    assert not torch.equal(d1, d2)

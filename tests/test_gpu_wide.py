@@ -244,3 +244,14 @@ def test_stress_full_size_sampled_objects():
         report(f"stress full size object {k} ({counts[k]} rays)", loss=e_l, theta=e_t)
         assert e_l <= 2e-2 and e_t <= 2e-2
         assert objs.get_state(k, vm.STATE_STEP) == 1
+
+
+@pytest.mark.parametrize("name", ["h64-fp32", "h128-bf16"])
+def test_wide_integrated_encoding(name):
+    make, ids, precision = CASES[name]
+    sc = make()
+    objs, states = make_pair(sc, precision, ids=ids)
+    batch = remap_batch(scenes.make_batch(sc, 0, object_ids=ids, pixel_radius=0.01), ids)
+    errs, errs16, unstable, _ = step_errors(objs, states, batch, precision, sc.B)
+    report(f"wide ipe step {name}", **errs)
+    check_step(errs, errs16, precision)

@@ -100,7 +100,31 @@ def test_init_argument_errors_before_device_use(lib):
     lib.vmap_destroy(None)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structs against sizeof/offsetof of the C header, compiled with g++."""
+    import shutil
+    import subprocess
     assert ctypes.sizeof(vm.VmapConfig) == 10 * 4 + 7 * 8
     assert ctypes.sizeof(vm.VmapObjectDesc) == 32
-    assert ctypes.sizeof(vm.VmapBatch) == 16 + 8 * 8
+    assert ctypes.sizeof(vm.VmapBatch) == 16 + 9 * 8
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    structs = {"vmap_config": vm.VmapConfig, "vmap_object_desc": vm.VmapObjectDesc,
+               "vmap_batch": vm.VmapBatch}
+    lines = ["#include <cstdio>", "#include <cstddef>", '#include "vmap.h"', "int main() {"]
+    for cname, py in structs.items():
+        lines.append(f'  std::printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  std::printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["g++", "-std=c++17", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

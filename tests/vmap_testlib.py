@@ -81,6 +81,8 @@ def near_kink_rays(states, batch, B, tau=1e-5, rnd=None):
             continue
         st = states[int(k)]
         kw = {} if rnd is None else {"rnd": rnd}
+        if batch.get("var") is not None:
+            kw["var"] = batch["var"][r0:r1]
         fw = oracle.object_forward(st.theta, st.H, st.L, B, st.centre, st.scale,
                                    batch["rays_o"][r0:r1], batch["rays_d"][r0:r1], batch["t"][r0:r1],
                                    **kw)
@@ -106,6 +108,8 @@ def keep_rays(batch, keep):
     offs = np.asarray(batch["ray_offsets"], np.int64)
     counts = [int(np.sum(keep[offs[j]:offs[j + 1]])) for j in range(len(batch["object_ids"]))]
     out = {k: batch[k][keep] for k in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
+    if batch.get("var") is not None:
+        out["var"] = batch["var"][keep]
     out["object_ids"] = batch["object_ids"].copy()
     out["ray_offsets"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     out["S"] = batch["S"]
