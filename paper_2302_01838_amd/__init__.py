@@ -116,6 +116,10 @@ def load_library():
     path = library_path()
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2302_01838_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has already loaded, so the
+    # process holds one runtime (a second copy loaded first finds no device once torch's runtime
+    # owns it)
+    _torch()
     lib = ctypes.CDLL(path)
     for name, (res, args) in EXPORTED.items():
         fn = getattr(lib, name)

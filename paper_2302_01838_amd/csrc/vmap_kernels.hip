@@ -450,6 +450,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   read_batch(a);
   constexpr int MT = H / 32;
   constexpr bool TRAIN = (MODE == MODE_TRAIN);
+  constexpr bool KEEP = TRAIN && !BF;  // activations kept across the rendering (no recompute)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr LdsLayout L = lds_layout(H, BF, 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -550,23 +551,27 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         }
       };
       float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
-      // the encodings of both passes are kept for the recomputation in the backward
-      using Enc = typename std::remove_reference<decltype(Acts<H, BF>{}.v[0][0])>::type;
-      Enc enc0, enc1;
+      // FP32 (one wave per SIMD either way) keeps both passes' activations for the backward;
+      // BF16 recomputes them there, which keeps it at two waves per SIMD (measured faster).
+      Acts<H, BF> keep0, keep1;
+      if constexpr (KEEP) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          float xt[4], z[kOut];
+          point(p, xt);
+          forward_pass<H, BF, true>(xt, smem, Bl, p == 0 ? keep0 : keep1, z, a.var != nullptr);
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
+        }
+      } else {
 #pragma unroll 1
-      for (int p = 0; p < 2; ++p) {
-        Acts<H, BF> tmp;
-        float xt[4], z[kOut];
-        point(p, xt);
-        forward_pass<H, BF, true>(xt, smem, Bl, tmp, z, a.var != nullptr);
+        for (int p = 0; p < 2; ++p) {
+          Acts<H, BF> tmp;
+          float xt[4], z[kOut];
+          point(p, xt);
+          forward_pass<H, BF, true>(xt, smem, Bl, tmp, z, a.var != nullptr);
 #pragma unroll
-        for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
-        if constexpr (TRAIN) {
-#pragma unroll
-          for (int q = 0; q < (int)(sizeof(Enc) / sizeof(tmp.v[0][0][0])); ++q) {
-            if (p == 0) enc0[q] = tmp.v[0][0][q];
-            else enc1[q] = tmp.v[0][0][q];
-          }
+          for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
         }
       }
 
@@ -583,12 +588,18 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
         Acts<H, BF> act;
-        {  // recompute the activations of this pass from its encoding
+        if constexpr (KEEP) {
 #pragma unroll
-          for (int q = 0; q < (int)(sizeof(Enc) / sizeof(act.v[0][0][0])); ++q)
-            act.v[0][0][q] = (p == 0) ? enc0[q] : enc1[q];
-          float z[kOut];
-          forward_pass<H, BF, false, false>(nullptr, smem, Bl, act, z);
+          for (int l = 0; l <= kLayers; ++l)
+#pragma unroll
+            for (int b = 0; b < H / 32; ++b)
+#pragma unroll
+              for (int q = 0; q < (int)(sizeof(act.v[0][0]) / sizeof(act.v[0][0][0])); ++q)
+                act.v[l][b][q] = (p == 0) ? keep0.v[l][b][q] : keep1.v[l][b][q];
+        } else {  // recompute the activations of this pass
+          float xt[4], z[kOut];
+          point(p, xt);
+          forward_pass<H, BF, false>(xt, smem, Bl, act, z, a.var != nullptr);
         }
         float dz[kOut];
 #pragma unroll
