@@ -1875,6 +1875,7 @@ __global__ void __launch_bounds__(1024) k_scene_scan(const SceneArgs a, int nblk
     b->rgb = nullptr;
     b->mask = nullptr;
     b->loss_out = nullptr;
+    b->var = nullptr;  // point samples (the scratch holding the descriptor is not cleared)
   }
 }
 
