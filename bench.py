@@ -49,6 +49,39 @@ def flop_per_sample(H: int) -> int:
 
 FLOP_PER_SAMPLE_H32 = flop_per_sample(32)
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_traffic_k50_uneven.md")
+
+
+def tile_kernel_fingerprint() -> str:
+    """SHA-256 of the source that defines the hidden-32 tile kernel: vmap_kernels.hip from the
+    activation types to the end of k_step_tiles, plus vmap_internal.h and vmap_math.h."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2302_01838_amd", "csrc")
+    k = open(os.path.join(csrc, "vmap_kernels.hip")).read()
+    a = k.index("// Activations of one 32-sample pass")
+    b = k.index("// Tile kernel for wide models")
+    h = hashlib.sha256(k[a:b].encode())
+    for name in ("vmap_internal.h", "vmap_math.h"):
+        h.update(open(os.path.join(csrc, name)).read().encode())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the tile kernel from the committed counter summary, or None if
+    the summary is missing or was taken on a different version of the kernel source."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            key, val = line[2:].split(":", 1)
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("kernel source sha256") != tile_kernel_fingerprint():
+        return None
+    val = fields.get(f"traffic bytes per launch ({precision})")
+    return int(val.replace(",", "")) if val else None
 
 
 def log(msg):
@@ -312,8 +345,9 @@ def main():
             2e-2 * abs(forms["fp32"]["final_loss"])
     flops = head["kernel_flops"]
     achieved = flops / (head["kernel_ms"] * 1e-3) if head["kernel_ms"] > 0 else 0.0
+    traffic = measured_traffic(prec) if args.workload == WORKLOAD else None
     roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK[prec], traffic=None,
+                    frac=achieved / PEAK[prec], traffic=traffic,
                     kernel="tile kernels (fused encode+MLP+render+loss+backward)",
                     kernel_avg_ms=head["kernel_ms"], flop_per_launch=flops)
     log(f"cpu baseline: oracle for up to {args.cpu_budget:.0f} s")
