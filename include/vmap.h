@@ -78,6 +78,9 @@ typedef struct {
   int32_t precision;            /* VMAP_FP32, or VMAP_BF16: MLP products on BF16 MFMA */
   int32_t rays_per_tile;        /* rays per work tile; 0 = library default for (H, S) */
   int32_t scale_growth_interval;/* BF16: good steps before the loss scale doubles (2000) */
+  int32_t rays_per_tile_wide;   /* rays per work tile of objects wider than 32; 0 = one round
+                                 * of the cooperative kernel (4 waves x floor(64 / S) rays) */
+  int32_t reserved;
   double lr;                    /* Adam learning rate (1e-3) */
   double beta1, beta2, eps;     /* Adam moments (0.9, 0.999) and epsilon (1e-8) */
   double lambda_colour;         /* lambda_1 of Eq. 7 (5) */

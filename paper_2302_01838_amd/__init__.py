@@ -46,6 +46,7 @@ class VmapConfig(ctypes.Structure):
                 ("max_hidden", ctypes.c_int32), ("max_samples_per_ray", ctypes.c_int32),
                 ("max_rays", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rays_per_tile", ctypes.c_int32), ("scale_growth_interval", ctypes.c_int32),
+                ("rays_per_tile_wide", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double), ("lambda_colour", ctypes.c_double),
                 ("lambda_occ", ctypes.c_double), ("loss_scale_init", ctypes.c_double)]
@@ -186,7 +187,8 @@ class ObjectSet:
 
     def __init__(self, max_objects: int, B: np.ndarray, hidden: int = 32, precision: str = "fp32",
                  max_rays: int = 1 << 16, max_samples_per_ray: int = 32,
-                 max_hidden: Optional[int] = None, rays_per_tile: int = 0, lr: float = 1e-3,
+                 max_hidden: Optional[int] = None, rays_per_tile: int = 0,
+                 rays_per_tile_wide: int = 0, lr: float = 1e-3,
                  betas=(0.9, 0.999), eps: float = 1e-8, lambda_colour: float = 5.0,
                  lambda_occ: float = 10.0, loss_scale_init: float = 4096.0,
                  scale_growth_interval: int = 2000, device=None, autotune: bool = True):
@@ -204,7 +206,8 @@ class ObjectSet:
             max_objects=max_objects, hidden=hidden, max_hidden=max_hidden or hidden,
             max_samples_per_ray=max_samples_per_ray, max_rays=max_rays,
             precision=VMAP_BF16 if precision == "bf16" else VMAP_FP32,
-            rays_per_tile=rays_per_tile, scale_growth_interval=scale_growth_interval, lr=lr,
+            rays_per_tile=rays_per_tile, rays_per_tile_wide=rays_per_tile_wide,
+            scale_growth_interval=scale_growth_interval, lr=lr,
             beta1=betas[0], beta2=betas[1], eps=eps, lambda_colour=lambda_colour,
             lambda_occ=lambda_occ, loss_scale_init=loss_scale_init)
         self.precision = precision

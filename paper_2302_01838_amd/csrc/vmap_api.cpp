@@ -49,6 +49,8 @@ const char* check_config(const vmap_config* c) {
   if (c->max_samples_per_ray < 1 || c->max_samples_per_ray > kSlots) return "max_samples_per_ray must be in [1, 64]";
   if (c->max_rays < 0 || c->max_rays > (1 << 26)) return "max_rays must be in [0, 2^26]";
   if (c->rays_per_tile < 0 || c->rays_per_tile > (1 << 16)) return "rays_per_tile must be in [0, 65536]";
+  if (c->rays_per_tile_wide < 0 || c->rays_per_tile_wide > (1 << 16))
+    return "rays_per_tile_wide must be in [0, 65536]";
   if (!(c->lr > 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
       !(c->eps > 0.0))
     return "Adam settings out of range (lr > 0, 0 <= beta < 1, eps > 0)";
@@ -64,6 +66,21 @@ int default_rays_per_tile(const vmap_config* c) {
   if (c->rays_per_tile > 0) return c->rays_per_tile;
   const int rpw = std::max(1, kSlots / c->max_samples_per_ray);
   return rpw * 4 * 2;  // two sub-tiles per wave of a four-wave block
+}
+
+// Objects wider than 32 run in the cooperative kernel, whose workgroups do far more work per
+// ray: one round (a sub-tile for each of the four waves) per tile spreads a single wide object
+// (the room workload's background) over as many workgroups as it has rays for.
+int default_rays_per_tile_wide(const vmap_config* c) {
+  if (c->rays_per_tile_wide > 0) return c->rays_per_tile_wide;
+  const int rpw = std::max(1, kSlots / c->max_samples_per_ray);
+  return rpw * 4;
+}
+
+// Smallest tile any object of the config may use (capacity bound).
+int min_rays_per_tile(const vmap_config* c) {
+  const int rpt = default_rays_per_tile(c);
+  return c->max_hidden > 32 ? std::min(rpt, default_rays_per_tile_wide(c)) : rpt;
 }
 
 StateLayout state_layout(const vmap_config* c) {
@@ -84,7 +101,7 @@ StateLayout state_layout(const vmap_config* c) {
 
 WorkLayout work_layout(const vmap_config* c) {
   WorkLayout w{};
-  const int rpt = default_rays_per_tile(c);
+  const int rpt = min_rays_per_tile(c);
   const size_t ps = (size_t)pad_params(n_params_of(c->max_hidden));
   w.max_tiles = (c->max_rays + rpt - 1) / rpt + c->max_objects;
   size_t off = 0;
@@ -122,6 +139,11 @@ struct vmap_ctx {
   unsigned char* work = nullptr;
   int p_stride = 0;
   int rays_per_tile = 0;
+  int rays_per_tile_wide = 0;
+  int min_rays_per_tile = 0;
+  // second stream for the width groups after the first (overlapped), with fork/join events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int waves = 4;
   int grid_blocks = 0;
   int device = 0;
@@ -190,7 +212,7 @@ int validate_batch(vmap_ctx* c, const vmap_batch* b, bool need_targets) {
     if (need_targets && (!b->depth || !b->rgb || !b->mask))
       return c->fail(VMAP_EINVAL, "batch targets (depth, rgb, mask) must not be NULL");
   }
-  const int rpt = c->rays_per_tile;
+  const int rpt = c->min_rays_per_tile;
   const long long tiles = ((long long)b->n_rays_total + rpt - 1) / rpt + b->n_objects;
   if (tiles > c->wl.max_tiles) return c->fail(VMAP_ECAPACITY, "batch needs more tiles than the workspace holds");
   return VMAP_OK;
@@ -209,6 +231,7 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.n_objects = b->n_objects;
   a.S = b->samples_per_ray;
   a.rays_per_tile = c->rays_per_tile;
+  a.rays_per_tile_wide = c->rays_per_tile_wide;
   a.max_objects = c->cfg.max_objects;
   a.object_ids = b->object_ids;
   a.ray_offsets = b->ray_offsets;
@@ -249,6 +272,7 @@ hipEvent_t pooled_event(vmap_ctx* c) {
 hipError_t enqueue_worklist(vmap_ctx* c, const vmap_batch* b, hipStream_t s,
                             const BatchDev* bd = nullptr) {
   return launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
+                         c->rays_per_tile_wide,
                          c->cfg.max_objects, c->desc(), c->tile_start(), c->flags(), c->t_next(),
                          bd, s);
 }
@@ -296,7 +320,7 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
   a.out_occ = occ_out;
   a.use_scale = (mode == MODE_TRAIN && c->cfg.precision == VMAP_BF16) ? 1 : 0;
   const bool bf = c->cfg.precision == VMAP_BF16;
-  const int bound = (b->n_rays_total + c->rays_per_tile - 1) / c->rays_per_tile + b->n_objects;
+  const int bound = (b->n_rays_total + c->min_rays_per_tile - 1) / c->min_rays_per_tile + b->n_objects;
   int grid = bound;
   if (c->grid_blocks > 0) grid = std::min(grid, c->grid_blocks);
   TimedLaunch tl{};
@@ -308,12 +332,35 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
     hipError_t e = hipEventRecord(tl.a, s);
     if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
   }
-  for (int H : widths_present(c)) {
+  // Width groups run as separate kernels; with more than one, every group after the first goes
+  // to a side stream (forked from and joined back into `s` by events, which graph capture
+  // follows), so that the groups overlap on the GPU.
+  const std::vector<int> widths = widths_present(c);
+  const bool fork = widths.size() > 1;
+  if (fork) {
+    if (!c->side_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return c->hip_fail(e, "side stream");
+    }
+    hipError_t e = hipEventRecord(c->fork_ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side_stream, c->fork_ev, 0);
+    if (e != hipSuccess) return c->hip_fail(e, "stream fork");
+  }
+  for (size_t i = 0; i < widths.size(); ++i) {
+    const int H = widths[i];
+    hipStream_t si = (i == 0) ? s : c->side_stream;
     a.hidden = H;
-    hipError_t e = launch_stage_images(H, bf, a, -1, s);
+    hipError_t e = launch_stage_images(H, bf, a, -1, si);
     if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
-    e = launch_tiles(H, bf, mode, a, c->waves, grid, s);
+    e = launch_tiles(H, bf, mode, a, c->waves, grid, si);
     if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(c->join_ev, c->side_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join_ev, 0);
+    if (e != hipSuccess) return c->hip_fail(e, "stream join");
   }
   if (timed) {
     hipError_t e = hipEventRecord(tl.b, s);
@@ -422,6 +469,8 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   c->work = reinterpret_cast<unsigned char*>(workspace_dev);
   c->p_stride = pad_params(n_params_of(cfg->max_hidden));
   c->rays_per_tile = default_rays_per_tile(cfg);
+  c->rays_per_tile_wide = default_rays_per_tile_wide(cfg);
+  c->min_rays_per_tile = min_rays_per_tile(cfg);
   c->objs.resize(cfg->max_objects);
   (void)hipGetDevice(&c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -879,6 +928,9 @@ void vmap_destroy(vmap_ctx* c) {
   }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   for (int i = 0; i < vmap_ctx::kRing; ++i)
     if (c->ring_used[i]) (void)hipEventDestroy(c->ring_ev[i]);
   if (c->ring) (void)hipHostFree(c->ring);

@@ -138,6 +138,9 @@ __host__ __device__ constexpr CoopLayout coop_layout(int H, bool bf16) {
   return C;
 }
 
+// Rays per work tile of an object of width H.
+__host__ __device__ constexpr int tile_rays(int H, int rpt, int rpt_wide) { return H > 32 ? rpt_wide : rpt; }
+
 // Offset of layer l's weights in an object's parameter vector (l = kLayers: the output layer).
 __host__ __device__ constexpr int layer_param_off(int H, int l) {
   return l == 0 ? 0 : (H * kEnc + H) + (l - 1) * (H * H + H);
@@ -167,6 +170,7 @@ struct StepArgs {
   int n_objects;
   int S;
   int rays_per_tile;
+  int rays_per_tile_wide;     // tiles of objects wider than 32
   int max_objects;
   const int32_t* object_ids;
   const int32_t* ray_offsets;
@@ -278,7 +282,8 @@ struct SceneArgs {
 // Kernel launchers (vmap_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int max_objects, const ObjDesc* desc,
+                           int rays_per_tile, int rays_per_tile_wide, int max_objects,
+                           const ObjDesc* desc,
                            int32_t* tile_start, int32_t* flags, int32_t* t_next,
                            const BatchDev* bd, hipStream_t s);
 hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,

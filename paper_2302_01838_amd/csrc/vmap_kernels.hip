@@ -477,8 +477,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       continue;
     }
     if (a.desc[k].hidden != H) continue;  // handled by the launch for that width
-    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * a.rays_per_tile;
-    const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
+    const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
+    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * rpt;
+    const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
     if (k != staged) {
       __syncthreads();
       stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, tid, blockDim.x);
@@ -946,8 +947,9 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
       continue;
     }
     if (a.desc[k].hidden != H) continue;
-    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * a.rays_per_tile;
-    const int ray_hi = min(ray_lo + a.rays_per_tile, a.ray_offsets[j + 1]);
+    const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
+    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * rpt;
+    const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
     const unsigned char* wb = smem;
     if constexpr (GW) {
       wb = a.wimage + (size_t)k * a.wimage_stride;
@@ -1460,7 +1462,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
 // that the optimiser kernels read it from here while one of their blocks advances the count.
 
 __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t* ids,
-                                                   const int32_t* offs, int rpt,
+                                                   const int32_t* offs, int rpt, int rpt_wide,
                                                    int max_objects, const ObjDesc* __restrict__ desc,
                                                    int32_t* __restrict__ tile_start,
                                                    int32_t* __restrict__ flags,
@@ -1476,9 +1478,15 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
   const int per = (n_objects + nt - 1) / nt;
   const int j0 = min(tid * per, n_objects), j1 = min(j0 + per, n_objects);
   int local = 0;
+  // rays per tile of batch object j (by its width; invalid ids take the narrow size)
+  auto rpt_of = [&](int j) {
+    const int k = ids[j];
+    return (k >= 0 && k < max_objects && desc[k].registered) ? tile_rays(desc[k].hidden, rpt, rpt_wide) : rpt;
+  };
   for (int j = j0; j < j1; ++j) {
     const int nr = offs[j + 1] - offs[j];
-    local += (nr > 0) ? (nr + rpt - 1) / rpt : 0;
+    const int rj = rpt_of(j);
+    local += (nr > 0) ? (nr + rj - 1) / rj : 0;
     const int k = ids[j];
     const bool valid = k >= 0 && k < max_objects;
     if (valid) flags[k] = 0;
@@ -1497,7 +1505,8 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
   for (int j = j0; j < j1; ++j) {
     tile_start[j] = run;
     const int nr = offs[j + 1] - offs[j];
-    run += (nr > 0) ? (nr + rpt - 1) / rpt : 0;
+    const int rj = rpt_of(j);
+    run += (nr > 0) ? (nr + rj - 1) / rj : 0;
   }
   if (tid == nt - 1) tile_start[n_objects] = part[nt - 1];
 }
@@ -2078,11 +2087,12 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int max_objects, const ObjDesc* desc,
-                           int32_t* tile_start, int32_t* flags, int32_t* t_next,
-                           const BatchDev* bd, hipStream_t s) {
+                           int rays_per_tile, int rays_per_tile_wide, int max_objects,
+                           const ObjDesc* desc, int32_t* tile_start, int32_t* flags,
+                           int32_t* t_next, const BatchDev* bd, hipStream_t s) {
   hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, object_ids, ray_offsets,
-                     rays_per_tile, max_objects, desc, tile_start, flags, t_next, bd);
+                     rays_per_tile, rays_per_tile_wide, max_objects, desc, tile_start, flags,
+                     t_next, bd);
   return hipGetLastError();
 }
 

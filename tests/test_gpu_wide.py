@@ -46,10 +46,10 @@ CASES = {
 }
 
 
-def _case(name, rays_per_tile=0):
+def _case(name, rays_per_tile_wide=0):
     make, ids, precision = CASES[name]
     sc = make()
-    objs, states = make_pair(sc, precision, ids=ids, rays_per_tile=rays_per_tile)
+    objs, states = make_pair(sc, precision, ids=ids, rays_per_tile_wide=rays_per_tile_wide)
     batch = remap_batch(scenes.make_batch(sc, 0, object_ids=ids), ids)
     return sc, ids, precision, objs, states, batch
 
@@ -89,8 +89,9 @@ def test_wide_train_step_parity(name):
                                       ("h128-bf16", 64)])
 def test_wide_tile_shapes(name, rpt):
     """Tiles of one ray (three waves idle in every round), ragged tiles, and tiles of many
-    rounds (the partial is accumulated across rounds)."""
-    sc, ids, precision, objs, states, batch = _case(name, rays_per_tile=rpt)
+    rounds (the partial is accumulated across rounds); the hidden-32 objects of the room case
+    keep their own tile size."""
+    sc, ids, precision, objs, states, batch = _case(name, rays_per_tile_wide=rpt)
     errs, errs16, unstable, _ = step_errors(objs, states, batch, precision, sc.B)
     report(f"wide step {name} rays_per_tile={rpt}", **errs)
     check_step(errs, errs16, precision)
@@ -221,7 +222,7 @@ def test_stress_full_size_sampled_objects():
     n = sc.n_objects
     objs = vm.ObjectSet(max_objects=n, B=sc.B, hidden=64, precision="bf16",
                         max_rays=sum(o.n_rays for o in sc.objects) + 64, max_samples_per_ray=sc.S,
-                        rays_per_tile=64)
+                        rays_per_tile_wide=64)
     states = {}
     for k, ob in enumerate(sc.objects):
         assert objs.add(ob.norm_centre, ob.norm_scale, seed=ob.seed) == k

@@ -63,7 +63,8 @@ def test_wide_models_bf16_only(lib):
 @pytest.mark.parametrize("field,value", [("max_objects", 0), ("n_features", 8),
                                          ("n_hidden_layers", 3), ("hidden", 48),
                                          ("max_samples_per_ray", 65), ("precision", 7),
-                                         ("lr", 0.0), ("beta2", 1.0), ("max_rays", -1)])
+                                         ("lr", 0.0), ("beta2", 1.0), ("max_rays", -1),
+                                         ("rays_per_tile_wide", -1)])
 def test_invalid_config_rejected(lib, field, value):
     cfg = vm.default_config()
     setattr(cfg, field, value)
@@ -104,7 +105,7 @@ def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structs against sizeof/offsetof of the C header, compiled with g++."""
     import shutil
     import subprocess
-    assert ctypes.sizeof(vm.VmapConfig) == 10 * 4 + 7 * 8
+    assert ctypes.sizeof(vm.VmapConfig) == 12 * 4 + 7 * 8
     assert ctypes.sizeof(vm.VmapObjectDesc) == 32
     assert ctypes.sizeof(vm.VmapBatch) == 16 + 9 * 8
     if shutil.which("g++") is None:
