@@ -107,13 +107,15 @@ def batch_flops(scene, db) -> float:
                      for j, k in enumerate(ids)))
 
 
-def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps):
+def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
+             rays_per_tile_wide=0):
     import torch
     import paper_2302_01838_amd as vm
     nrays = max(db.n_rays for db in dev_batches)
     objs = vm.ObjectSet(max_objects=scene.n_objects, B=scene.B, hidden=scene.objects[0].hidden,
                         max_hidden=max(o.hidden for o in scene.objects), precision=precision,
-                        max_rays=nrays, max_samples_per_ray=scene.S)
+                        max_rays=nrays, max_samples_per_ray=scene.S,
+                        rays_per_tile_wide=rays_per_tile_wide)
     for ob in scene.objects:
         objs.add(ob.norm_centre, ob.norm_scale, hidden=ob.hidden, seed=ob.seed)
     objs.set_graph_mode(graph)
@@ -283,6 +285,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--forms", default=None,
                     help="comma-separated precisions (default fp32,bf16; bf16 with hidden 128)")
+    ap.add_argument("--rays-per-tile-wide", type=int, default=0,
+                    help="tile size of objects wider than 32 (0: the library default)")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
                     help="k50_uneven is the headline workload; the others are reported in the docs")
     ap.add_argument("--sweep-objects", type=int, nargs="*", default=None,
@@ -332,7 +336,8 @@ def main():
     for prec in args.forms.split(","):
         log(f"form {prec}: {args.warmup} warmup + {args.steps} timed steps")
         forms[prec] = run_form(prec, scene, dev_batches, args.steps, args.warmup,
-                               bool(args.graph), timing_steps=min(args.steps, 50))
+                               bool(args.graph), timing_steps=min(args.steps, 50),
+                               rays_per_tile_wide=args.rays_per_tile_wide)
         log(f"form {prec}: {forms[prec]['ms_per_step']:.4f} ms/step, "
             f"{forms[prec]['ray_samples_per_s']:.4g} samples/s, final loss "
             f"{forms[prec]['final_loss']:.6g}")

@@ -68,13 +68,18 @@ int default_rays_per_tile(const vmap_config* c) {
   return rpw * 4 * 2;  // two sub-tiles per wave of a four-wave block
 }
 
-// Objects wider than 32 run in the cooperative kernel, whose workgroups do far more work per
-// ray: one round (a sub-tile for each of the four waves) per tile spreads a single wide object
-// (the room workload's background) over as many workgroups as it has rays for.
+// Objects wider than 32 run in the cooperative kernel, whose tiles hold whole rounds (a sub-tile
+// for each of its four waves). Few rays per object (a room's background: 1,200 rays) want one
+// round per tile, to spread the object over many workgroups; many rays per object want longer
+// tiles, to write fewer partial gradients (each is a whole object's parameter vector). Default:
+// about max_rays / max_objects / 32 rays, in whole rounds, between one and eight rounds.
 int default_rays_per_tile_wide(const vmap_config* c) {
   if (c->rays_per_tile_wide > 0) return c->rays_per_tile_wide;
   const int rpw = std::max(1, kSlots / c->max_samples_per_ray);
-  return rpw * 4;
+  const int round = rpw * 4;
+  const double per_object = (double)c->max_rays / std::max(1, c->max_objects);
+  const int rounds = (int)std::lround(per_object / 32.0 / round);
+  return round * std::min(8, std::max(1, rounds));
 }
 
 // Smallest tile any object of the config may use (capacity bound).

@@ -65,6 +65,10 @@ __host__ __device__ constexpr int tr_tile_bytes(int H, bool bf16) {
   return bf16 ? H * 40 * 2 : 32 * (H + 4) * 4;
 }
 
+// BF16 training keeps the encodings of a sub-tile's two 32-sample passes in LDS (BF16, 32 features
+// per sample) for the backward's recomputation, which then starts at the first layer.
+__host__ __device__ constexpr int enc_cache_bytes(bool bf16) { return bf16 ? 2 * 32 * kEnc * 2 : 0; }
+
 // Every offset except `total` is independent of the wave count, so kernels evaluate the layout at
 // compile time (immediate LDS offsets) and only the host needs `total`.
 __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves) {
@@ -96,7 +100,7 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   off = round_up(off + 3 * kFeatures * 4, 16);
   L.loss_off = off;
   off = round_up(off + 16, 16);
-  L.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16), 16);
+  L.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16) + enc_cache_bytes(bf16), 16);
   L.scratch_off = off;
   int scratch = nwaves * L.scratch_wave;
   const int red = n_params_of(H) * 4;

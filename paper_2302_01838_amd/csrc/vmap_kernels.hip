@@ -524,6 +524,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     float wave_loss = 0.f;
 
     unsigned char* scr = smem + L.scratch_off + wave * L.scratch_wave;
+    unsigned char* encc = scr + dz_tile_bytes(BF) + 2 * tr_tile_bytes(H, BF);
     const int nrays = ray_hi - ray_lo;
     const int nsub = (nrays + rpw - 1) / rpw;
 
@@ -553,7 +554,8 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       };
       float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
       // FP32 (one wave per SIMD either way) keeps both passes' activations for the backward;
-      // BF16 recomputes them there, which keeps it at two waves per SIMD (measured faster).
+      // BF16 recomputes them there from the encodings kept in LDS (no sine/cosine twice), which
+      // keeps it at two waves per SIMD (measured faster than keeping the activations).
       Acts<H, BF> keep0, keep1;
       if constexpr (KEEP) {
 #pragma unroll
@@ -573,6 +575,11 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           forward_pass<H, BF, true>(xt, smem, Bl, tmp, z, a.var != nullptr);
 #pragma unroll
           for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
+          if constexpr (TRAIN && BF) {  // the pass's encoding, for the recomputation
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+              *reinterpret_cast<bf16x8*>(encc + p * 2048 + lane * 32 + 16 * jj) = tmp.v[0][0][jj];
+          }
         }
       }
 
@@ -597,7 +604,13 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
               for (int q = 0; q < (int)(sizeof(act.v[0][0]) / sizeof(act.v[0][0][0])); ++q)
                 act.v[l][b][q] = (p == 0) ? keep0.v[l][b][q] : keep1.v[l][b][q];
-        } else {  // recompute the activations of this pass
+        } else if constexpr (BF) {  // recompute from the pass's encoding kept in LDS
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+            act.v[0][0][jj] = *reinterpret_cast<const bf16x8*>(encc + p * 2048 + lane * 32 + 16 * jj);
+          float z[kOut];
+          forward_pass<H, BF, false, false>(nullptr, smem, Bl, act, z);
+        } else {
           float xt[4], z[kOut];
           point(p, xt);
           forward_pass<H, BF, false>(xt, smem, Bl, act, z, a.var != nullptr);
@@ -1527,14 +1540,21 @@ __device__ __forceinline__ float tile_sum(const float* __restrict__ partial, int
                                           int t1, int p) {
   float g = 0.f;
   int t = t0;
-  for (; t + 8 <= t1; t += 8) {
-    float x[8];
+  for (; t + 16 <= t1; t += 16) {
+    float x[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
+    for (int u = 0; u < 16; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) g += x[u];
+    for (int u = 0; u < 16; ++u) g += x[u];
   }
-  for (; t < t1; ++t) g += partial[(size_t)t * p_stride + p];
+  if (t < t1) {  // the rest, loads issued together, added in order
+    float x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = (t + u < t1) ? partial[(size_t)(t + u) * p_stride + p] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (t + u < t1) g += x[u];
+  }
   return g;
 }
 
@@ -1661,11 +1681,13 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   }
   if (!valid || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
   const int t = a.t_next[j];
-  const AdamCoef c = adam_coef(a, t);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < a.desc[k].n_params) {
+  const bool mine = p < a.desc[k].n_params;
+  // the partials' loads are issued before the block waits for the Adam coefficients
+  const float g = mine ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
+  const AdamCoef c = adam_coef(a, t);
+  if (mine) {
     const size_t i = (size_t)k * a.p_stride + p;
-    const float g = tile_sum(a.partial, a.p_stride, t0, t1, p);
     a.grad[i] = g;
     if (isfinite(g)) {
       float th = a.theta[i], m = a.m[i], v = a.v[i];
