@@ -83,7 +83,7 @@ def tune(workload: str = "k50_uneven", precision: str = "bf16", steps: int = 20,
     dev_batches = [DeviceBatch(scenes.make_batch(scene, s)) for s in range(4)]
     S = scene.S
     rpw = max(1, 64 // S)
-    rpts = list(rays_per_tile) or sorted({rpw * m for m in (2, 4, 8, 16)})
+    rpts = list(rays_per_tile) or sorted({rpw * m for m in (2, 4, 6, 8, 10, 12, 16, 20)})
     results = []
     for rpt in rpts:
         for w in waves:
@@ -111,11 +111,12 @@ def main():
     ap.add_argument("--waves", type=int, nargs="*", default=[2, 4])
     ap.add_argument("--grids", type=int, nargs="*", default=[0])
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--cache", default=CACHE, help="cache file to update")
     args = ap.parse_args()
     import sys
     sys.path.insert(0, os.path.dirname(HERE))
     best = tune(args.workload, args.precision, args.steps, args.rays_per_tile, args.waves,
-                args.grids, bool(args.graph))
+                args.grids, bool(args.graph), path=args.cache)
     print(json.dumps({k: v for k, v in best.items() if k != "swept"}))
 
 
