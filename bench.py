@@ -66,9 +66,10 @@ def tile_kernel_fingerprint() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, rays_per_tile: int, waves: int):
     """HBM bytes per launch of the tile kernel from the committed counter summary, or None if
-    the summary is missing or was taken on a different version of the kernel source."""
+    the summary is missing, was taken on a different version of the kernel source, or holds no
+    figure for this launch shape."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -80,7 +81,8 @@ def measured_traffic(precision: str):
             fields[key.strip()] = val.strip().strip("`")
     if fields.get("kernel source sha256") != tile_kernel_fingerprint():
         return None
-    val = fields.get(f"traffic bytes per launch ({precision})")
+    val = fields.get(f"traffic bytes per launch ({precision}, rays_per_tile {rays_per_tile}, "
+                     f"waves {waves})")
     return int(val.replace(",", "")) if val else None
 
 
@@ -148,9 +150,8 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     k_flops = statistics.mean(batch_flops(scene, dev_batches[i % len(dev_batches)])
                               for i in range(timing_steps))
     scale, skipped, err = objs.step_info()
-    launch = {"tuned": bool(objs.tuned)}
-    if objs.tuned:
-        launch.update({k: objs.tuned[k] for k in ("rays_per_tile", "waves", "grid")})
+    launch = {"tuned": bool(objs.tuned), "rays_per_tile": objs.rays_per_tile,
+              "waves": objs.waves, "grid": objs.grid}
     objs.close()
     return dict(
         precision=precision,
@@ -350,7 +351,9 @@ def main():
             2e-2 * abs(forms["fp32"]["final_loss"])
     flops = head["kernel_flops"]
     achieved = flops / (head["kernel_ms"] * 1e-3) if head["kernel_ms"] > 0 else 0.0
-    traffic = measured_traffic(prec) if args.workload == WORKLOAD else None
+    shape = head.get("launch", {})
+    traffic = (measured_traffic(prec, shape.get("rays_per_tile", 0), shape.get("waves", 0))
+               if args.workload == WORKLOAD else None)
     roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK[prec], traffic=traffic,
                     kernel="tile kernels (fused encode+MLP+render+loss+backward)",

@@ -228,6 +228,10 @@ class ObjectSet:
         self.ctx = ctx
         self.n_params: Dict[int, int] = {}
         self.p_stride = 0
+        # launch shape (the library's default tile: two sub-tiles of floor(64 / S) rays for each
+        # of four waves)
+        self.rays_per_tile = rays_per_tile or max(1, 64 // max_samples_per_ray) * 8
+        self.waves, self.grid = 4, 0
         if self.tuned:
             self.set_launch(int(self.tuned["waves"]), int(self.tuned["grid"]))
 
@@ -401,6 +405,7 @@ class ObjectSet:
 
     def set_launch(self, waves: int = 4, grid_blocks: int = 0):
         self._check(self.lib.vmap_set_launch(self.ctx, waves, grid_blocks))
+        self.waves, self.grid = int(waves), int(grid_blocks)
 
     def kernel_timing(self, enable: int = -1):
         avg = ctypes.c_double()
