@@ -54,14 +54,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_traffic_k50_uneven.md
 
 def tile_kernel_fingerprint() -> str:
     """SHA-256 of the source that defines the hidden-32 tile kernel: vmap_kernels.hip from the
-    activation types to the end of k_step_tiles, plus vmap_internal.h and vmap_math.h."""
+    activation types to the end of k_step_tiles, plus vmap_internal.h, vmap_math.h and
+    vmap_bf16.h."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2302_01838_amd", "csrc")
     k = open(os.path.join(csrc, "vmap_kernels.hip")).read()
     a = k.index("// Activations of one 32-sample pass")
     b = k.index("// Tile kernel for wide models")
     h = hashlib.sha256(k[a:b].encode())
-    for name in ("vmap_internal.h", "vmap_math.h"):
+    for name in ("vmap_internal.h", "vmap_math.h", "vmap_bf16.h"):
         h.update(open(os.path.join(csrc, name)).read().encode())
     return h.hexdigest()
 

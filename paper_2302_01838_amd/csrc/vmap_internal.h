@@ -45,6 +45,7 @@ struct LdsLayout {
   int whb_off;          // BF16: head weights [4][H + 8] BF16, permuted columns
   int whtb_off;         // BF16: head weights transposed [H][4] BF16
   int bh_off;           // head biases [4]
+  int bA_off;           // BF16: bias operand table [kLayers][H][16] (hi, mid, lo split)
   int B_off;            // encoding matrix [3][16] FP32
   int scratch_off;      // per-wave staging, then the tile's gradient sum
   int scratch_wave;     // bytes per wave
@@ -96,6 +97,8 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   if (bf16) off = round_up(off + H * kOut * 2, 16);
   L.bh_off = off;
   off = round_up(off + kOut * 4, 16);
+  L.bA_off = off;
+  if (bf16) off = round_up(off + kLayers * H * 32, 16);
   L.B_off = off;
   off = round_up(off + 3 * kFeatures * 4, 16);
   L.loss_off = off;

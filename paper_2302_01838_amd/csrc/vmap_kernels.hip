@@ -42,11 +42,10 @@
 
 #include "vmap_internal.h"
 #include "vmap_math.h"
+#include "vmap_bf16.h"
 
 namespace vmapi {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Accumulator row held in register r (0..15) by lanes of half h (0, 1) of a 32x32 MFMA tile.
@@ -166,6 +165,30 @@ __device__ void stage_weights(const float* __restrict__ th, unsigned char* smem,
   off += kOut * H;
   float* bh = reinterpret_cast<float*>(smem + L.bh_off);
   for (int e = tid; e < kOut; e += nt) bh[e] = th[off + e];
+  if constexpr (BF) {
+    // bias as an MFMA operand: b = hi + mid + lo exactly (three BF16 pieces of 8 bits each)
+    __bf16* bA = reinterpret_cast<__bf16*>(smem + L.bA_off);
+    int boff[kLayers];
+    int o2 = 0;
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+      const int K = (l == 0) ? kEnc : H;
+      boff[l] = o2 + H * K;
+      o2 += H * K + H;
+    }
+    for (int e = tid; e < kLayers * H; e += nt) {
+      const int l = e / H, row = e - l * H;
+      const float b = th[boff[l] + row];
+      const __bf16 hi = (__bf16)b;
+      const __bf16 mid = (__bf16)(b - (float)hi);
+      const __bf16 lo = (__bf16)((b - (float)hi) - (float)mid);
+      __bf16* dst = bA + (size_t)e * 16;
+      dst[0] = hi;
+      dst[1] = mid;
+      dst[2] = lo;
+      for (int q = 3; q < 16; ++q) dst[q] = (__bf16)0.0f;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -264,6 +287,13 @@ __device__ __forceinline__ void forward_pass(const float xt[4], const unsigned c
       f32x16 acc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+      if constexpr (BF) {  // accumulator starts at the bias (one MFMA, exact)
+        const bf16x8 ba = *reinterpret_cast<const bf16x8*>(
+            reinterpret_cast<const __bf16*>(smem + L.bA_off) + (l * H + mo * 32 + n) * 16 + 8 * hf);
+        const bf16x8 ones3 = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)0.0f,
+                              (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ba, ones3, acc, 0, 0, 0);
+      }
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         if constexpr (BF) {
@@ -282,9 +312,14 @@ __device__ __forceinline__ void forward_pass(const float xt[4], const unsigned c
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wrow[q], A.v[l][kb][q], acc, 0, 0, 0);
         }
       }
+      if constexpr (BF) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        A.set(l + 1, mo, r, fmaxf(acc[r] + bias[l * H + mo * 32 + rowof(r, hf)], 0.0f));
+        for (int jj = 0; jj < 2; ++jj) A.v[l + 1][mo][jj] = relu_round8(acc, 8 * jj);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          A.set(l + 1, mo, r, fmaxf(acc[r] + bias[l * H + mo * 32 + rowof(r, hf)], 0.0f));
+      }
     }
   }
   if constexpr (!WITH_HEAD) return;
@@ -638,7 +673,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
               reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[kLayers][mt][r];
           }
         wave_lds_sync();
-        float dl[MT][16];
+        Deltas<H, BF> dl;
         if constexpr (BF) {
           // output-layer weight gradient on MFMA 16x16x32: rows = the four outputs (padded to 16),
           // columns = 16 features, K = the pass's 32 samples
@@ -670,10 +705,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
             for (int r = 0; r < 16; ++r) acc[r] = 0.f;
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dzb, acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const float hv = (float)reinterpret_cast<const __bf16*>(htile)[(mt * 32 + rowof(r, hf)) * 40 + n];
-              dl[mt][r] = (hv > 0.f) ? acc[r] : 0.f;
-            }
+            for (int jj = 0; jj < 2; ++jj) dl.v[mt][jj] = relu_mask(round8(acc, 8 * jj), act.v[kLayers][mt][jj]);
           }
         } else {
           // output-layer weight gradient: lane owns feature mt*32 + n, half hf takes 16 samples
@@ -698,7 +730,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
               for (int c = 0; c < kOut; ++c) s += Wh[c * (H + 4) + mt * 32 + 16 * hf + r] * dz[c];
               const float hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mt * 32 + rowof(r, hf)];
-              dl[mt][r] = (hv > 0.f) ? s : 0.f;
+              dl.set(mt, r, (hv > 0.f) ? s : 0.f);
             }
         }
 #pragma unroll
@@ -711,8 +743,8 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int f = mt * 32 + rowof(r, hf);
-              if constexpr (BF) reinterpret_cast<__bf16*>(dtile)[f * 40 + n] = (__bf16)dl[mt][r];
-              else reinterpret_cast<float*>(dtile)[n * (H + 4) + f] = dl[mt][r];
+              if constexpr (BF) reinterpret_cast<__bf16*>(dtile)[f * 40 + n] = dl.v[mt][r >> 3][r & 7];
+              else reinterpret_cast<float*>(dtile)[n * (H + 4) + f] = dl.v[mt][r];
             }
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb)
@@ -760,7 +792,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           if (l == 0) break;
           // delta_{l-1} = (W_l^T delta_l) masked by ReLU' of layer l-1
           const int ws = L.w_stride[l];
-          float nd[MT][16];
+          Deltas<H, BF> nd;
 #pragma unroll
           for (int mi = 0; mi < MT; ++mi) {
             f32x16 acc;
@@ -776,31 +808,28 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
                   const bf16x8 wa = *reinterpret_cast<const bf16x8*>(Wt + 8 * jj);
-                  bf16x8 db;
-#pragma unroll
-                  for (int e = 0; e < 8; ++e) db[e] = (__bf16)dl[ko][8 * jj + e];
-                  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, db, acc, 0, 0, 0);
+                  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dl.v[ko][jj], acc, 0, 0, 0);
                 }
               } else {
                 const float* W = reinterpret_cast<const float*>(smem + L.w_off[l]);
 #pragma unroll
                 for (int qq = 0; qq < 16; ++qq)
                   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W[(ko * 32 + rowof(qq, hf)) * ws + col],
-                                                             dl[ko][qq], acc, 0, 0, 0);
+                                                             dl.v[ko][qq], acc, 0, 0, 0);
               }
             }
+            if constexpr (BF) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              float hv;
-              if constexpr (BF) hv = (float)reinterpret_cast<const __bf16*>(htile)[(mi * 32 + rowof(r, hf)) * 40 + n];
-              else hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mi * 32 + rowof(r, hf)];
-              nd[mi][r] = (hv > 0.f) ? acc[r] : 0.f;
+              for (int jj = 0; jj < 2; ++jj) nd.v[mi][jj] = relu_mask(round8(acc, 8 * jj), act.v[l][mi][jj]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const float hv = reinterpret_cast<const float*>(htile)[n * (H + 4) + mi * 32 + rowof(r, hf)];
+                nd.set(mi, r, (hv > 0.f) ? acc[r] : 0.f);
+              }
             }
           }
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) dl[mt][r] = nd[mt][r];
+          dl = nd;
         }
       }
     }  // sub-tiles
