@@ -67,10 +67,10 @@ def tile_kernel_fingerprint() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str, rays_per_tile: int, waves: int):
-    """HBM bytes per launch of the tile kernel from the committed counter summary, or None if
+def measured_traffic(precision: str, rays_per_tile: int, waves: int, split_step: bool = False):
+    """HBM bytes per launch of the timed kernel from the committed counter summary, or None if
     the summary is missing, was taken on a different version of the kernel source, or holds no
-    figure for this launch shape."""
+    figure for this launch shape and step form."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -82,8 +82,9 @@ def measured_traffic(precision: str, rays_per_tile: int, waves: int):
             fields[key.strip()] = val.strip().strip("`")
     if fields.get("kernel source sha256") != tile_kernel_fingerprint():
         return None
+    form = "split" if split_step else "table"
     val = fields.get(f"traffic bytes per launch ({precision}, rays_per_tile {rays_per_tile}, "
-                     f"waves {waves})")
+                     f"waves {waves}, {form})")
     return int(val.replace(",", "")) if val else None
 
 
@@ -111,14 +112,14 @@ def batch_flops(scene, db) -> float:
 
 
 def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
-             rays_per_tile_wide=0):
+             rays_per_tile_wide=0, split_step=False):
     import torch
     import paper_2302_01838_amd as vm
     nrays = max(db.n_rays for db in dev_batches)
     objs = vm.ObjectSet(max_objects=scene.n_objects, B=scene.B, hidden=scene.objects[0].hidden,
                         max_hidden=max(o.hidden for o in scene.objects), precision=precision,
                         max_rays=nrays, max_samples_per_ray=scene.S,
-                        rays_per_tile_wide=rays_per_tile_wide)
+                        rays_per_tile_wide=rays_per_tile_wide, split_step=split_step)
     for ob in scene.objects:
         objs.add(ob.norm_centre, ob.norm_scale, hidden=ob.hidden, seed=ob.seed)
     objs.set_graph_mode(graph)
@@ -152,7 +153,7 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
                               for i in range(timing_steps))
     scale, skipped, err = objs.step_info()
     launch = {"tuned": bool(objs.tuned), "rays_per_tile": objs.rays_per_tile,
-              "waves": objs.waves, "grid": objs.grid}
+              "waves": objs.waves, "grid": objs.grid, "split_step": bool(split_step)}
     objs.close()
     return dict(
         precision=precision,
@@ -281,7 +282,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--graph", type=int, default=1, help="replay the step as a hipGraph")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="replay the step as a hipGraph (slower here: hipGraphLaunch costs more "
+                         "host time than the three plain launches)")
+    ap.add_argument("--split-step", action="store_true",
+                    help="a separate work-list launch before the tile kernel (default: the tile "
+                         "kernel builds its work list)")
     ap.add_argument("--distinct-batches", type=int, default=0,
                     help="distinct pre-generated batches (default: warmup + steps)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -339,7 +345,8 @@ def main():
         log(f"form {prec}: {args.warmup} warmup + {args.steps} timed steps")
         forms[prec] = run_form(prec, scene, dev_batches, args.steps, args.warmup,
                                bool(args.graph), timing_steps=min(args.steps, 50),
-                               rays_per_tile_wide=args.rays_per_tile_wide)
+                               rays_per_tile_wide=args.rays_per_tile_wide,
+                               split_step=args.split_step)
         log(f"form {prec}: {forms[prec]['ms_per_step']:.4f} ms/step, "
             f"{forms[prec]['ray_samples_per_s']:.4g} samples/s, final loss "
             f"{forms[prec]['final_loss']:.6g}")
@@ -353,11 +360,15 @@ def main():
     flops = head["kernel_flops"]
     achieved = flops / (head["kernel_ms"] * 1e-3) if head["kernel_ms"] > 0 else 0.0
     shape = head.get("launch", {})
-    traffic = (measured_traffic(prec, shape.get("rays_per_tile", 0), shape.get("waves", 0))
+    traffic = (measured_traffic(prec, shape.get("rays_per_tile", 0), shape.get("waves", 0),
+                                shape.get("split_step", False))
                if args.workload == WORKLOAD else None)
+    kname = ("tile kernel (encode+MLP+render+loss+backward; work list launched apart)"
+             if shape.get("split_step") else
+             "tile kernel (work list built in-kernel, encode+MLP+render+loss+backward)")
     roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK[prec], traffic=traffic,
-                    kernel="tile kernels (fused encode+MLP+render+loss+backward)",
+                    kernel=kname,
                     kernel_avg_ms=head["kernel_ms"], flop_per_launch=flops)
     log(f"cpu baseline: oracle for up to {args.cpu_budget:.0f} s")
     cpu = cpu_baseline(scene, batches, args.cpu_budget, args.workload)

@@ -80,7 +80,11 @@ typedef struct {
   int32_t scale_growth_interval;/* BF16: good steps before the loss scale doubles (2000) */
   int32_t rays_per_tile_wide;   /* rays per work tile of objects wider than 32; 0 = one round
                                  * of the cooperative kernel (4 waves x floor(64 / S) rays) */
-  int32_t reserved;
+  int32_t split_step;           /* 0: when every object has width 32 and a batch has at most
+                                 * 2048 objects, the training step's tile kernel builds its work
+                                 * list itself (two launches per step: tiles, then gradient sums
+                                 * and Adam); 1: always a separate work-list launch first (three).
+                                 * Results are bitwise the same either way. */
   double lr;                    /* Adam learning rate (1e-3) */
   double beta1, beta2, eps;     /* Adam moments (0.9, 0.999) and epsilon (1e-8) */
   double lambda_colour;         /* lambda_1 of Eq. 7 (5) */

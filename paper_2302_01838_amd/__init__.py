@@ -46,7 +46,7 @@ class VmapConfig(ctypes.Structure):
                 ("max_hidden", ctypes.c_int32), ("max_samples_per_ray", ctypes.c_int32),
                 ("max_rays", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rays_per_tile", ctypes.c_int32), ("scale_growth_interval", ctypes.c_int32),
-                ("rays_per_tile_wide", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rays_per_tile_wide", ctypes.c_int32), ("split_step", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double), ("lambda_colour", ctypes.c_double),
                 ("lambda_occ", ctypes.c_double), ("loss_scale_init", ctypes.c_double)]
@@ -191,7 +191,8 @@ class ObjectSet:
                  rays_per_tile_wide: int = 0, lr: float = 1e-3,
                  betas=(0.9, 0.999), eps: float = 1e-8, lambda_colour: float = 5.0,
                  lambda_occ: float = 10.0, loss_scale_init: float = 4096.0,
-                 scale_growth_interval: int = 2000, device=None, autotune: bool = True):
+                 scale_growth_interval: int = 2000, device=None, autotune: bool = True,
+                 split_step: bool = False):
         torch = _torch()
         self.lib = load_library()
         self.device = device or torch.device("cuda", torch.cuda.current_device())
@@ -209,7 +210,8 @@ class ObjectSet:
             rays_per_tile=rays_per_tile, rays_per_tile_wide=rays_per_tile_wide,
             scale_growth_interval=scale_growth_interval, lr=lr,
             beta1=betas[0], beta2=betas[1], eps=eps, lambda_colour=lambda_colour,
-            lambda_occ=lambda_occ, loss_scale_init=loss_scale_init)
+            lambda_occ=lambda_occ, loss_scale_init=loss_scale_init,
+            split_step=1 if split_step else 0)
         self.precision = precision
         sb = self.lib.vmap_state_bytes(ctypes.byref(self.cfg))
         wb = self.lib.vmap_workspace_bytes(ctypes.byref(self.cfg))

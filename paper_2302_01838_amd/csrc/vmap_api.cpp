@@ -29,7 +29,7 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, t_next, batch, tile_loss, partial, wimage, total;
+  size_t tile_start, flags, t_next, batch, tile_bad, tile_loss, partial, wimage, total;
   size_t wimage_stride;
   int max_tiles;
 };
@@ -51,6 +51,7 @@ const char* check_config(const vmap_config* c) {
   if (c->rays_per_tile < 0 || c->rays_per_tile > (1 << 16)) return "rays_per_tile must be in [0, 65536]";
   if (c->rays_per_tile_wide < 0 || c->rays_per_tile_wide > (1 << 16))
     return "rays_per_tile_wide must be in [0, 65536]";
+  if (c->split_step != 0 && c->split_step != 1) return "split_step must be 0 or 1";
   if (!(c->lr > 0.0) || !(c->beta1 >= 0.0 && c->beta1 < 1.0) || !(c->beta2 >= 0.0 && c->beta2 < 1.0) ||
       !(c->eps > 0.0))
     return "Adam settings out of range (lr > 0, 0 <= beta < 1, eps > 0)";
@@ -115,6 +116,7 @@ WorkLayout work_layout(const vmap_config* c) {
   w.t_next = off; off = align256(off + (size_t)c->max_objects * 4);
   w.batch = off; off = align256(off + sizeof(BatchDev));
   w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
+  w.tile_bad = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.partial = off; off = align256(off + (size_t)w.max_tiles * ps * 4);
   // weight images of wide objects (weights read from device memory by the tile kernel)
   const bool bf = c->precision == VMAP_BF16;
@@ -185,6 +187,7 @@ struct vmap_ctx {
   int32_t* flags() { return reinterpret_cast<int32_t*>(work + wl.flags); }
   int32_t* t_next() { return reinterpret_cast<int32_t*>(work + wl.t_next); }
   BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
+  int32_t* tile_bad() { return reinterpret_cast<int32_t*>(work + wl.tile_bad); }
   float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
   float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
   unsigned char* wimage() { return wl.wimage_stride ? work + wl.wimage : nullptr; }
@@ -375,8 +378,52 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
   return VMAP_OK;
 }
 
+// Training step whose tile kernel builds the tile table itself (no work-list launch), used when
+// every registered object has width 32, the batch fits the kernel's LDS table and the
+// configuration does not ask for the separate work-list launch.
+bool table_in_tiles(vmap_ctx* c, const vmap_batch* b) {
+  if (c->cfg.split_step || b->n_objects > kTableMaxObjects) return false;
+  const std::vector<int> w = widths_present(c);
+  return w.size() == 1 && w[0] == 32;
+}
+
+int enqueue_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing,
+                 const BatchDev* bd) {
+  StepArgs a = make_step_args(c, b);
+  a.bd = bd;
+  a.use_scale = c->cfg.precision == VMAP_BF16 ? 1 : 0;
+  a.hidden = 32;
+  a.tile_start_out = c->tile_start();
+  a.t_next = c->t_next();
+  a.tile_bad = c->tile_bad();
+  int grid = (b->n_rays_total + c->rays_per_tile - 1) / c->rays_per_tile + b->n_objects;
+  if (c->grid_blocks > 0) grid = std::min(grid, c->grid_blocks);
+  TimedLaunch tl{};
+  const bool timed = allow_timing && c->timing;
+  if (timed) {
+    tl.a = pooled_event(c);
+    tl.b = pooled_event(c);
+    if (!tl.a || !tl.b) return c->fail(VMAP_EHIP, "hipEventCreate failed");
+    hipError_t e = hipEventRecord(tl.a, s);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+  }
+  hipError_t e = launch_tiles(32, c->cfg.precision == VMAP_BF16, MODE_STEP, a, c->waves, grid, s);
+  if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
+  if (timed) {
+    e = hipEventRecord(tl.b, s);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+    c->timed.push_back(tl);
+  }
+  OptArgs o = make_opt_args(c, b, loss_out, nullptr, bd);
+  o.tile_bad = c->tile_bad();
+  e = launch_optimizer(OPT_REDUCE_ADAM, o, s);
+  if (e != hipSuccess) return c->hip_fail(e, "gradient/Adam launch");
+  return VMAP_OK;
+}
+
 int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing,
                   const BatchDev* bd = nullptr) {
+  if (table_in_tiles(c, b)) return enqueue_step(c, b, loss_out, s, allow_timing, bd);
   hipError_t e = enqueue_worklist(c, b, s, bd);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
   int rc = enqueue_tiles(c, b, MODE_TRAIN, nullptr, nullptr, nullptr, nullptr, s, allow_timing, bd);

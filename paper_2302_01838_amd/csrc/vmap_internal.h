@@ -13,8 +13,10 @@ constexpr int kOut = 4;              // (r, g, b, occupancy)
 constexpr int kLayers = 4;           // hidden ReLU layers
 constexpr int kWave = 64;
 constexpr int kSlots = 64;           // sample slots per wave sub-tile (two MFMA column blocks)
+constexpr int kTableMaxObjects = 2048;  // batch objects MODE_STEP keeps in its LDS tile table
 
-enum Mode { MODE_FWD = 0, MODE_TRAIN = 1 };
+// MODE_STEP: training whose tile kernel builds the tile table itself (no work-list launch).
+enum Mode { MODE_FWD = 0, MODE_TRAIN = 1, MODE_STEP = 2 };
 
 // Per-object descriptor in device memory (one slot per possible object id).
 struct ObjDesc {
@@ -172,6 +174,33 @@ struct BatchDev {
   const float* var;
 };
 
+// Arguments of the gradient / optimiser kernels.
+struct OptArgs {
+  int n_objects;
+  const int32_t* ids;
+  const int32_t* offs;        // ray offsets of the batch
+  const int32_t* tile_start;
+  const float* partial;
+  const float* tile_loss;
+  const int32_t* t_next;      // per batch object, from k_worklist
+  const int32_t* tile_bad;    // [tiles] non-finite partial per tile (MODE_STEP), or NULL: flags
+  int p_stride;
+  int max_objects;
+  ObjDesc* desc;
+  ScalerState* scaler;
+  int32_t* flags;
+  float* theta;
+  float* m;
+  float* v;
+  float* grad;
+  float* grad_out;
+  float* loss_out;
+  double lr, beta1, beta2, eps;
+  int bf16;
+  int growth;
+  const BatchDev* bd;         // if not NULL, n_objects, ids, offs and loss_out come from here
+};
+
 struct StepArgs {
   // batch
   int n_objects;
@@ -210,6 +239,13 @@ struct StepArgs {
   const BatchDev* bd;         // if not NULL, the batch fields above are read from here
   unsigned char* wimage;      // weight images of wide objects, [max_objects][wimage_stride]
   int64_t wimage_stride;
+  // MODE_STEP only: the tile table (in LDS at byte offset lds_table) is also written to
+  // tile_start_out, with the next Adam step counts (t_next) and cleared flags, for the optimiser;
+  // tiles report a non-finite partial in tile_bad [tiles].
+  int32_t* tile_start_out;
+  int32_t* t_next;
+  int32_t* tile_bad;
+  int lds_table;
 };
 
 struct QueryArgs {
@@ -227,31 +263,6 @@ struct QueryArgs {
   int max_objects;
 };
 
-// Arguments of the gradient / optimiser kernels.
-struct OptArgs {
-  int n_objects;
-  const int32_t* ids;
-  const int32_t* offs;        // ray offsets of the batch
-  const int32_t* tile_start;
-  const float* partial;
-  const float* tile_loss;
-  const int32_t* t_next;      // per batch object, from k_worklist
-  int p_stride;
-  int max_objects;
-  ObjDesc* desc;
-  ScalerState* scaler;
-  int32_t* flags;
-  float* theta;
-  float* m;
-  float* v;
-  float* grad;
-  float* grad_out;
-  float* loss_out;
-  double lr, beta1, beta2, eps;
-  int bf16;
-  int growth;
-  const BatchDev* bd;         // if not NULL, n_objects, ids, offs and loss_out come from here
-};
 
 // Scene rendering (Sec. 3.4): rays against the bounds of a list of objects.
 struct SceneArgs {

@@ -64,7 +64,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+// Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
+// division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float sgnf(float x) { return (x > 0.f) ? 1.f : ((x < 0.f) ? -1.f : 0.f); }
 
 template <bool BF>
@@ -97,12 +99,24 @@ struct Acts<H, false> {
   float v[kLayers + 1][H / 32][16];
   __device__ __forceinline__ float get(int l, int b, int r) const { return v[l][b][r]; }
   __device__ __forceinline__ void set(int l, int b, int r, float x) { v[l][b][r] = x; }
+  // registers r and r + 1 (r even)
+  __device__ __forceinline__ void set2(int l, int b, int r, float x, float y) {
+    v[l][b][r] = x;
+    v[l][b][r + 1] = y;
+  }
 };
 template <int H>
 struct Acts<H, true> {
   bf16x8 v[kLayers + 1][H / 32][2];
   __device__ __forceinline__ float get(int l, int b, int r) const { return (float)v[l][b][r >> 3][r & 7]; }
   __device__ __forceinline__ void set(int l, int b, int r, float x) { v[l][b][r >> 3][r & 7] = (__bf16)x; }
+  // registers r and r + 1 (r even), rounded as one packed pair
+  __device__ __forceinline__ void set2(int l, int b, int r, float x, float y) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 w = __builtin_bit_cast(u4, v[l][b][r >> 3]);
+    w[(r & 7) >> 1] = pack2(x, y);
+    v[l][b][r >> 3] = __builtin_bit_cast(bf16x8, w);
+  }
 };
 
 // Back-propagated deltas of one 32-sample pass in the accumulator layout. In BF16 mode they only
@@ -216,20 +230,23 @@ __device__ __forceinline__ void forward_pass(const float xt[4], const unsigned c
 #pragma unroll
   for (int g = 0; g < (ENC ? 2 : 0); ++g) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int f = 8 * g + 4 * hf + i;
-      const float phi = xt[0] * Bm[f] + xt[1] * Bm[kFeatures + f] + xt[2] * Bm[2 * kFeatures + f];
-      float s, c;
-      vmap_sincosf(phi, &s, &c);
-      if (ipe) {  // expectation under N(x, v I): attenuation exp(-v |b_f|^2 / 2)
-        const float nb = Bm[f] * Bm[f] + Bm[kFeatures + f] * Bm[kFeatures + f] +
-                         Bm[2 * kFeatures + f] * Bm[2 * kFeatures + f];
-        const float att = expf(-0.5f * xt[3] * nb);
-        s *= att;
-        c *= att;
+    for (int i = 0; i < 4; i += 2) {  // two features at a time: one packed pair per half
+      float s[2], c[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int f = 8 * g + 4 * hf + i + u;
+        const float phi = xt[0] * Bm[f] + xt[1] * Bm[kFeatures + f] + xt[2] * Bm[2 * kFeatures + f];
+        vmap_sincosf(phi, &s[u], &c[u]);
+        if (ipe) {  // expectation under N(x, v I): attenuation exp(-v |b_f|^2 / 2)
+          const float nb = Bm[f] * Bm[f] + Bm[kFeatures + f] * Bm[kFeatures + f] +
+                           Bm[2 * kFeatures + f] * Bm[2 * kFeatures + f];
+          const float att = expf(-0.5f * xt[3] * nb);
+          s[u] *= att;
+          c[u] *= att;
+        }
       }
-      A.set(0, 0, 4 * g + i, s);
-      A.set(0, 0, 8 + 4 * g + i, c);
+      A.set2(0, 0, 4 * g + i, s[0], s[1]);
+      A.set2(0, 0, 8 + 4 * g + i, c[0], c[1]);
     }
   }
   if constexpr (weights_global(H)) {
@@ -468,15 +485,165 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
   }
   float Snext = __shfl_down(Bq, 1);
   if (si == S - 1) Snext = 0.f;
-  if (valid) {
-    const float dO = Pex * (g - Snext);
-    dzs[3] = dO * o * q;
+  // selects, not branches: with stores under divergent branches the compiler kept dzs in
+  // scratch memory
+  const float dO = Pex * (g - Snext);
+  dzs[3] = valid ? dO * o * q : 0.f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) dzs[c] = Tw * aC[c] * c3[c] * cq[c];
-  } else {
+  for (int c = 0; c < 3; ++c) dzs[c] = valid ? Tw * aC[c] * c3[c] * cq[c] : 0.f;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-object gradient and optimiser. Tile partials are already unscaled by the tile kernel, which
+// also flagged objects with a non-finite partial. Three kernels share the pieces below:
+//   k_reduce      — loss and gradient per object (forward/backward split),
+//   k_adam        — Adam from the stored gradient (after k_reduce),
+//   k_reduce_adam — both in one pass (the training step when it is split into launches).
+// The optimiser kernels take each object's next step count from the work-list kernel; block
+// (0, j) writes it back, block (0, 0) updates the loss scaler from the flags. No block reads what
+// another block of the same launch writes, so no device-scope fence is needed. The one-launch
+// training step (MODE_STEP, below) runs the same sum and update inside the tile kernel.
+
+// Sum of an object's tile partials at parameter p, in tile order; loads are issued eight at a
+// time and added in order.
+__device__ __forceinline__ float tile_sum(const float* __restrict__ partial, int p_stride, int t0,
+                                          int t1, int p) {
+  float g = 0.f;
+  int t = t0;
+  for (; t + 16 <= t1; t += 16) {
+    float x[16];
 #pragma unroll
-    for (int c = 0; c < kOut; ++c) dzs[c] = 0.f;
+    for (int u = 0; u < 16; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) g += x[u];
   }
+  if (t < t1) {  // the rest, loads issued together, added in order
+    float x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = (t + u < t1) ? partial[(size_t)(t + u) * p_stride + p] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (t + u < t1) g += x[u];
+  }
+  return g;
+}
+
+
+__device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
+  return k >= 0 && k < a.max_objects && a.desc[k].registered;
+}
+
+// Whether batch object j (id k) had a non-finite tile partial: its flag, or with per-tile
+// reports the OR of its tiles' entries. Called by every thread of the workgroup.
+__device__ __forceinline__ bool object_bad(const OptArgs& a, int j, int k) {
+  if (!a.tile_bad) return a.flags[k] != 0;
+  int bad = 0;
+  for (int t = a.tile_start[j] + (int)threadIdx.x; t < a.tile_start[j + 1]; t += blockDim.x)
+    bad |= a.tile_bad[t];
+  return __syncthreads_or(bad) != 0;
+}
+
+// One workgroup (any size): count the batch objects with rays whose gradient was not finite;
+// BF16 loss scaler.
+__device__ void scaler_update(const OptArgs& a) {
+  __shared__ int count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  int skipped = 0;
+  for (int jj = threadIdx.x; jj < a.n_objects; jj += blockDim.x) {
+    const int kk = a.ids[jj];
+    if (!obj_valid(a, kk) || a.offs[jj + 1] <= a.offs[jj]) continue;
+    bool bad = false;
+    if (a.tile_bad) {  // from the tiles: the objects' flags are being written by this launch
+      for (int t = a.tile_start[jj]; t < a.tile_start[jj + 1]; ++t) bad |= a.tile_bad[t] != 0;
+    } else {
+      bad = a.flags[kk] != 0;
+    }
+    if (bad) ++skipped;
+  }
+  if (skipped) atomicAdd(&count, skipped);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int total = count;
+    a.scaler->skipped = total;
+    if (a.bf16) {
+      if (total > 0) {
+        a.scaler->scale *= 0.5f;
+        a.scaler->good_steps = 0;
+      } else if (++a.scaler->good_steps >= a.growth) {
+        a.scaler->scale *= 2.0f;
+        a.scaler->good_steps = 0;
+      }
+    }
+  }
+}
+
+struct AdamCoef {
+  float step, rs, b1, c1, b2, c2, eps;
+};
+
+// Bias-corrected step size and 1/sqrt(bias correction of v) in FP64, then rounded once.
+__device__ AdamCoef adam_coef(const OptArgs& a, int t) {
+  __shared__ float sh[2];
+  if (threadIdx.x == 0) {
+    const double bc1 = 1.0 - pow(a.beta1, (double)t), bc2 = 1.0 - pow(a.beta2, (double)t);
+    sh[0] = (float)(a.lr / bc1);
+    sh[1] = (float)(1.0 / sqrt(bc2));
+  }
+  __syncthreads();
+  return AdamCoef{sh[0], sh[1], (float)a.beta1, (float)(1.0 - a.beta1), (float)a.beta2,
+                  (float)(1.0 - a.beta2), (float)a.eps};
+}
+
+__device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th, float& m, float& v) {
+  m = c.b1 * m + c.c1 * g;
+  v = c.b2 * v + c.c2 * g * g;
+  th = th - c.step * m / (sqrtf(v) * c.rs + c.eps);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Training step without a work-list launch (MODE_STEP). Every workgroup of the tile kernel scans
+// the batch's ray offsets into a tile table in LDS (what k_worklist writes to device memory);
+// workgroup 0 also leaves in device memory what k_worklist leaves for the optimiser: the table,
+// the next Adam step counts and cleared flags. Tiles then report a non-finite partial in their
+// own tile_bad entry instead of the object's flag (which workgroup 0 may clear concurrently), and
+// k_reduce_adam reads those entries.
+
+// tbl[j] = first tile of batch object j, tbl[n_objects] = tiles: the exclusive scan of
+// ceil(rays_j / rays_per_tile) over the batch (the launch's objects share one width, so one tile
+// size). Returns the tile count. Called by every thread of the workgroup.
+__device__ int step_table(const StepArgs& a, int32_t* tbl) {
+  __shared__ int wtot[4];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int rpt = a.rays_per_tile;
+  int carry = 0;
+  for (int base = 0; base < a.n_objects; base += nt) {
+    const int j = base + tid;
+    int cnt = 0;
+    if (j < a.n_objects) {
+      const int nr = a.ray_offsets[j + 1] - a.ray_offsets[j];
+      cnt = nr > 0 ? (nr + rpt - 1) / rpt : 0;
+    }
+    int x = cnt;  // inclusive scan over the wave
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wtot[wave] = x;
+    __syncthreads();
+    int before = carry, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int v = wtot[w];
+      if (w < wave) before += v;
+      total += v;
+    }
+    if (j < a.n_objects) tbl[j] = before + x - cnt;
+    carry += total;
+    __syncthreads();
+  }
+  if (tid == 0) tbl[a.n_objects] = carry;
+  __syncthreads();
+  return carry;
 }
 
 template <int H, bool BF, int MODE>
@@ -484,7 +651,8 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   StepArgs a = a_in;
   read_batch(a);
   constexpr int MT = H / 32;
-  constexpr bool TRAIN = (MODE == MODE_TRAIN);
+  constexpr bool TABLE = (MODE == MODE_STEP);  // tile table built here, not by k_worklist
+  constexpr bool TRAIN = (MODE == MODE_TRAIN) || TABLE;
   constexpr bool KEEP = TRAIN && !BF;  // activations kept across the rendering (no recompute)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr LdsLayout L = lds_layout(H, BF, 1);
@@ -492,18 +660,36 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   const int n = lane & 31, hf = lane >> 5;
   const int S = a.S;
   const int rpw = kSlots / S;
-  const int n_tiles = a.tile_start[a.n_objects];
+
+  // first tile of every batch object: from the LDS table or from k_worklist
+  int32_t* tbl = reinterpret_cast<int32_t*>(smem + a.lds_table);
+  auto first_tile = [&](int j) { return TABLE ? tbl[j] : a.tile_start[j]; };
+  int n_tiles;
+  if constexpr (TABLE) {
+    n_tiles = step_table(a, tbl);
+    if (blockIdx.x == 0) {  // what k_worklist leaves for the optimiser
+      for (int j = tid; j <= a.n_objects; j += blockDim.x) a.tile_start_out[j] = tbl[j];
+      for (int j = tid; j < a.n_objects; j += blockDim.x) {
+        const int k = a.object_ids[j];
+        const bool valid = k >= 0 && k < a.max_objects;
+        if (valid) a.flags[k] = 0;
+        a.t_next[j] = (valid && a.desc[k].registered) ? a.desc[k].step + 1 : 0;
+      }
+    }
+  } else {
+    n_tiles = a.tile_start[a.n_objects];
+  }
 
   float* Bl = reinterpret_cast<float*>(smem + L.B_off);
   if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
   int staged = -1;
 
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    // object of this tile: largest j with tile_start[j] <= tile
+    // object of this tile: largest j with first_tile(j) <= tile
     int jlo = 0, jhi = a.n_objects;
     while (jhi - jlo > 1) {
       const int mid = (jlo + jhi) >> 1;
-      if (a.tile_start[mid] <= tile) jlo = mid; else jhi = mid;
+      if (first_tile(mid) <= tile) jlo = mid; else jhi = mid;
     }
     const int j = jlo;
     const int k = a.object_ids[j];
@@ -513,7 +699,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     }
     if (a.desc[k].hidden != H) continue;  // handled by the launch for that width
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
-    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * rpt;
+    const int ray_lo = a.ray_offsets[j] + (tile - first_tile(j)) * rpt;
     const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
     if (k != staged) {
       __syncthreads();
@@ -770,10 +956,15 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
                   const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
                       reinterpret_cast<const __bf16*>(htile) + (ki * 32 + n) * 40 + 16 * jj + 8 * hf);
                   accW[l][mo][ki] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, hb, accW[l][mo][ki], 0, 0, 0);
-                  if (ki == 0) {
+                  if (ki == 0) {  // bias gradient: the 8 deltas' sum, two at a time (v_dot2)
+                    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+                    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+                    const u4 dw = __builtin_bit_cast(u4, da);
+                    const b2 ones = {(__bf16)1.0f, (__bf16)1.0f};
                     float s = 0.f;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) s += (float)da[e];
+                    for (int e = 0; e < 4; ++e)
+                      s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, (unsigned int)dw[e]), ones, s, false);
                     accDb[l][mo] += s;
                   }
                 }
@@ -923,11 +1114,14 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       for (int e = tid; e < P; e += blockDim.x) {
         const float g = red[e] * inv;
         bad |= !isfinite(g);
-        dst[e] = g;
+        __builtin_nontemporal_store(g, &dst[e]);  // read once, by the next kernel
       }
       if (bad) *any_bad = 1;  // every writer stores the same value
       __syncthreads();
-      if (tid == 0 && *any_bad) atomicOr(&a.flags[k], 1);
+      if (tid == 0) {
+        if constexpr (TABLE) a.tile_bad[tile] = *any_bad;
+        else if (*any_bad) atomicOr(&a.flags[k], 1);
+      }
     }
     if (tid == 0) a.tile_loss[tile] = lsum[0];
     __syncthreads();
@@ -1553,97 +1747,6 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
   if (tid == nt - 1) tile_start[n_objects] = part[nt - 1];
 }
 
-// ---------------------------------------------------------------------------------------------
-// Per-object gradient and optimiser. Tile partials are already unscaled by the tile kernel, which
-// also flagged objects with a non-finite partial. Three kernels share the pieces below:
-//   k_reduce      — loss and gradient per object (forward/backward split),
-//   k_adam        — Adam from the stored gradient (after k_reduce),
-//   k_reduce_adam — both in one pass (the training step).
-// The optimiser kernels take each object's next step count from the work-list kernel; block
-// (0, j) writes it back, block (0, 0) updates the loss scaler from the flags. No block reads what
-// another block of the same launch writes, so no device-scope fence is needed.
-
-// Sum of an object's tile partials at parameter p, in tile order; loads are issued eight at a
-// time and added in order.
-__device__ __forceinline__ float tile_sum(const float* __restrict__ partial, int p_stride, int t0,
-                                          int t1, int p) {
-  float g = 0.f;
-  int t = t0;
-  for (; t + 16 <= t1; t += 16) {
-    float x[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) g += x[u];
-  }
-  if (t < t1) {  // the rest, loads issued together, added in order
-    float x[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = (t + u < t1) ? partial[(size_t)(t + u) * p_stride + p] : 0.f;
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (t + u < t1) g += x[u];
-  }
-  return g;
-}
-
-
-__device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
-  return k >= 0 && k < a.max_objects && a.desc[k].registered;
-}
-
-// Block (0, 0): count the batch objects with rays whose gradient was not finite; BF16 scaler.
-__device__ void scaler_update(const OptArgs& a) {
-  __shared__ int red[256];
-  int skipped = 0;
-  for (int jj = threadIdx.x; jj < a.n_objects; jj += blockDim.x) {
-    const int kk = a.ids[jj];
-    if (obj_valid(a, kk) && a.offs[jj + 1] > a.offs[jj] && a.flags[kk]) ++skipped;
-  }
-  red[threadIdx.x] = skipped;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const int total = red[0];
-    a.scaler->skipped = total;
-    if (a.bf16) {
-      if (total > 0) {
-        a.scaler->scale *= 0.5f;
-        a.scaler->good_steps = 0;
-      } else if (++a.scaler->good_steps >= a.growth) {
-        a.scaler->scale *= 2.0f;
-        a.scaler->good_steps = 0;
-      }
-    }
-  }
-}
-
-struct AdamCoef {
-  float step, rs, b1, c1, b2, c2, eps;
-};
-
-// Bias-corrected step size and 1/sqrt(bias correction of v) in FP64, then rounded once.
-__device__ AdamCoef adam_coef(const OptArgs& a, int t) {
-  __shared__ float sh[2];
-  if (threadIdx.x == 0) {
-    const double bc1 = 1.0 - pow(a.beta1, (double)t), bc2 = 1.0 - pow(a.beta2, (double)t);
-    sh[0] = (float)(a.lr / bc1);
-    sh[1] = (float)(1.0 / sqrt(bc2));
-  }
-  __syncthreads();
-  return AdamCoef{sh[0], sh[1], (float)a.beta1, (float)(1.0 - a.beta1), (float)a.beta2,
-                  (float)(1.0 - a.beta2), (float)a.eps};
-}
-
-__device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th, float& m, float& v) {
-  m = c.b1 * m + c.c1 * g;
-  v = c.b2 * v + c.c2 * g * g;
-  th = th - c.step * m / (sqrtf(v) * c.rs + c.eps);
-}
-
 __global__ void __launch_bounds__(256) k_reduce(const OptArgs a_in, int want_grad) {
   OptArgs a = a_in;
   read_batch(a);
@@ -1708,7 +1811,11 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
       for (int t = t0; t < t1; ++t) s += a.tile_loss[t];
     a.loss_out[j] = s;
   }
-  if (!valid || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
+  if (!valid || a.offs[j + 1] <= a.offs[j]) return;
+  if (object_bad(a, j, k)) {
+    if (a.tile_bad && blockIdx.x == 0 && threadIdx.x == 0) a.flags[k] = 1;
+    return;
+  }
   const int t = a.t_next[j];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool mine = p < a.desc[k].n_params;
@@ -2047,14 +2154,21 @@ static hipError_t allow_lds(const void* fn, int bytes, int* allowed) {
 }
 
 template <int H, bool BF, int MODE>
-static hipError_t launch_tiles_t(const StepArgs& a, int nwaves, int grid, hipStream_t s) {
+static hipError_t launch_tiles_t(const StepArgs& a_in, int nwaves, int grid, hipStream_t s) {
   static int allowed = 0;
+  StepArgs a = a_in;
   const void* fn;
   int bytes;
   if constexpr (H == 32) {
     fn = reinterpret_cast<const void*>(k_step_tiles<H, BF, MODE>);
     bytes = lds_layout(H, BF, nwaves).total;
+    if constexpr (MODE == MODE_STEP) {  // the tile table follows the layout
+      if (a.n_objects > kTableMaxObjects || !a.tile_bad) return hipErrorInvalidValue;
+      a.lds_table = bytes;
+      bytes += round_up((a.n_objects + 1) * 4, 16);
+    }
   } else {
+    static_assert(MODE != MODE_STEP, "the in-kernel tile table is built for width 32 only");
     fn = reinterpret_cast<const void*>(k_step_coop<H, BF, MODE>);
     bytes = coop_layout(H, BF).total;
     nwaves = 4;
@@ -2085,6 +2199,11 @@ hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwave
   if (H == HH && bf16 == BB) {                                                                 \
     return mode == MODE_TRAIN ? launch_tiles_t<HH, BB, MODE_TRAIN>(a, nwaves, grid, s)        \
                               : launch_tiles_t<HH, BB, MODE_FWD>(a, nwaves, grid, s);         \
+  }
+  if (mode == MODE_STEP) {
+    if (H != 32) return hipErrorInvalidValue;
+    return bf16 ? launch_tiles_t<32, true, MODE_STEP>(a, nwaves, grid, s)
+                : launch_tiles_t<32, false, MODE_STEP>(a, nwaves, grid, s);
   }
   VMAP_TILES(32, false)
   VMAP_TILES(32, true)

@@ -74,7 +74,7 @@ def _time_shape(scene, dev_batches, precision, rpt, waves, grid, steps, graph):
 
 def tune(workload: str = "k50_uneven", precision: str = "bf16", steps: int = 20,
          rays_per_tile: Iterable[int] = (), waves: Iterable[int] = (2, 4),
-         grids: Iterable[int] = (0,), graph: bool = True, path: str = CACHE,
+         grids: Iterable[int] = (0,), graph: bool = False, path: str = CACHE,
          log=print) -> dict:
     """Sweep launch shapes on ``workload``; store and return the best."""
     import scenes
@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--rays-per-tile", type=int, nargs="*", default=[])
     ap.add_argument("--waves", type=int, nargs="*", default=[2, 4])
     ap.add_argument("--grids", type=int, nargs="*", default=[0])
-    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--cache", default=CACHE, help="cache file to update")
     args = ap.parse_args()
     import sys

@@ -29,7 +29,7 @@ def tol(precision: str) -> float:
 
 
 def make_pair(scene, precision="fp32", ids=None, max_rays=None, rays_per_tile=0, seed_init=True,
-              lr=1e-3, rays_per_tile_wide=0):
+              lr=1e-3, rays_per_tile_wide=0, split_step=False):
     """An ObjectSet with the scene's objects registered, plus the oracle states of the same
     objects (initial parameters read back from the library: the init kernel is checked against
     the oracle's own initialisation separately)."""
@@ -41,7 +41,7 @@ def make_pair(scene, precision="fp32", ids=None, max_rays=None, rays_per_tile=0,
     objs = vm.ObjectSet(max_objects=len(ids), B=scene.B, hidden=scene.objects[ids[0]].hidden,
                         max_hidden=H, precision=precision, max_rays=max_rays,
                         max_samples_per_ray=max(scene.S, 1), rays_per_tile=rays_per_tile,
-                        rays_per_tile_wide=rays_per_tile_wide, lr=lr)
+                        rays_per_tile_wide=rays_per_tile_wide, lr=lr, split_step=split_step)
     states = {}
     for j, k in enumerate(ids):
         ob = scene.objects[k]
