@@ -140,8 +140,31 @@ struct Deltas<H, true> {
 // tid, tid + nt, ... of the caller share the work; the destination may also be a weight image in
 // device memory (wide models).
 
+// Object parameters (FP32, 16-byte aligned) to LDS unchanged: every thread issues its 16-byte
+// loads in batches of eight before storing any.
+template <int H>
+__device__ __forceinline__ void copy_params(const float* __restrict__ src, float* dst, int tid, int nt) {
+  constexpr int P4 = n_params_of(H) / 4;
+  static_assert(n_params_of(H) % 4 == 0, "parameter vectors are copied as float4");
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+  for (int q0 = 0; q0 < P4; q0 += 8 * nt) {
+    float4 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = min(q0 + tid + i * nt, P4 - 1);  // clamped: every load is in bounds
+      v[i] = s4[q];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = q0 + tid + i * nt;
+      if (q < P4) d4[q] = v[i];
+    }
+  }
+}
+
 template <int H, bool BF>
-__device__ void stage_weights(const float* __restrict__ th, unsigned char* smem, int tid, int nt) {
+__device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsigned char* smem, int tid, int nt) {
   constexpr LdsLayout L = lds_layout(H, BF, 1);
   using WT = typename std::conditional<BF, __bf16, float>::type;
   int off = 0;
@@ -703,7 +726,13 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
     if (k != staged) {
       __syncthreads();
-      stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, smem, tid, blockDim.x);
+      // the object's parameters first go raw into the (idle) reduction area with one batch of
+      // 16-byte loads, so that the staging below waits for device memory once, not once per
+      // element loop
+      float* raw = reinterpret_cast<float*>(smem + L.scratch_off);
+      copy_params<H>(a.theta + (size_t)k * a.p_stride, raw, tid, blockDim.x);
+      __syncthreads();
+      stage_weights<H, BF>(raw, smem, tid, blockDim.x);
       staged = k;
     }
     __syncthreads();
@@ -787,8 +816,8 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
           for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
         }
-      } else {
-#pragma unroll 1
+      } else {  // (unrolled: the two passes' chains interleave)
+#pragma unroll
         for (int p = 0; p < 2; ++p) {
           Acts<H, BF> tmp;
           float xt[4], z[kOut];
