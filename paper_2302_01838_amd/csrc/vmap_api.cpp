@@ -29,7 +29,7 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, t_next, batch, tile_bad, tile_loss, partial, wimage, total;
+  size_t tile_start, flags, t_next, batch, tile_bad, tile_loss, partial, wimage, img32, total;
   size_t wimage_stride;
   int max_tiles;
 };
@@ -122,6 +122,8 @@ WorkLayout work_layout(const vmap_config* c) {
   const bool bf = c->precision == VMAP_BF16;
   w.wimage_stride = weights_global(c->max_hidden) ? (size_t)image_bytes(c->max_hidden, bf) : 0;
   w.wimage = off; off = align256(off + (size_t)c->max_objects * w.wimage_stride);
+  // weight images of width-32 objects (staged by a plain copy)
+  w.img32 = off; off = align256(off + (size_t)c->max_objects * img32_bytes(bf));
   w.total = off;
   return w;
 }
@@ -188,6 +190,7 @@ struct vmap_ctx {
   int32_t* t_next() { return reinterpret_cast<int32_t*>(work + wl.t_next); }
   BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
   int32_t* tile_bad() { return reinterpret_cast<int32_t*>(work + wl.tile_bad); }
+  unsigned char* img32() { return work + wl.img32; }
   float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
   float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
   unsigned char* wimage() { return wl.wimage_stride ? work + wl.wimage : nullptr; }
@@ -263,6 +266,7 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.lambda_o = (float)c->cfg.lambda_occ;
   a.wimage = c->wimage();
   a.wimage_stride = (int64_t)c->wl.wimage_stride;
+  a.img32 = c->img32();
   return a;
 }
 
@@ -313,6 +317,7 @@ OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* 
   a.eps = c->cfg.eps;
   a.bf16 = c->cfg.precision == VMAP_BF16;
   a.growth = c->cfg.scale_growth_interval;
+  a.img32 = c->img32();
   return a;
 }
 
@@ -540,6 +545,18 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   return VMAP_OK;
 }
 
+// The weight image of object k (width 32) from its current parameters.
+hipError_t restage_image(vmap_ctx* c, int k, hipStream_t s) {
+  if (c->objs[k].hidden != 32) return hipSuccess;
+  StepArgs a{};
+  a.max_objects = c->cfg.max_objects;
+  a.theta = c->theta();
+  a.p_stride = c->p_stride;
+  a.desc = c->desc();
+  a.img32 = c->img32();
+  return launch_stage_image32(c->cfg.precision == VMAP_BF16, a, k, s);
+}
+
 int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_params_host,
                     void* stream, int32_t* object_id_out) {
   if (!c) return VMAP_EINVAL;
@@ -580,6 +597,8 @@ int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_pa
   c->objs[k].hidden = H;
   c->objs[k].n_params = P;
   c->n_registered++;
+  e = restage_image(c, k, s);
+  if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
   *object_id_out = k;
   return VMAP_OK;
 }
@@ -896,6 +915,7 @@ int vmap_set_state(vmap_ctx* c, int32_t k, int32_t which, const void* host_src, 
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(dev, host_src, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && which == VMAP_STATE_PARAMS) e = restage_image(c, k, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return c->hip_fail(e, "writing state");
   return VMAP_OK;

@@ -147,6 +147,12 @@ __host__ __device__ constexpr CoopLayout coop_layout(int H, bool bf16) {
   return C;
 }
 
+// Weight image of a width-32 object: the bytes its LDS staging holds before the encoding matrix
+// (lds_layout(32, bf16, 1) up to B_off), kept in device memory so that a tile kernel stages it with
+// a plain copy. Written whole when the object's parameters are set, then per parameter by the
+// optimiser kernels after each update.
+__host__ __device__ constexpr int img32_bytes(bool bf16) { return round_up(lds_layout(32, bf16, 1).B_off, 256); }
+
 // Rays per work tile of an object of width H.
 __host__ __device__ constexpr int tile_rays(int H, int rpt, int rpt_wide) { return H > 32 ? rpt_wide : rpt; }
 
@@ -184,6 +190,7 @@ struct OptArgs {
   const float* tile_loss;
   const int32_t* t_next;      // per batch object, from k_worklist
   const int32_t* tile_bad;    // [tiles] non-finite partial per tile (MODE_STEP), or NULL: flags
+  unsigned char* img32;       // weight images of width-32 objects [max_objects][img32_bytes]
   int p_stride;
   int max_objects;
   ObjDesc* desc;
@@ -239,6 +246,7 @@ struct StepArgs {
   const BatchDev* bd;         // if not NULL, the batch fields above are read from here
   unsigned char* wimage;      // weight images of wide objects, [max_objects][wimage_stride]
   int64_t wimage_stride;
+  unsigned char* img32;       // weight images of width-32 objects [max_objects][img32_bytes]
   // MODE_STEP only: the tile table (in LDS at byte offset lds_table) is also written to
   // tile_start_out, with the next Adam step counts (t_next) and cleared flags, for the optimiser;
   // tiles report a non-finite partial in tile_bad [tiles].
@@ -324,5 +332,7 @@ int tile_lds_bytes(int H, bool bf16, int nwaves);
 int tile_waves(int H, int requested);
 // Weight images of wide objects: those of the batch (single < 0) or of object `single`.
 hipError_t launch_stage_images(int H, bool bf16, const StepArgs& a, int single, hipStream_t s);
+// The weight image of width-32 object k, whole, from its parameters.
+hipError_t launch_stage_image32(bool bf16, const StepArgs& a, int k, hipStream_t s);
 
 }  // namespace vmapi

@@ -140,25 +140,71 @@ struct Deltas<H, true> {
 // tid, tid + nt, ... of the caller share the work; the destination may also be a weight image in
 // device memory (wide models).
 
-// Object parameters (FP32, 16-byte aligned) to LDS unchanged: every thread issues its 16-byte
-// loads in batches of eight before storing any.
-template <int H>
-__device__ __forceinline__ void copy_params(const float* __restrict__ src, float* dst, int tid, int nt) {
-  constexpr int P4 = n_params_of(H) / 4;
-  static_assert(n_params_of(H) % 4 == 0, "parameter vectors are copied as float4");
-  const float4* s4 = reinterpret_cast<const float4*>(src);
-  float4* d4 = reinterpret_cast<float4*>(dst);
-  for (int q0 = 0; q0 < P4; q0 += 8 * nt) {
-    float4 v[8];
+// Where stage_weights puts parameter p (value w) of a width-H object: the same bytes, one
+// parameter at a time (BF16: with its transposed copy, or its bias's three pieces). The
+// optimiser kernels keep the weight images current with it after each update.
+template <int H, bool BF>
+__device__ __forceinline__ void place_param(unsigned char* img, int p, float w) {
+  constexpr LdsLayout L = lds_layout(H, BF, 1);
+  using WT = typename std::conditional<BF, __bf16, float>::type;
+  int off = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int q = min(q0 + tid + i * nt, P4 - 1);  // clamped: every load is in bounds
-      v[i] = s4[q];
+  for (int l = 0; l < kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : H;
+    if (p < off + H * K) {
+      const int e = p - off, row = e / K, col = e - row * K;
+      reinterpret_cast<WT*>(img + L.w_off[l])[row * L.w_stride[l] + (col & ~31) + colpos(col & 31)] = (WT)w;
+      if constexpr (BF) {
+        if (l > 0)
+          reinterpret_cast<__bf16*>(img + L.wt_off[l])[col * (H + 8) + (row & ~31) + colpos(row & 31)] = (__bf16)w;
+      }
+      return;
     }
+    off += H * K;
+    if (p < off + H) {
+      const int row = p - off;
+      reinterpret_cast<float*>(img + L.b_off)[l * H + row] = w;
+      if constexpr (BF) {
+        const __bf16 hi = (__bf16)w;
+        const __bf16 mid = (__bf16)(w - (float)hi);
+        const __bf16 lo = (__bf16)((w - (float)hi) - (float)mid);
+        __bf16* dst = reinterpret_cast<__bf16*>(img + L.bA_off) + (size_t)(l * H + row) * 16;
+        dst[0] = hi;
+        dst[1] = mid;
+        dst[2] = lo;
+      }
+      return;
+    }
+    off += H;
+  }
+  if (p < off + kOut * H) {
+    const int e = p - off, c = e / H, col = e - c * H;
+    if constexpr (BF) {
+      reinterpret_cast<__bf16*>(img + L.whb_off)[c * (H + 8) + (col & ~31) + colpos(col & 31)] = (__bf16)w;
+      reinterpret_cast<__bf16*>(img + L.whtb_off)[col * kOut + c] = (__bf16)w;
+    } else {
+      reinterpret_cast<float*>(img + L.wh_off)[c * (H + 4) + (col & ~31) + colpos(col & 31)] = w;
+    }
+    return;
+  }
+  off += kOut * H;
+  reinterpret_cast<float*>(img + L.bh_off)[p - off] = w;
+}
+
+// A weight image (a multiple of 16 bytes) to LDS: every thread issues its 16-byte loads in
+// batches of eight before storing any.
+__device__ __forceinline__ void copy_image(const unsigned char* __restrict__ src, unsigned char* dst, int n16,
+                                           int tid, int nt) {
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  for (int q0 = 0; q0 < n16; q0 += 8 * nt) {
+    uint4 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = s4[min(q0 + tid + i * nt, n16 - 1)];  // clamped: in bounds
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int q = q0 + tid + i * nt;
-      if (q < P4) d4[q] = v[i];
+      if (q < n16) d4[q] = v[i];
     }
   }
 }
@@ -618,10 +664,19 @@ __device__ AdamCoef adam_coef(const OptArgs& a, int t) {
                   (float)(1.0 - a.beta2), (float)a.eps};
 }
 
+// Parameter p of object k changed to th: its entry in the object's weight image (width 32).
+__device__ __forceinline__ void update_image(const OptArgs& a, int k, int p, float th) {
+  if (!a.img32 || a.desc[k].hidden != 32) return;
+  if (a.bf16) place_param<32, true>(a.img32 + (size_t)k * img32_bytes(true), p, th);
+  else place_param<32, false>(a.img32 + (size_t)k * img32_bytes(false), p, th);
+}
+
+// One Adam update; the contractions are spelled out so that the rounding does not depend on how
+// the compiler schedules the surrounding code.
 __device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th, float& m, float& v) {
-  m = c.b1 * m + c.c1 * g;
-  v = c.b2 * v + c.c2 * g * g;
-  th = th - c.step * m / (sqrtf(v) * c.rs + c.eps);
+  m = fmaf(c.b1, m, c.c1 * g);
+  v = fmaf(c.b2, v, c.c2 * (g * g));
+  th = fmaf(-c.step, m / fmaf(sqrtf(v), c.rs, c.eps), th);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -724,15 +779,10 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
     const int ray_lo = a.ray_offsets[j] + (tile - first_tile(j)) * rpt;
     const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
-    if (k != staged) {
+    if (k != staged) {  // the object's weight image, as it is, with batched 16-byte loads
       __syncthreads();
-      // the object's parameters first go raw into the (idle) reduction area with one batch of
-      // 16-byte loads, so that the staging below waits for device memory once, not once per
-      // element loop
-      float* raw = reinterpret_cast<float*>(smem + L.scratch_off);
-      copy_params<H>(a.theta + (size_t)k * a.p_stride, raw, tid, blockDim.x);
-      __syncthreads();
-      stage_weights<H, BF>(raw, smem, tid, blockDim.x);
+      static_assert(H == 32 && L.B_off % 16 == 0, "weight images are kept for width 32");
+      copy_image(a.img32 + (size_t)k * img32_bytes(BF), smem, L.B_off / 16, tid, blockDim.x);
       staged = k;
     }
     __syncthreads();
@@ -951,6 +1001,38 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
         for (int l = kLayers - 1; l >= 0; --l) {
           const int KB = (l == 0) ? 1 : MT;
+          // delta_{l-1} = (W_l^T delta_l) masked by ReLU' of layer l-1: its products first, so that
+          // they run while this layer's operands are staged and its weight gradient accumulates
+          const int ws = L.w_stride[l > 0 ? l : 1];
+          f32x16 nacc[MT];
+          if (l > 0) {
+#pragma unroll
+            for (int mi = 0; mi < MT; ++mi) {
+              f32x16& acc = nacc[mi];
+#pragma unroll
+              for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+              const int col = mi * 32 + colpos(n);
+#pragma unroll
+              for (int ko = 0; ko < MT; ++ko) {
+                if constexpr (BF) {
+                  // A = W_l^T from its transposed copy: 8 consecutive BF16 per lane
+                  const __bf16* Wt = reinterpret_cast<const __bf16*>(smem + L.wt_off[l]) +
+                                     (mi * 32 + n) * (H + 8) + ko * 32 + 16 * hf;
+#pragma unroll
+                  for (int jj = 0; jj < 2; ++jj) {
+                    const bf16x8 wa = *reinterpret_cast<const bf16x8*>(Wt + 8 * jj);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dl.v[ko][jj], acc, 0, 0, 0);
+                  }
+                } else {
+                  const float* W = reinterpret_cast<const float*>(smem + L.w_off[l]);
+#pragma unroll
+                  for (int qq = 0; qq < 16; ++qq)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W[(ko * 32 + rowof(qq, hf)) * ws + col],
+                                                               dl.v[ko][qq], acc, 0, 0, 0);
+                }
+              }
+            }
+          }
           // stage delta_l (out features) and h_{l-1} (in features) transposed
           wave_lds_sync();
 #pragma unroll
@@ -1010,34 +1092,10 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
             }
           }
           if (l == 0) break;
-          // delta_{l-1} = (W_l^T delta_l) masked by ReLU' of layer l-1
-          const int ws = L.w_stride[l];
           Deltas<H, BF> nd;
 #pragma unroll
           for (int mi = 0; mi < MT; ++mi) {
-            f32x16 acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-            const int col = mi * 32 + colpos(n);
-#pragma unroll
-            for (int ko = 0; ko < MT; ++ko) {
-              if constexpr (BF) {
-                // A = W_l^T from its transposed copy: 8 consecutive BF16 per lane
-                const __bf16* Wt = reinterpret_cast<const __bf16*>(smem + L.wt_off[l]) +
-                                   (mi * 32 + n) * (H + 8) + ko * 32 + 16 * hf;
-#pragma unroll
-                for (int jj = 0; jj < 2; ++jj) {
-                  const bf16x8 wa = *reinterpret_cast<const bf16x8*>(Wt + 8 * jj);
-                  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dl.v[ko][jj], acc, 0, 0, 0);
-                }
-              } else {
-                const float* W = reinterpret_cast<const float*>(smem + L.w_off[l]);
-#pragma unroll
-                for (int qq = 0; qq < 16; ++qq)
-                  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W[(ko * 32 + rowof(qq, hf)) * ws + col],
-                                                             dl.v[ko][qq], acc, 0, 0, 0);
-              }
-            }
+            const f32x16& acc = nacc[mi];
             if constexpr (BF) {
 #pragma unroll
               for (int jj = 0; jj < 2; ++jj) nd.v[mi][jj] = relu_mask(round8(acc, 8 * jj), act.v[l][mi][jj]);
@@ -1677,8 +1735,10 @@ __global__ void __launch_bounds__(256) k_stage_image(const StepArgs a_in, int si
     k = a.object_ids[blockIdx.y];
   }
   if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
-  stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, a.wimage + (size_t)k * a.wimage_stride,
-                       blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  unsigned char* dst = (H == 32) ? a.img32 + (size_t)k * img32_bytes(BF)
+                                 : a.wimage + (size_t)k * a.wimage_stride;
+  stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, dst, blockIdx.x * blockDim.x + threadIdx.x,
+                       gridDim.x * blockDim.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1819,6 +1879,7 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
     a.theta[i] = th;
     a.m[i] = m;
     a.v[i] = v;
+    update_image(a, k, p, th);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
 }
@@ -1841,21 +1902,27 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     a.loss_out[j] = s;
   }
   if (!valid || a.offs[j + 1] <= a.offs[j]) return;
+  const int t = a.t_next[j];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mine = p < a.desc[k].n_params;
+  const size_t i = (size_t)k * a.p_stride + p;
+  // every load of the thread (θ, m, v, then the partials) is issued before the first barrier,
+  // so the block waits for device memory once
+  float th = 0.f, m = 0.f, v = 0.f;
+  if (mine) {
+    th = a.theta[i];
+    m = a.m[i];
+    v = a.v[i];
+  }
+  const float g = mine ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
   if (object_bad(a, j, k)) {
     if (a.tile_bad && blockIdx.x == 0 && threadIdx.x == 0) a.flags[k] = 1;
     return;
   }
-  const int t = a.t_next[j];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mine = p < a.desc[k].n_params;
-  // the partials' loads are issued before the block waits for the Adam coefficients
-  const float g = mine ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
   const AdamCoef c = adam_coef(a, t);
   if (mine) {
-    const size_t i = (size_t)k * a.p_stride + p;
     a.grad[i] = g;
     if (isfinite(g)) {
-      float th = a.theta[i], m = a.m[i], v = a.v[i];
       adam_elem(c, g, th, m, v);
       a.theta[i] = th;
       a.m[i] = m;
@@ -1863,6 +1930,7 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     } else {
       atomicOr(&a.flags[k], 1);
     }
+    update_image(a, k, p, th);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
 }
@@ -2249,6 +2317,13 @@ hipError_t launch_stage_images(int H, bool bf16, const StepArgs& a, int single, 
   const int ny = single >= 0 ? 1 : a.n_objects;
   if (ny <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_stage_image<128, true>), dim3(16, ny), dim3(256), 0, s, a, single);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_image32(bool bf16, const StepArgs& a, int k, hipStream_t s) {
+  if (!a.img32 || k < 0) return hipErrorInvalidValue;
+  if (bf16) hipLaunchKernelGGL((k_stage_image<32, true>), dim3(8), dim3(256), 0, s, a, k);
+  else hipLaunchKernelGGL((k_stage_image<32, false>), dim3(8), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
 

@@ -1,0 +1,99 @@
+"""Weight images of width-32 objects, through the C ABI.
+
+The tile kernel stages a width-32 object's weights by copying its weight image: the object's
+parameters already in the byte layout of the LDS staging (BF16 with transposed copies and bias
+pieces, or FP32). The image is written whole when parameters are set (object added,
+vmap_set_state) and per parameter by the optimiser after each update. These tests train one
+object set normally and a twin whose images are rewritten whole from its parameters after every
+update (a set_state of each object's own parameters); every loss, render and state must agree
+bitwise, so the incremental image writes put every parameter where the whole staging does.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from vmap_testlib import make_pair, scaled
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts, never run there
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2302_01838_amd as vm  # noqa: E402
+
+WHAT = (vm.STATE_PARAMS, vm.STATE_ADAM_M, vm.STATE_ADAM_V, vm.STATE_GRAD)
+
+
+def _restage(objs, ids):
+    for k in ids:
+        objs.set_state(k, vm.STATE_PARAMS, objs.get_state(k, vm.STATE_PARAMS))
+
+
+def _same(a, b, ids):
+    for k in ids:
+        for w in WHAT:
+            assert np.array_equal(a.get_state(k, w), b.get_state(k, w)), (k, w)
+        assert a.get_state(k, vm.STATE_STEP) == b.get_state(k, vm.STATE_STEP)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_images_after_training_steps_match_whole_staging(precision):
+    sc = scaled(scenes.make_scene("k50_uneven"), 10)
+    ids = range(sc.n_objects)
+    inc, _ = make_pair(sc, precision)
+    whole, _ = make_pair(sc, precision)
+    for s in range(3):
+        db = vm.DeviceBatch(scenes.make_batch(sc, s))
+        l1 = inc.step(db).cpu().numpy()
+        l2 = whole.step(db).cpu().numpy()
+        torch.cuda.synchronize()
+        print(f"[image] {precision} step {s}: loss sum {l1.sum():.6g}", flush=True)
+        assert np.array_equal(l1, l2), s
+        _restage(whole, ids)
+    _same(inc, whole, ids)
+    db = vm.DeviceBatch(scenes.make_batch(sc, 3))
+    for a, b in zip(inc.forward(db), whole.forward(db)):
+        assert torch.equal(a, b)
+
+
+def test_images_after_autograd_adam_step():
+    """The autograd split's Adam kernel keeps the images current as well."""
+    sc = scenes.make_scene("tiny_k4")
+    inc, _ = make_pair(sc, "bf16")
+    whole, _ = make_pair(sc, "bf16")
+    db = vm.DeviceBatch(scenes.make_batch(sc, 0))
+    for o in (inc, whole):
+        o.backward(db, torch.ones(db.n_objects, device="cuda"))
+        o.adam_step(db)
+    torch.cuda.synchronize()
+    _restage(whole, range(4))
+    db1 = vm.DeviceBatch(scenes.make_batch(sc, 1))
+    l1 = inc.step(db1).cpu().numpy()
+    l2 = whole.step(db1).cpu().numpy()
+    assert np.array_equal(l1, l2)
+    _same(inc, whole, range(4))
+
+
+def test_set_state_restages_the_image():
+    """Parameters written through vmap_set_state are what the next step trains: a set whose
+    objects were added with random weights and then given new parameters trains exactly like a
+    set whose objects were added with those parameters."""
+    sc = scenes.make_scene("tiny_k4")
+    a, _ = make_pair(sc, "bf16")
+    rng = np.random.default_rng(5)
+    new = {}
+    for k in range(4):
+        th = a.get_state(k, vm.STATE_PARAMS)
+        new[k] = (th + rng.standard_normal(th.shape).astype(np.float32) * np.float32(0.05)).astype(np.float32)
+        a.set_state(k, vm.STATE_PARAMS, new[k])
+    b = vm.ObjectSet(max_objects=4, B=sc.B, precision="bf16", max_rays=a.cfg.max_rays,
+                     max_samples_per_ray=sc.S)
+    for k in range(4):
+        ob = sc.objects[k]
+        assert b.add(ob.norm_centre, ob.norm_scale, seed=ob.seed, init=new[k]) == k
+    db = vm.DeviceBatch(scenes.make_batch(sc, 0))
+    la = a.step(db).cpu().numpy()
+    lb = b.step(db).cpu().numpy()
+    assert np.array_equal(la, lb)
+    _same(a, b, range(4))
