@@ -64,6 +64,35 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("" ::: "memory");
 }
 
+// BF16 operand tiles of the weight-gradient products are staged sample-major: row s (a sample)
+// holds the tile's features, TR_STRIDE elements apart. A lane writes its accumulator-layout
+// values as 8-byte runs of four consecutive features, and ds_read_b64_tr_b16 regroups them: in
+// each group of 16 lanes, lane 4a + b receives element b of the 8-byte chunks addressed by lanes
+// a, a + 4, a + 8 and a + 12 of its group (checked on the device), so four lanes that address
+// four consecutive rows at the same feature offset hand each of their readers one feature's four
+// consecutive samples.
+constexpr int kTrStride = 36;  // BF16 elements per staged row (32 features + 4: 8-byte rows)
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef short v8i16 __attribute__((ext_vector_type(8)));
+
+// Eight BF16 (two transposing reads, the second four rows further down) as one MFMA operand.
+__device__ __forceinline__ bf16x8 tr_read8(const __bf16* p) {
+  typedef __attribute__((address_space(3))) v4i16 lds_v4;
+  const v4i16 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(p));
+  const v4i16 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(p + 4 * kTrStride));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// Elements 0-3 of v to p and elements 4-7 to p + 8 (two 8-byte stores).
+__device__ __forceinline__ void write_runs(__bf16* p, bf16x8 v) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u2w __attribute__((ext_vector_type(2)));
+  const u4 w = __builtin_bit_cast(u4, v);
+  *reinterpret_cast<u2w*>(p) = (u2w){w[0], w[1]};
+  *reinterpret_cast<u2w*>(p + 8) = (u2w){w[2], w[3]};
+}
+
 // Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
 // division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
@@ -927,16 +956,20 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
             else reinterpret_cast<float*>(dzt)[n * kOut + c] = dz[c];
           }
         }
+        if constexpr (BF) {  // sample-major runs (register block jj: features 16jj + 4hf + 0..3, + 8)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+          for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int f = mt * 32 + rowof(r, hf);
-            if constexpr (BF)
-              reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[kLayers][mt][r >> 3][r & 7];
-            else
-              reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[kLayers][mt][r];
-          }
+            for (int jj = 0; jj < 2; ++jj)
+              write_runs(reinterpret_cast<__bf16*>(htile) + n * kTrStride + mt * 32 + 16 * jj + 4 * hf,
+                         act.v[kLayers][mt][jj]);
+        } else {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              reinterpret_cast<float*>(htile)[n * (H + 4) + mt * 32 + rowof(r, hf)] = act.v[kLayers][mt][r];
+        }
         wave_lds_sync();
         Deltas<H, BF> dl;
         if constexpr (BF) {
@@ -945,10 +978,12 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           const int m16 = lane & 15, kg = lane >> 4;
           bf16x8 da = {};
           if (m16 < kOut) da = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(dzt) + m16 * 40 + 8 * kg);
+          // B operand (feature 16b + m16, samples 8kg..8kg+7): lane x of group kg addresses row
+          // 8kg + x/4 at feature 16b + 4(x mod 4)
+          const __bf16* hq = reinterpret_cast<const __bf16*>(htile) + (8 * kg + (m16 >> 2)) * kTrStride + 4 * (m16 & 3);
 #pragma unroll
           for (int b = 0; b < H / 16; ++b) {
-            const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
-                reinterpret_cast<const __bf16*>(htile) + (b * 16 + m16) * 40 + 8 * kg);
+            const bf16x8 hb = tr_read8(hq + 16 * b);
             accWh[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da, hb, accWh[b], 0, 0, 0);
           }
           // delta of the last hidden layer: W_out^T dz on MFMA (K = 4 outputs padded to 16)
@@ -1033,26 +1068,34 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
               }
             }
           }
-          // stage delta_l (out features) and h_{l-1} (in features) transposed
+          // stage delta_l (out features) and h_{l-1} (in features): BF16 sample-major runs, FP32
+          // sample-major
           wave_lds_sync();
+          if constexpr (BF) {
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int f = mt * 32 + rowof(r, hf);
-              if constexpr (BF) reinterpret_cast<__bf16*>(dtile)[f * 40 + n] = dl.v[mt][r >> 3][r & 7];
-              else reinterpret_cast<float*>(dtile)[n * (H + 4) + f] = dl.v[mt][r];
-            }
+              for (int jj = 0; jj < 2; ++jj)
+                write_runs(reinterpret_cast<__bf16*>(dtile) + n * kTrStride + mt * 32 + 16 * jj + 4 * hf,
+                           dl.v[mt][jj]);
 #pragma unroll
-          for (int kb = 0; kb < KB; ++kb)
+            for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int f = kb * 32 + rowof(r, hf);
-              if constexpr (BF)
-                reinterpret_cast<__bf16*>(htile)[f * 40 + n] = act.v[l][kb][r >> 3][r & 7];
-              else
-                reinterpret_cast<float*>(htile)[n * (H + 4) + f] = act.v[l][kb][r];
-            }
+              for (int jj = 0; jj < 2; ++jj)
+                write_runs(reinterpret_cast<__bf16*>(htile) + n * kTrStride + kb * 32 + 16 * jj + 4 * hf,
+                           act.v[l][kb][jj]);
+          } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int r = 0; r < 16; ++r)
+                reinterpret_cast<float*>(dtile)[n * (H + 4) + mt * 32 + rowof(r, hf)] = dl.v[mt][r];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+              for (int r = 0; r < 16; ++r)
+                reinterpret_cast<float*>(htile)[n * (H + 4) + kb * 32 + rowof(r, hf)] = act.v[l][kb][r];
+          }
           wave_lds_sync();
           // weight gradient dW_l += delta_l h_{l-1}^T over the pass's 32 samples
 #pragma unroll
@@ -1062,10 +1105,12 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
               if constexpr (BF) {
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
-                  const bf16x8 da = *reinterpret_cast<const bf16x8*>(
-                      reinterpret_cast<const __bf16*>(dtile) + (mo * 32 + n) * 40 + 16 * jj + 8 * hf);
-                  const bf16x8 hb = *reinterpret_cast<const bf16x8*>(
-                      reinterpret_cast<const __bf16*>(htile) + (ki * 32 + n) * 40 + 16 * jj + 8 * hf);
+                  // A and B operands (feature row lane & 31, samples 16jj + 8hf + 0..7): lane x of
+                  // group G = lane / 16 addresses row 16jj + 8(G / 2) + x/4 at feature
+                  // 16(G mod 2) + 4(x mod 4)
+                  const int lo = (16 * jj + 8 * hf + ((lane & 15) >> 2)) * kTrStride + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+                  const bf16x8 da = tr_read8(reinterpret_cast<const __bf16*>(dtile) + lo + mo * 32);
+                  const bf16x8 hb = tr_read8(reinterpret_cast<const __bf16*>(htile) + lo + ki * 32);
                   accW[l][mo][ki] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, hb, accW[l][mo][ki], 0, 0, 0);
                   if (ki == 0) {  // bias gradient: the 8 deltas' sum, two at a time (v_dot2)
                     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
