@@ -904,10 +904,14 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           forward_pass<H, BF, true>(xt, smem, Bl, tmp, z, a.var != nullptr);
 #pragma unroll
           for (int c = 0; c < kOut; ++c) zs[c] = (hf == p) ? z[c] : zs[c];
-          if constexpr (TRAIN && BF) {  // the pass's encoding, for the recomputation
+          if constexpr (TRAIN && BF) {
+            if (p == 1) {  // the last pass's activations stay for its backward, which runs first
+              keep1 = tmp;
+            } else {  // the first pass's encoding, for its recomputation
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj)
-              *reinterpret_cast<bf16x8*>(encc + p * 2048 + lane * 32 + 16 * jj) = tmp.v[0][0][jj];
+              for (int jj = 0; jj < 2; ++jj)
+                *reinterpret_cast<bf16x8*>(encc + lane * 32 + 16 * jj) = tmp.v[0][0][jj];
+            }
           }
         }
       }
@@ -922,8 +926,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       unsigned char* dzt = scr;
       unsigned char* dtile = scr + dz_tile_bytes(BF);
       unsigned char* htile = dtile + tr_tile_bytes(H, BF);
-#pragma unroll 1
-      for (int p = 0; p < 2; ++p) {
+      // one pass's backward (p: which 32 samples); BF16 runs the last pass first, on the
+      // activations its forward left in registers, and recomputes only the first pass
+      auto backward_pass = [&](const int p) {
         Acts<H, BF> act;
         if constexpr (KEEP) {
 #pragma unroll
@@ -933,12 +938,16 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 #pragma unroll
               for (int q = 0; q < (int)(sizeof(act.v[0][0]) / sizeof(act.v[0][0][0])); ++q)
                 act.v[l][b][q] = (p == 0) ? keep0.v[l][b][q] : keep1.v[l][b][q];
-        } else if constexpr (BF) {  // recompute from the pass's encoding kept in LDS
+        } else if constexpr (BF) {
+          if (p == 1) {
+            act = keep1;
+          } else {  // recompute from the pass's encoding kept in LDS
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj)
-            act.v[0][0][jj] = *reinterpret_cast<const bf16x8*>(encc + p * 2048 + lane * 32 + 16 * jj);
-          float z[kOut];
-          forward_pass<H, BF, false, false>(nullptr, smem, Bl, act, z);
+            for (int jj = 0; jj < 2; ++jj)
+              act.v[0][0][jj] = *reinterpret_cast<const bf16x8*>(encc + lane * 32 + 16 * jj);
+            float z[kOut];
+            forward_pass<H, BF, false, false>(nullptr, smem, Bl, act, z);
+          }
         } else {
           float xt[4], z[kOut];
           point(p, xt);
@@ -1154,6 +1163,13 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           }
           dl = nd;
         }
+      };
+      if constexpr (BF) {
+        backward_pass(1);
+        backward_pass(0);
+      } else {
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) backward_pass(p);
       }
     }  // sub-tiles
 
