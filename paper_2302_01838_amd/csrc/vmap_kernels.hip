@@ -93,6 +93,21 @@ __device__ __forceinline__ void write_runs(__bf16* p, bf16x8 v) {
   *reinterpret_cast<u2w*>(p + 8) = (u2w){w[2], w[3]};
 }
 
+// First tile of a workgroup. Workgroups are dealt to the eight XCDs in turn (workgroup b runs on
+// XCD b mod 8, each with its own L2); when the grid has a workgroup per tile, the first n_tiles
+// workgroups of one XCD take consecutive tiles, so that an object's tiles (its weights, rays and
+// samples) share one L2 instead of being fetched into all eight. Workgroups past n_tiles (the
+// last dispatched) stay without a tile. Otherwise tile = workgroup index.
+__device__ __forceinline__ int first_tile_of_block(int n_tiles) {
+  constexpr int kXcds = 8;
+  const int b = blockIdx.x;
+  if ((int)gridDim.x < n_tiles || b >= n_tiles) return b;
+  const int x = b % kXcds;
+  int start = 0;
+  for (int y = 0; y < x; ++y) start += (n_tiles - y + kXcds - 1) / kXcds;  // workgroups of XCD y
+  return start + b / kXcds;
+}
+
 // Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
 // division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
@@ -506,9 +521,35 @@ __device__ __forceinline__ void read_batch(OptArgs& a) {
 // sub-tile of the calling wave: lane = sample slot, zs = the slot's head pre-activations (r, g, b,
 // occupancy). Adds the sub-tile's loss to `loss`; forward mode writes the rendered outputs;
 // training returns dL/dz of the slot in dzs (zero on slots at or past nslots).
+// The rendering's per-sample inputs of a sub-tile (sample depth; the ray's depth, mask and colour
+// targets), loaded before the forward pass so that their latency hides behind it.
+struct RenderIn {
+  float tt, D, M, rgb[3];
+};
+
+template <bool TRAIN>
+__device__ __forceinline__ RenderIn render_inputs(const StepArgs& a, int r0, int nslots) {
+  const int lane = threadIdx.x & 63;
+  RenderIn in{0.f, 0.f, 0.f, {0.f, 0.f, 0.f}};
+  if (lane < nslots) {
+    const int ray = r0 + lane / a.S;
+    in.tt = a.t[(size_t)r0 * a.S + lane];
+    // rendering without targets (forward mode, NULL target buffers) evaluates the loss terms
+    // against zero targets; that loss is not reported
+    if (TRAIN || a.depth != nullptr) {
+      in.D = a.depth[ray];
+      in.M = a.mask[ray];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) in.rgb[c] = a.rgb[3 * ray + c];
+    }
+  }
+  return in;
+}
+
 template <bool TRAIN>
 __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int nslots, float wseed,
-                                               const float zs[kOut], float dzs[kOut], float& loss) {
+                                               const RenderIn& in, const float zs[kOut], float dzs[kOut],
+                                               float& loss) {
   const int lane = threadIdx.x & 63;
   const int S = a.S;
   const float lc = a.lambda_c, lo = a.lambda_o;
@@ -516,13 +557,13 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
   const int jr = valid ? lane / S : 0;
   const int si = valid ? lane - jr * S : 0;
   const int ray = r0 + jr;
-  float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f}, tt = 0.f;
+  float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f};
+  const float tt = in.tt;
   if (valid) {
     o = sigm(zs[3]);
     q = sigm(-zs[3]);  // 1 - o, without cancellation
 #pragma unroll
     for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
-    tt = a.t[(size_t)r0 * S + lane];
   }
   // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift
   float Pin = q;
@@ -546,16 +587,11 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
 
   float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
   if (valid) {
-    // rendering without targets (forward mode, NULL target buffers) evaluates the loss terms
-    // against zero targets; that loss is not reported
-    const bool tg = TRAIN || a.depth != nullptr;
-    const float D = tg ? a.depth[ray] : 0.f, M = tg ? a.mask[ray] : 0.f;
+    const float D = in.D, M = in.M;
     const float rD = Dh - D;
-    float rC[3] = {Ch[0], Ch[1], Ch[2]};
-    if (tg) {
+    float rC[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rC[c] -= a.rgb[3 * ray + c];
-    }
+    for (int c = 0; c < 3; ++c) rC[c] = Ch[c] - in.rgb[c];
     const float rho = (M == 1.0f) ? -Pend : (Oh - M);
     if (si == 0) {
       loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
@@ -599,28 +635,21 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
 //   k_reduce_adam — both in one pass (the training step when it is split into launches).
 // The optimiser kernels take each object's next step count from the work-list kernel; block
 // (0, j) writes it back, block (0, 0) updates the loss scaler from the flags. No block reads what
-// another block of the same launch writes, so no device-scope fence is needed. The one-launch
-// training step (MODE_STEP, below) runs the same sum and update inside the tile kernel.
+// another block of the same launch writes, so no device-scope fence is needed. After a MODE_STEP
+// tile launch (below) the table, step counts and cleared flags come from the tile kernel and the
+// non-finite reports from its tiles.
 
-// Sum of an object's tile partials at parameter p, in tile order; loads are issued eight at a
-// time and added in order.
+// Sum of an object's tile partials at parameter p, in tile order; up to 32 loads are issued
+// before the first add (objects here have at most a few tens of tiles).
 __device__ __forceinline__ float tile_sum(const float* __restrict__ partial, int p_stride, int t0,
                                           int t1, int p) {
   float g = 0.f;
-  int t = t0;
-  for (; t + 16 <= t1; t += 16) {
-    float x[16];
+  for (int t = t0; t < t1; t += 32) {
+    float x[32];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = partial[(size_t)(t + u) * p_stride + p];
+    for (int u = 0; u < 32; ++u) x[u] = (t + u < t1) ? partial[(size_t)(t + u) * p_stride + p] : 0.f;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) g += x[u];
-  }
-  if (t < t1) {  // the rest, loads issued together, added in order
-    float x[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = (t + u < t1) ? partial[(size_t)(t + u) * p_stride + p] : 0.f;
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < 32; ++u)
       if (t + u < t1) g += x[u];
   }
   return g;
@@ -791,7 +820,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
   int staged = -1;
 
-  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  for (int tile = first_tile_of_block(n_tiles); tile < n_tiles; tile += gridDim.x) {
     // object of this tile: largest j with first_tile(j) <= tile
     int jlo = 0, jhi = a.n_objects;
     while (jhi - jlo > 1) {
@@ -862,6 +891,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       const int r0 = ray_lo + sub * rpw;
       const int nr = min(rpw, ray_hi - r0);
       const int nslots = nr * S;
+      const RenderIn rin = render_inputs<TRAIN>(a, r0, nslots);  // in flight during the forward
 
       // ---------------- forward of both passes for the head outputs only. Each pass's
       // activations are recomputed right before its backward (activation recomputation), so no
@@ -917,7 +947,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       }
 
       float dzs[kOut];
-      render_subtile<TRAIN>(a, r0, nslots, wseed, zs, dzs, wave_loss);
+      render_subtile<TRAIN>(a, r0, nslots, wseed, rin, zs, dzs, wave_loss);
       if constexpr (!TRAIN) continue;
 #pragma unroll
       for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
@@ -1317,7 +1347,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
   unsigned char* const scr0 = smem + C.scratch_off;
   int staged = -1;
 
-  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  for (int tile = first_tile_of_block(n_tiles); tile < n_tiles; tile += gridDim.x) {
     int jlo = 0, jhi = a.n_objects;
     while (jhi - jlo > 1) {
       const int mid = (jlo + jhi) >> 1;
@@ -1401,6 +1431,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
       const int r0 = ray_lo + sub * rpw;
       const int nr = (sub < nsub) ? min(rpw, ray_hi - r0) : 0;
       const int nslots = nr * S;
+      const RenderIn rin = render_inputs<TRAIN>(a, r0, nslots);  // in flight during the forward
 
       // the lane's sample: normalised point and (integrated encoding) normalised variance
       auto point = [&](int p, float xt[4]) {
@@ -1430,7 +1461,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
         }
       }
       float dzs[kOut];
-      render_subtile<TRAIN>(a, r0, nslots, wseed, zs, dzs, wave_loss);
+      render_subtile<TRAIN>(a, r0, nslots, wseed, rin, zs, dzs, wave_loss);
       if constexpr (!TRAIN) continue;
 #pragma unroll
       for (int c = 0; c < kOut; ++c) accDbH[c] += dzs[c];
