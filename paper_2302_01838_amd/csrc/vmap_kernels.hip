@@ -97,7 +97,8 @@ __device__ __forceinline__ void write_runs(__bf16* p, bf16x8 v) {
 // XCD b mod 8, each with its own L2); when the grid has a workgroup per tile, the first n_tiles
 // workgroups of one XCD take consecutive tiles, so that an object's tiles (its weights, rays and
 // samples) share one L2 instead of being fetched into all eight. Workgroups past n_tiles (the
-// last dispatched) stay without a tile. Otherwise tile = workgroup index.
+// last dispatched) stay without a tile. Otherwise tile = workgroup index. Only for launches whose
+// tiles all do work: each XCD gets an equal share of tiles, not of work.
 __device__ __forceinline__ int first_tile_of_block(int n_tiles) {
   constexpr int kXcds = 8;
   const int b = blockIdx.x;
@@ -820,7 +821,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
   int staged = -1;
 
-  for (int tile = first_tile_of_block(n_tiles); tile < n_tiles; tile += gridDim.x) {
+  // XCD-aware order only when every tile belongs to this launch (tiles of other widths would
+  // crowd the XCDs that hold them)
+  for (int tile = TABLE ? first_tile_of_block(n_tiles) : (int)blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     // object of this tile: largest j with first_tile(j) <= tile
     int jlo = 0, jhi = a.n_objects;
     while (jhi - jlo > 1) {
@@ -1347,7 +1350,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
   unsigned char* const scr0 = smem + C.scratch_off;
   int staged = -1;
 
-  for (int tile = first_tile_of_block(n_tiles); tile < n_tiles; tile += gridDim.x) {
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     int jlo = 0, jhi = a.n_objects;
     while (jhi - jlo > 1) {
       const int mid = (jlo + jhi) >> 1;
