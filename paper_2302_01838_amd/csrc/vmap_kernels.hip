@@ -664,15 +664,29 @@ __device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
 // Whether batch object j (id k) had a non-finite tile partial: its flag, or with per-tile
 // reports the OR of its tiles' entries. Called by every thread of the workgroup.
 __device__ __forceinline__ bool object_bad(const OptArgs& a, int j, int k) {
-  if (!a.tile_bad) return a.flags[k] != 0;
+  if (!a.tile_bad) return __syncthreads_or(a.flags[k] != 0) != 0;
   int bad = 0;
   for (int t = a.tile_start[j] + (int)threadIdx.x; t < a.tile_start[j + 1]; t += blockDim.x)
     bad |= a.tile_bad[t];
   return __syncthreads_or(bad) != 0;
 }
 
+// OR of the non-finite reports of tiles [t0, t1); up to 32 loads are issued before the first use.
+__device__ __forceinline__ int tile_or(const int32_t* __restrict__ bad, int t0, int t1) {
+  int r = 0;
+  for (int t = t0; t < t1; t += 32) {
+    int x[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) x[u] = (t + u < t1) ? bad[t + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 32; ++u) r |= x[u];
+  }
+  return r;
+}
+
 // One workgroup (any size): count the batch objects with rays whose gradient was not finite;
-// BF16 loss scaler.
+// BF16 loss scaler. Each thread loads its object's id, rays, tiles and descriptor at once (an id
+// out of range reads object 0's descriptor and is then discarded), then its tiles' reports.
 __device__ void scaler_update(const OptArgs& a) {
   __shared__ int count;
   if (threadIdx.x == 0) count = 0;
@@ -680,14 +694,14 @@ __device__ void scaler_update(const OptArgs& a) {
   int skipped = 0;
   for (int jj = threadIdx.x; jj < a.n_objects; jj += blockDim.x) {
     const int kk = a.ids[jj];
-    if (!obj_valid(a, kk) || a.offs[jj + 1] <= a.offs[jj]) continue;
-    bool bad = false;
-    if (a.tile_bad) {  // from the tiles: the objects' flags are being written by this launch
-      for (int t = a.tile_start[jj]; t < a.tile_start[jj + 1]; ++t) bad |= a.tile_bad[t] != 0;
-    } else {
-      bad = a.flags[kk] != 0;
-    }
-    if (bad) ++skipped;
+    const int r0 = a.offs[jj], r1 = a.offs[jj + 1];
+    const int t0 = a.tile_start[jj], t1 = a.tile_start[jj + 1];
+    const bool in_range = kk >= 0 && kk < a.max_objects;
+    const int kc = in_range ? kk : 0;
+    const bool registered = a.desc[kc].registered != 0;
+    // from the tiles: the objects' flags are being written by this launch
+    const int bad = a.tile_bad ? tile_or(a.tile_bad, t0, t1) : a.flags[kc];
+    if (in_range && registered && r1 > r0 && bad != 0) ++skipped;
   }
   if (skipped) atomicAdd(&count, skipped);
   __syncthreads();
@@ -711,21 +725,27 @@ struct AdamCoef {
 };
 
 // Bias-corrected step size and 1/sqrt(bias correction of v) in FP64, then rounded once.
-__device__ AdamCoef adam_coef(const OptArgs& a, int t) {
-  __shared__ float sh[2];
-  if (threadIdx.x == 0) {
-    const double bc1 = 1.0 - pow(a.beta1, (double)t), bc2 = 1.0 - pow(a.beta2, (double)t);
-    sh[0] = (float)(a.lr / bc1);
-    sh[1] = (float)(1.0 / sqrt(bc2));
-  }
-  __syncthreads();
+__device__ __forceinline__ void adam_coef_store(const OptArgs& a, int t, float* sh) {
+  const double bc1 = 1.0 - pow(a.beta1, (double)t), bc2 = 1.0 - pow(a.beta2, (double)t);
+  sh[0] = (float)(a.lr / bc1);
+  sh[1] = (float)(1.0 / sqrt(bc2));
+}
+
+__device__ __forceinline__ AdamCoef adam_coef_load(const OptArgs& a, const float* sh) {
   return AdamCoef{sh[0], sh[1], (float)a.beta1, (float)(1.0 - a.beta1), (float)a.beta2,
                   (float)(1.0 - a.beta2), (float)a.eps};
 }
 
+__device__ AdamCoef adam_coef(const OptArgs& a, int t) {
+  __shared__ float sh[2];
+  if (threadIdx.x == 0) adam_coef_store(a, t, sh);
+  __syncthreads();
+  return adam_coef_load(a, sh);
+}
+
 // Parameter p of object k changed to th: its entry in the object's weight image (width 32).
-__device__ __forceinline__ void update_image(const OptArgs& a, int k, int p, float th) {
-  if (!a.img32 || a.desc[k].hidden != 32) return;
+__device__ __forceinline__ void update_image(const OptArgs& a, int k, int hidden, int p, float th) {
+  if (!a.img32 || hidden != 32) return;
   if (a.bf16) place_param<32, true>(a.img32 + (size_t)k * img32_bytes(true), p, th);
   else place_param<32, false>(a.img32 + (size_t)k * img32_bytes(false), p, th);
 }
@@ -1974,48 +1994,58 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
     a.theta[i] = th;
     a.m[i] = m;
     a.v[i] = v;
-    update_image(a, k, p, th);
+    update_image(a, k, a.desc[k].hidden, p, th);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
 }
 
 // Training step: gradient and update in one pass. A non-finite gradient element (possible only
 // if finite tile partials overflow when added) leaves its parameter unchanged and flags the
-// object for the skip count.
+// object for the skip count. Every load of a thread depends on at most the batch object's id, ray
+// range and tile range, so a workgroup waits for device memory twice (those, then the object's
+// data); the validity checks only decide what is stored. Thread 0 works out the Adam
+// coefficients while the loads are in flight. The grid has one row of workgroups per batch object
+// and a last row whose first workgroup updates the loss scaler (its own chain of loads).
 __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   OptArgs a = a_in;
   read_batch(a);
   const int j = blockIdx.y;
-  if (blockIdx.x == 0 && j == 0) scaler_update(a);
-  const int k = a.ids[j];
-  const bool valid = obj_valid(a, k);
-  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
-    float s = 0.f;
-    if (valid)
-      for (int t = t0; t < t1; ++t) s += a.tile_loss[t];
-    a.loss_out[j] = s;
+  if (j == (int)gridDim.y - 1) {
+    if (blockIdx.x == 0) scaler_update(a);
+    return;
   }
-  if (!valid || a.offs[j + 1] <= a.offs[j]) return;
+  const int k = a.ids[j];
+  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
+  const int r0 = a.offs[j], r1 = a.offs[j + 1];
   const int t = a.t_next[j];
+  const bool in_range = k >= 0 && k < a.max_objects;
+  const int kc = in_range ? k : 0;  // loads of an id out of range are discarded
+  const ObjDesc& d = a.desc[kc];
+  const int registered = d.registered, n_params = d.n_params, hidden = d.hidden;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mine = p < a.desc[k].n_params;
-  const size_t i = (size_t)k * a.p_stride + p;
-  // every load of the thread (θ, m, v, then the partials) is issued before the first barrier,
-  // so the block waits for device memory once
-  float th = 0.f, m = 0.f, v = 0.f;
-  if (mine) {
+  const size_t i = (size_t)kc * a.p_stride + p;
+  float th = 0.f, m = 0.f, v = 0.f, g = 0.f;
+  if (p < a.p_stride) {
     th = a.theta[i];
     m = a.m[i];
     v = a.v[i];
+    g = tile_sum(a.partial, a.p_stride, t0, t1, p);
   }
-  const float g = mine ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  float loss = 0.f;
+  if (lead && a.loss_out) loss = tile_sum(a.tile_loss, 1, t0, t1, 0);
+  __shared__ float sh[2];
+  if (threadIdx.x == 0) adam_coef_store(a, t, sh);
+  const bool valid = in_range && registered != 0;
+  if (lead && a.loss_out) a.loss_out[j] = valid ? loss : 0.f;
+  if (!valid || r1 <= r0) return;
+  // the barrier of object_bad also publishes the coefficients
   if (object_bad(a, j, k)) {
-    if (a.tile_bad && blockIdx.x == 0 && threadIdx.x == 0) a.flags[k] = 1;
+    if (a.tile_bad && lead) a.flags[k] = 1;
     return;
   }
-  const AdamCoef c = adam_coef(a, t);
-  if (mine) {
+  const AdamCoef c = adam_coef_load(a, sh);
+  if (p < n_params) {
     a.grad[i] = g;
     if (isfinite(g)) {
       adam_elem(c, g, th, m, v);
@@ -2025,9 +2055,9 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     } else {
       atomicOr(&a.flags[k], 1);
     }
-    update_image(a, k, p, th);
+    update_image(a, k, hidden, p, th);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
+  if (lead) a.desc[k].step = t;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2471,7 +2501,7 @@ hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
   if (kind == OPT_REDUCE) hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, 1);
   else if (kind == OPT_LOSS) hipLaunchKernelGGL(k_reduce, dim3(1, a.n_objects), dim3(256), 0, s, a, 0);
   else if (kind == OPT_ADAM) hipLaunchKernelGGL(k_adam, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_reduce_adam, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_reduce_adam, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
