@@ -12,6 +12,7 @@ namespace vmapi {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 namespace bf16_detail {
 typedef float f2 __attribute__((ext_vector_type(2)));

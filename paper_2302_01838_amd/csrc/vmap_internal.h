@@ -63,7 +63,11 @@ __host__ __device__ constexpr int n_params_of(int H) {
 
 // Per-wave staging: the output-layer seeds dz (FP32 [32][4], or BF16 [4][40]) and two transposed
 // tiles (delta and activations): FP32 [32 samples][H + 4], BF16 [H features][40].
-__host__ __device__ constexpr int dz_tile_bytes(bool bf16) { return bf16 ? 4 * 40 * 2 : 32 * kOut * 4; }
+// dL/dz of a 32-sample pass: BF16 as four output rows of 40 (the output layer's weight-gradient
+// operand), then sample-major, four per sample (the output layer's delta operand); FP32
+// sample-major.
+constexpr int kDzRowsBytes = 4 * 40 * 2;
+__host__ __device__ constexpr int dz_tile_bytes(bool bf16) { return bf16 ? kDzRowsBytes + 32 * kOut * 2 : 32 * kOut * 4; }
 __host__ __device__ constexpr int tr_tile_bytes(int H, bool bf16) {
   return bf16 ? H * 40 * 2 : 32 * (H + 4) * 4;
 }

@@ -112,7 +112,6 @@ __device__ __forceinline__ int first_tile_of_block(int n_tiles) {
 // Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
 // division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
-__device__ __forceinline__ float sgnf(float x) { return (x > 0.f) ? 1.f : ((x < 0.f) ? -1.f : 0.f); }
 
 template <bool BF>
 __device__ __forceinline__ float round_w(float x) {
@@ -547,6 +546,79 @@ __device__ __forceinline__ RenderIn render_inputs(const StepArgs& a, int r0, int
   return in;
 }
 
+// Cross-lane moves of the ray scans, by DPP (a VALU operand modifier, no LDS round trip). DPP
+// controls: row_shr:n (lane l takes lane l - n of its row of 16), row_shl:n (lane l + n),
+// wave_shr:1 / wave_shl:1 (lane l - 1 / l + 1 across the wave), row_bcast:15 (lane 15 of each row
+// into the next row, rows 1 and 3 written), row_bcast:31 (lane 31 into rows 2 and 3). Lanes whose
+// source does not exist keep 0; the scans below never use those lanes' results. A move reads its
+// source lane's register only if that lane is active, so every move runs with the whole wave
+// active (computed before any select that uses it, never in a conditional arm).
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138,
+              kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               ROW_MASK, 0xf, false));
+}
+
+// Inclusive scans within the rays of a sub-tile. A ray is a segment of S consecutive lanes from
+// lane 0 (lanes past the last ray are segments of one lane); si = the lane's position in its
+// segment, de = its distance to the segment's last lane. Forward: lane l combines lanes
+// [segment start, l], by shifts of 1, 2, 4 and 8 within rows of 16 lanes (a step combines where
+// the source lies in both the row and the segment), then lane 15 of each row into the next row
+// and lane 31 into rows 2 and 3 (where no segment starts between the row's first lane and l).
+// Reverse: lane l combines lanes [l, segment end], by shifts within rows, then the first lane of
+// rows 3, 2 and 1 into the row before, in that order.
+struct RayScan {
+  bool f[6];  // forward steps
+  bool r[4];  // reverse steps within rows
+  int de, lr, row;
+
+  __device__ __forceinline__ RayScan(int lane, int si, int de_) : de(de_) {
+    lr = lane & 15;
+    row = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f[i] = si >= (1 << i) && lr >= (1 << i);
+      r[i] = de >= (1 << i) && lr + (1 << i) <= 15;
+    }
+    f[4] = (row & 1) && si > lr;
+    f[5] = lane >= 32 && si > lane - 32;
+  }
+
+  template <int N, class Op>
+  __device__ __forceinline__ void forward(float (&v)[N], Op op) const {
+    float u[N];
+#define VMAP_SCAN_STEP(I, CTRL, RM)                                        \
+  {                                                                        \
+    _Pragma("unroll") for (int q = 0; q < N; ++q) u[q] = dpp_mov<CTRL, RM>(v[q]); \
+    _Pragma("unroll") for (int q = 0; q < N; ++q) v[q] = f[I] ? op(v[q], u[q]) : v[q]; \
+  }
+    VMAP_SCAN_STEP(0, kDppRowShr + 1, 0xf)
+    VMAP_SCAN_STEP(1, kDppRowShr + 2, 0xf)
+    VMAP_SCAN_STEP(2, kDppRowShr + 4, 0xf)
+    VMAP_SCAN_STEP(3, kDppRowShr + 8, 0xf)
+    VMAP_SCAN_STEP(4, kDppBcast15, 0xa)
+    VMAP_SCAN_STEP(5, kDppBcast31, 0xc)
+#undef VMAP_SCAN_STEP
+  }
+
+  __device__ __forceinline__ float reverse_sum(float v) const {
+    float u;
+    u = dpp_mov<kDppRowShl + 1>(v); v = r[0] ? v + u : v;
+    u = dpp_mov<kDppRowShl + 2>(v); v = r[1] ? v + u : v;
+    u = dpp_mov<kDppRowShl + 4>(v); v = r[2] ? v + u : v;
+    u = dpp_mov<kDppRowShl + 8>(v); v = r[3] ? v + u : v;
+#pragma unroll
+    for (int rr = 2; rr >= 0; --rr) {
+      const float s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16 * (rr + 1)));
+      v = (row == rr && de > 15 - lr) ? v + s : v;
+    }
+    return v;
+  }
+};
+
 template <bool TRAIN>
 __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int nslots, float wseed,
                                                const RenderIn& in, const float zs[kOut], float dzs[kOut],
@@ -557,7 +629,9 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
   const bool valid = lane < nslots;
   const int jr = valid ? lane / S : 0;
   const int si = valid ? lane - jr * S : 0;
+  const int de = valid ? S - 1 - si : 0;
   const int ray = r0 + jr;
+  const RayScan sc(lane, si, de);
   float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f};
   const float tt = in.tt;
   if (valid) {
@@ -566,64 +640,57 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
 #pragma unroll
     for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
   }
-  // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift
-  float Pin = q;
-  for (int off = 1; off < S; off <<= 1) {
-    const float u = __shfl_up(Pin, off);
-    if (si >= off) Pin *= u;
-  }
-  float Pex = __shfl_up(Pin, 1);
-  if (si == 0) Pex = 1.f;
+  // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift by one lane
+  float pin[1] = {q};
+  sc.forward(pin, [](float x, float y) { return x * y; });
+  const float Pin = pin[0];
+  const float Pprev = dpp_mov<kDppWaveShr1>(Pin);  // outside the select: every lane must take part
+  const float Pex = (si == 0) ? 1.f : Pprev;
   const float Tw = o * Pex;  // termination probability T_i
-  float sO = Tw, sD = Tw * tt, sC0 = Tw * c3[0], sC1 = Tw * c3[1], sC2 = Tw * c3[2];
-  for (int off = 1; off < S; off <<= 1) {
-    const float u0 = __shfl_up(sO, off), u1 = __shfl_up(sD, off), u2 = __shfl_up(sC0, off),
-                u3 = __shfl_up(sC1, off), u4 = __shfl_up(sC2, off);
-    if (si >= off) { sO += u0; sD += u1; sC0 += u2; sC1 += u3; sC2 += u4; }
-  }
-  const int last = jr * S + S - 1;
-  const float Oh = __shfl(sO, last), Dh = __shfl(sD, last);
-  const float Ch[3] = {__shfl(sC0, last), __shfl(sC1, last), __shfl(sC2, last)};
-  const float Pend = __shfl(Pin, last);
+  // the ray's sums end up in its last lane
+  float sums[5] = {Tw, Tw * tt, Tw * c3[0], Tw * c3[1], Tw * c3[2]};
+  sc.forward(sums, [](float x, float y) { return x + y; });
 
-  float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
-  if (valid) {
+  // the ray's outputs, loss and residual signs, in its last lane; the signs (each -1, 0 or 1)
+  // travel packed to the other lanes of the ray
+  int code = 0;
+  if (valid && de == 0) {
+    const float Oh = sums[0], Dh = sums[1];
+    const float Ch[3] = {sums[2], sums[3], sums[4]};
     const float D = in.D, M = in.M;
     const float rD = Dh - D;
     float rC[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) rC[c] = Ch[c] - in.rgb[c];
-    const float rho = (M == 1.0f) ? -Pend : (Oh - M);
-    if (si == 0) {
-      loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
-      if constexpr (!TRAIN) {
-        if (a.out_depth) a.out_depth[ray] = Dh;
-        if (a.out_occ) a.out_occ[ray] = Oh;
-        if (a.out_rgb) { a.out_rgb[3 * ray] = Ch[0]; a.out_rgb[3 * ray + 1] = Ch[1]; a.out_rgb[3 * ray + 2] = Ch[2]; }
-      }
+    const float rho = (M == 1.0f) ? -Pin : (Oh - M);
+    loss += M * fabsf(rD) + lc * M * (fabsf(rC[0]) + fabsf(rC[1]) + fabsf(rC[2])) + lo * fabsf(rho);
+    if constexpr (!TRAIN) {
+      if (a.out_depth) a.out_depth[ray] = Dh;
+      if (a.out_occ) a.out_occ[ray] = Oh;
+      if (a.out_rgb) { a.out_rgb[3 * ray] = Ch[0]; a.out_rgb[3 * ray + 1] = Ch[1]; a.out_rgb[3 * ray + 2] = Ch[2]; }
     }
-    if constexpr (TRAIN) {
-      const float aD = wseed * M * sgnf(rD);
-      const float aO = wseed * lo * sgnf(rho);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) aC[c] = wseed * lc * M * sgnf(rC[c]);
-      g = aD * tt + aC[0] * c3[0] + aC[1] * c3[1] + aC[2] * c3[2] + aO;
-    }
+    auto sgn2 = [](float x) { return (x > 0.f) ? 2 : ((x < 0.f) ? 0 : 1); };
+    code = sgn2(rD) | (sgn2(rho) << 2) | (sgn2(rC[0]) << 4) | (sgn2(rC[1]) << 6) | (sgn2(rC[2]) << 8);
   }
   if constexpr (!TRAIN) return;
+  code = __shfl(code, jr * S + S - 1);
+  auto sgn_of = [&](int i) { return (float)(((code >> (2 * i)) & 3) - 1); };
 
-  // adjoint of rendering: reverse affine scan Q_i = o_i g_i + (1 - o_i) Q_{i+1}
-  float Aq = q, Bq = o * g;
-  for (int off = 1; off < S; off <<= 1) {
-    const float A2 = __shfl_down(Aq, off), B2 = __shfl_down(Bq, off);
-    if (si + off < S) { Bq = Bq + Aq * B2; Aq = Aq * A2; }
+  float g = 0.f, aC[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+    const float M = in.M;
+    const float aD = wseed * M * sgn_of(0);
+    const float aO = wseed * lo * sgn_of(1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) aC[c] = wseed * lc * M * sgn_of(2 + c);
+    g = aD * tt + aC[0] * c3[0] + aC[1] * c3[1] + aC[2] * c3[2] + aO;
   }
-  float Snext = __shfl_down(Bq, 1);
-  if (si == S - 1) Snext = 0.f;
-  // selects, not branches: with stores under divergent branches the compiler kept dzs in
-  // scratch memory
-  const float dO = Pex * (g - Snext);
-  dzs[3] = valid ? dO * o * q : 0.f;
+  // adjoint of rendering: dL/dz_occ,i = o_i (q_i g_i P_i - R_i), R_i = sum over the later samples j
+  // of the ray of g_j T_j (the exclusive suffix sum, a reverse scan shifted by one lane)
+  const float Rin = sc.reverse_sum(g * Tw);
+  const float Rnext = dpp_mov<kDppWaveShl1>(Rin);
+  const float R = (de == 0) ? 0.f : Rnext;
+  dzs[3] = valid ? o * (q * g * Pex - R) : 0.f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) dzs[c] = valid ? Tw * aC[c] * c3[c] * cq[c] : 0.f;
 }
@@ -1006,17 +1073,27 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           point(p, xt);
           forward_pass<H, BF, false>(xt, smem, Bl, act, z, a.var != nullptr);
         }
+        // the pass's dL/dz sits in lanes 32p..32p+31; FP32 moves it to both halves
         float dz[kOut];
+        if constexpr (!BF) {
 #pragma unroll
-        for (int c = 0; c < kOut; ++c) dz[c] = __shfl(dzs[c], 32 * p + n);
+          for (int c = 0; c < kOut; ++c) dz[c] = __shfl(dzs[c], 32 * p + n);
+        }
         // stage dz and h_L, transposed for the output layer's weight gradient
         wave_lds_sync();
-        if (hf == 0) {
+        if constexpr (BF) {  // written by the lanes that hold it (no cross-lane move)
+          if (hf == p) {
+            bf16x4 d4;
 #pragma unroll
-          for (int c = 0; c < kOut; ++c) {
-            if constexpr (BF) reinterpret_cast<__bf16*>(dzt)[c * 40 + n] = (__bf16)dz[c];
-            else reinterpret_cast<float*>(dzt)[n * kOut + c] = dz[c];
+            for (int c = 0; c < kOut; ++c) {
+              d4[c] = (__bf16)dzs[c];
+              reinterpret_cast<__bf16*>(dzt)[c * 40 + n] = d4[c];
+            }
+            *reinterpret_cast<bf16x4*>(dzt + kDzRowsBytes + 8 * n) = d4;
           }
+        } else if (hf == 0) {
+#pragma unroll
+          for (int c = 0; c < kOut; ++c) reinterpret_cast<float*>(dzt)[n * kOut + c] = dz[c];
         }
         if constexpr (BF) {  // sample-major runs (register block jj: features 16jj + 4hf + 0..3, + 8)
 #pragma unroll
@@ -1051,8 +1128,9 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
           // delta of the last hidden layer: W_out^T dz on MFMA (K = 4 outputs padded to 16)
           bf16x8 dzb = {};
           if (hf == 0) {
+            const bf16x4 d4 = *reinterpret_cast<const bf16x4*>(dzt + kDzRowsBytes + 8 * n);
 #pragma unroll
-            for (int c = 0; c < kOut; ++c) dzb[c] = (__bf16)dz[c];
+            for (int c = 0; c < kOut; ++c) dzb[c] = d4[c];
           }
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
