@@ -235,21 +235,21 @@ __device__ __forceinline__ void place_param(unsigned char* img, int p, float w) 
   reinterpret_cast<float*>(img + L.bh_off)[p - off] = w;
 }
 
-// A weight image (a multiple of 16 bytes) to LDS: every thread issues its 16-byte loads in
-// batches of eight before storing any.
-__device__ __forceinline__ void copy_image(const unsigned char* __restrict__ src, unsigned char* dst, int n16,
-                                           int tid, int nt) {
-  const uint4* s4 = reinterpret_cast<const uint4*>(src);
-  uint4* d4 = reinterpret_cast<uint4*>(dst);
-  for (int q0 = 0; q0 < n16; q0 += 8 * nt) {
-    uint4 v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = s4[min(q0 + tid + i * nt, n16 - 1)];  // clamped: in bounds
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int q = q0 + tid + i * nt;
-      if (q < n16) d4[q] = v[i];
-    }
+// A weight image fetched into LDS without registers: each wave's 64 lanes move 1 KiB blocks
+// (global_load_lds_dwordx4: lane l's 16 bytes land at the wave-uniform LDS address + 16 l); the
+// part past the last whole block goes through registers. The LDS writes complete under vmcnt, so
+// readers wait for it (s_waitcnt) and a barrier.
+__device__ __forceinline__ void fetch_image_lds(const unsigned char* src, unsigned char* dst, int bytes,
+                                                int lane, int wave, int nw) {
+  const int blocks = bytes >> 10;
+  for (int b = wave; b < blocks; b += nw)
+    __builtin_amdgcn_global_load_lds(src + (b << 10) + 16 * lane,
+                                     (__attribute__((address_space(3))) void*)(dst + (b << 10)), 16, 0, 0);
+  const int tail = (bytes - (blocks << 10)) >> 4;  // 16-byte pieces left
+  if (wave == nw - 1 && lane < tail) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<u32x4*>(dst + (blocks << 10) + 16 * lane) =
+        *reinterpret_cast<const u32x4*>(src + (blocks << 10) + 16 * lane);
   }
 }
 
@@ -835,8 +835,10 @@ __device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th,
 
 // tbl[j] = first tile of batch object j, tbl[n_objects] = tiles: the exclusive scan of
 // ceil(rays_j / rays_per_tile) over the batch (the launch's objects share one width, so one tile
-// size). Returns the tile count. Called by every thread of the workgroup.
-__device__ int step_table(const StepArgs& a, int32_t* tbl) {
+// size); tray[j] = the batch's ray offsets (n_objects + 1 of them) and tk[j] = object ids, so that
+// a tile finds its object and rays in LDS. Returns the tile count. Called by every thread of the
+// workgroup.
+__device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_t* tk) {
   __shared__ int wtot[4];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int rpt = a.rays_per_tile;
@@ -845,7 +847,11 @@ __device__ int step_table(const StepArgs& a, int32_t* tbl) {
     const int j = base + tid;
     int cnt = 0;
     if (j < a.n_objects) {
-      const int nr = a.ray_offsets[j + 1] - a.ray_offsets[j];
+      const int o0 = a.ray_offsets[j], o1 = a.ray_offsets[j + 1];
+      tray[j] = o0;
+      tk[j] = a.object_ids[j];
+      if (j == a.n_objects - 1) tray[j + 1] = o1;
+      const int nr = o1 - o0;
       cnt = nr > 0 ? (nr + rpt - 1) / rpt : 0;
     }
     int x = cnt;  // inclusive scan over the wave
@@ -886,15 +892,19 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   const int rpw = kSlots / S;
 
   // first tile of every batch object: from the LDS table or from k_worklist
+  // (and, with the LDS table, its ray offsets and object ids)
+  const int tbl_words = round_up(a.n_objects + 1, 4);
   int32_t* tbl = reinterpret_cast<int32_t*>(smem + a.lds_table);
+  int32_t* tray = tbl + tbl_words;
+  int32_t* tk = tray + tbl_words;
   auto first_tile = [&](int j) { return TABLE ? tbl[j] : a.tile_start[j]; };
   int n_tiles;
   if constexpr (TABLE) {
-    n_tiles = step_table(a, tbl);
+    n_tiles = step_table(a, tbl, tray, tk);
     if (blockIdx.x == 0) {  // what k_worklist leaves for the optimiser
       for (int j = tid; j <= a.n_objects; j += blockDim.x) a.tile_start_out[j] = tbl[j];
       for (int j = tid; j < a.n_objects; j += blockDim.x) {
-        const int k = a.object_ids[j];
+        const int k = tk[j];
         const bool valid = k >= 0 && k < a.max_objects;
         if (valid) a.flags[k] = 0;
         a.t_next[j] = (valid && a.desc[k].registered) ? a.desc[k].step + 1 : 0;
@@ -918,29 +928,43 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       if (first_tile(mid) <= tile) jlo = mid; else jhi = mid;
     }
     const int j = jlo;
-    const int k = a.object_ids[j];
-    if (k < 0 || k >= a.max_objects || !a.desc[k].registered) {
-      if (tid == 0) atomicOr(&a.scaler->device_error, 1);
-      continue;
-    }
-    if (a.desc[k].hidden != H) continue;  // handled by the launch for that width
+    const int k = TABLE ? tk[j] : a.object_ids[j];
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
-    const int ray_lo = a.ray_offsets[j] + (tile - first_tile(j)) * rpt;
-    const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
-    if (k != staged) {  // the object's weight image, as it is, with batched 16-byte loads
-      __syncthreads();
-      static_assert(H == 32 && L.B_off % 16 == 0, "weight images are kept for width 32");
-      copy_image(a.img32 + (size_t)k * img32_bytes(BF), smem, L.B_off / 16, tid, blockDim.x);
-      staged = k;
+    const int ray_lo = (TABLE ? tray[j] : a.ray_offsets[j]) + (tile - first_tile(j)) * rpt;
+    const int ray_hi = min(ray_lo + rpt, TABLE ? tray[j + 1] : a.ray_offsets[j + 1]);
+    const int nrays = ray_hi - ray_lo;
+    const int nsub = (nrays + rpw - 1) / rpw;
+    // The object's weight image goes to LDS before its descriptor is checked, so that the two are
+    // fetched together (an id out of range fetches object 0's image, which is then discarded).
+    const bool k_ok = k >= 0 && k < a.max_objects;
+    const int kc = k_ok ? k : 0;
+    static_assert(H == 32 && L.B_off % 16 == 0, "weight images are kept for width 32");
+    const unsigned char* img = a.img32 + (size_t)kc * img32_bytes(BF);
+    const bool restage = (k != staged);
+    if (restage) {  // the object's weight image, as it is, straight into LDS
+      if (staged >= 0) __syncthreads();  // the previous object's weights are no longer read
+      fetch_image_lds(img, smem, L.B_off, lane, wave, nw);
+      staged = -1;
     }
-    __syncthreads();
-    const double cx = a.desc[k].centre[0], cy = a.desc[k].centre[1], cz = a.desc[k].centre[2];
-    const double inv_s = a.desc[k].inv_scale;
+    const ObjDesc& od = a.desc[kc];
+    const int registered = od.registered, hidden = od.hidden;
+    const double cx = od.centre[0], cy = od.centre[1], cz = od.centre[2];
+    const double inv_s = od.inv_scale;
     float wseed = 1.0f;
     if constexpr (TRAIN) {
       if (a.dloss) wseed = a.dloss[j];
       if (a.use_scale) wseed *= a.scaler->scale;
     }
+    if (!k_ok || !registered) {
+      if (tid == 0) atomicOr(&a.scaler->device_error, 1);
+      continue;
+    }
+    if (hidden != H) continue;  // handled by the launch for that width
+    if (restage) {
+      __builtin_amdgcn_s_waitcnt(0);  // this thread's part of the image is in LDS
+      staged = k;
+    }
+    __syncthreads();
 
     f32x16 accW[kLayers][MT][MT];
     f32x4 accWh[H / 16];  // BF16: output-layer weight gradient, 16x16 blocks (rows 0..3 used)
@@ -973,8 +997,6 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
 
     unsigned char* scr = smem + L.scratch_off + wave * L.scratch_wave;
     unsigned char* encc = scr + dz_tile_bytes(BF) + 2 * tr_tile_bytes(H, BF);
-    const int nrays = ray_hi - ray_lo;
-    const int nsub = (nrays + rpw - 1) / rpw;
 
     for (int sub = wave; sub < nsub; sub += nw) {
       asm volatile("" ::: "memory");
@@ -2464,8 +2486,8 @@ static hipError_t launch_tiles_t(const StepArgs& a_in, int nwaves, int grid, hip
     bytes = lds_layout(H, BF, nwaves).total;
     if constexpr (MODE == MODE_STEP) {  // the tile table follows the layout
       if (a.n_objects > kTableMaxObjects || !a.tile_bad) return hipErrorInvalidValue;
-      a.lds_table = bytes;
-      bytes += round_up((a.n_objects + 1) * 4, 16);
+      a.lds_table = bytes;  // first tiles, ray offsets and object ids
+      bytes += 3 * round_up(a.n_objects + 1, 4) * 4;
     }
   } else {
     static_assert(MODE != MODE_STEP, "the in-kernel tile table is built for width 32 only");
