@@ -112,7 +112,8 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   L.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16) + enc_cache_bytes(bf16), 16);
   L.scratch_off = off;
   int scratch = nwaves * L.scratch_wave;
-  const int red = n_params_of(H) * 4;
+  // the tile's gradient at the end: one copy per pair of waves (two with two waves or more)
+  const int red = (nwaves > 1 ? 2 : 1) * round_up(n_params_of(H), 4) * 4;
   if (red > scratch) scratch = red;
   off = round_up(off + scratch, 16);
   L.total = off;

@@ -1344,12 +1344,18 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         for (int mo = 0; mo < MT; ++mo) accDb[l][mo] += __shfl_xor(accDb[l][mo], 32);
     }
     __syncthreads();  // staging buffers are free: reuse them for the tile's gradient
-    float* red = reinterpret_cast<float*>(smem + L.scratch_off);
+    // Two copies of the tile's gradient and loss: waves 0 and 1 write them, waves 2 and 3 then add
+    // theirs (copy c = waves c and c + 2, in that order); the partial is copy 0 + copy 1.
+    constexpr int kRedWords = round_up(n_params_of(H), 4);
+    float* red0 = reinterpret_cast<float*>(smem + L.scratch_off);
+    float* red = red0 + (wave & 1) * kRedWords;
     float* lsum = reinterpret_cast<float*>(smem + L.loss_off);
-    for (int w = 0; w < nw; ++w) {
-      if (wave == w) {
-        const bool first = (w == 0);
-        if (lane == 0) lsum[0] = (first ? 0.f : lsum[0]) + wave_loss;
+    int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 8);
+    if (tid == 0) *any_bad = 0;  // read after the barriers below
+    for (int ph = 0; ph < (nw + 1) / 2; ++ph) {
+      if ((wave >> 1) == ph) {
+        const bool first = (ph == 0);
+        if (lane == 0) lsum[wave & 1] = (first ? 0.f : lsum[wave & 1]) + wave_loss;
         if constexpr (TRAIN) {
           int off = 0;
 #pragma unroll
@@ -1408,12 +1414,10 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       const int P = n_params_of(H);
       const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
       float* dst = a.partial + (size_t)tile * a.p_stride;
-      int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 4);
-      if (tid == 0) *any_bad = 0;
-      __syncthreads();
+      const bool two = nw > 1;
       int bad = 0;
       for (int e = tid; e < P; e += blockDim.x) {
-        const float g = red[e] * inv;
+        const float g = (two ? red0[e] + red0[kRedWords + e] : red0[e]) * inv;
         bad |= !isfinite(g);
         __builtin_nontemporal_store(g, &dst[e]);  // read once, by the next kernel
       }
@@ -1424,7 +1428,7 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         else if (*any_bad) atomicOr(&a.flags[k], 1);
       }
     }
-    if (tid == 0) a.tile_loss[tile] = lsum[0];
+    if (tid == 0) a.tile_loss[tile] = nw > 1 ? lsum[0] + lsum[1] : lsum[0];
     __syncthreads();
   }
 }
