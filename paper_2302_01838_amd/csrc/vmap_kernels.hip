@@ -113,6 +113,16 @@ __device__ __forceinline__ int first_tile_of_block(int n_tiles) {
 // division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
+// sigma(z) and sigma(-z) = 1 - sigma(z) from one exponential e = exp(-z) (as 2^(-z log2 e), the
+// hardware v_exp_f32): sigma(z) = 1 / (1 + e); sigma(-z) = e sigma(z) for z > 0 (e < 1) and
+// 1 - sigma(z) for z <= 0 (sigma(z) <= 1/2, so no cancellation). e = inf for very negative z
+// gives sigma(z) = 0 and sigma(-z) = 1.
+__device__ __forceinline__ void sigm_pair(float z, float& sp, float& sn) {
+  const float e = __builtin_amdgcn_exp2f(-z * 1.44269504088896341f);
+  sp = __builtin_amdgcn_rcpf(1.0f + e);
+  sn = (z > 0.f) ? e * sp : 1.0f - sp;
+}
+
 template <bool BF>
 __device__ __forceinline__ float round_w(float x) {
   if constexpr (BF) return (float)(__bf16)x;
@@ -635,10 +645,9 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
   float o = 0.f, q = 1.f, c3[3] = {0.f, 0.f, 0.f}, cq[3] = {0.f, 0.f, 0.f};
   const float tt = in.tt;
   if (valid) {
-    o = sigm(zs[3]);
-    q = sigm(-zs[3]);  // 1 - o, without cancellation
+    sigm_pair(zs[3], o, q);  // q = 1 - o, without cancellation
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { c3[c] = sigm(zs[c]); cq[c] = sigm(-zs[c]); }
+    for (int c = 0; c < 3; ++c) sigm_pair(zs[c], c3[c], cq[c]);
   }
   // P_i = prod_{j<i} (1 - o_j): inclusive product scan within the ray, then shift by one lane
   float pin[1] = {q};
