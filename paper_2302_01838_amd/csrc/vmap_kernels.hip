@@ -17,8 +17,9 @@
 //      multiplicative scan of (1 - o) and additive scans for the rendered sums;
 //   4. the masked L1 losses of Eqs. 4-7;
 //   5. the adjoint of rendering: with g_i the derivative of the loss with respect to the
-//      termination probability T_i, a reverse affine scan S_i = o_{i+1} g_{i+1} +
-//      (1 - o_{i+1}) S_{i+1} gives dL/do_i = P_i (g_i - S_i) with no division;
+//      termination probability T_i, dL/do_i = P_i g_i - R_i / (1 - o_i) where R_i = sum over the
+//      ray's later samples of g_j T_j (a reverse scan); the logit's adjoint
+//      o_i ((1 - o_i) g_i P_i - R_i) needs no division;
 //   6. the MLP backward: dX products on MFMA from the accumulator layout, dW products on MFMA
 //      after an LDS transpose, accumulated in registers across the wave's sub-tiles.
 // The waves of a workgroup then add their gradients in a fixed order and write one partial
@@ -27,11 +28,11 @@
 //
 // Precision. Both modes use the sine/cosine of vmap_math.h (error below 2.5e-7; the hardware
 // v_sin/v_cos approximations were tried for BF16 and moved enough features across BF16 rounding
-// boundaries to show in the gradients) and accurate expf. FP32 mode uses v_mfma_f32_32x32x2f32.
-// BF16 mode rounds
-// weights, activations and back-propagated deltas to BF16 (round to nearest even) where they
-// enter a product and uses v_mfma_f32_32x32x16_bf16 with FP32 accumulation; encoding, head
-// activations, rendering, losses, reductions and Adam stay FP32.
+// boundaries to show in the gradients) and the hardware exp2 and reciprocal for the logistic.
+// FP32 mode uses v_mfma_f32_32x32x2f32. BF16 mode rounds weights, activations and
+// back-propagated deltas to BF16 (round to nearest even) where they enter a product and uses
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation; encoding, head activations, rendering,
+// losses, reductions and Adam stay FP32.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -711,7 +712,8 @@ __device__ __forceinline__ void render_subtile(const StepArgs& a, int r0, int ns
 //   k_adam        — Adam from the stored gradient (after k_reduce),
 //   k_reduce_adam — both in one pass (the training step when it is split into launches).
 // The optimiser kernels take each object's next step count from the work-list kernel; block
-// (0, j) writes it back, block (0, 0) updates the loss scaler from the flags. No block reads what
+// (0, j) writes it back; block (0, 0) of k_reduce and k_adam, and the extra last row of
+// k_reduce_adam, update the loss scaler from the flags. No block reads what
 // another block of the same launch writes, so no device-scope fence is needed. After a MODE_STEP
 // tile launch (below) the table, step counts and cleared flags come from the tile kernel and the
 // non-finite reports from its tiles.
