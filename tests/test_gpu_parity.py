@@ -182,7 +182,10 @@ def test_full_size_k50_bf16_step():
 
 # ------------------------------------------------------------------------------------ edge cases
 
-@pytest.mark.parametrize("S", [1, 3, 32, 64])
+# The rendering scans run per ray over lanes in rows of 16: besides the extremes, ray lengths whose
+# rays cross rows at odd places (7, 13), span two rows from an odd start (17, 18) or three rows
+# (31: rays at lanes 0 and 31; 33: one ray over lanes 0-32).
+@pytest.mark.parametrize("S", [1, 3, 7, 13, 17, 18, 31, 32, 33, 64])
 def test_samples_per_ray_edges(S):
     base = scenes.make_scene("tiny_k4")
     sc = dataclasses.replace(base, S=S, n_strat=max(1, S // 2))
