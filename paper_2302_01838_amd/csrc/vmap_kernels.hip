@@ -739,10 +739,12 @@ __device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
   return k >= 0 && k < a.max_objects && a.desc[k].registered;
 }
 
-// Whether batch object j (id k) had a non-finite tile partial: its flag, or with per-tile
-// reports the OR of its tiles' entries. Called by every thread of the workgroup.
+// Whether batch object j (id k) had a non-finite tile partial: bit 0 of its flag (set by the tiles;
+// k_reduce_adam marks its own overflows in bit 1, which this test leaves out, so every workgroup
+// of an object decides alike), or with per-tile reports the OR of its tiles' entries. Called by
+// every thread of the workgroup.
 __device__ __forceinline__ bool object_bad(const OptArgs& a, int j, int k) {
-  if (!a.tile_bad) return __syncthreads_or(a.flags[k] != 0) != 0;
+  if (!a.tile_bad) return __syncthreads_or((a.flags[k] & 1) != 0) != 0;
   int bad = 0;
   for (int t = a.tile_start[j] + (int)threadIdx.x; t < a.tile_start[j + 1]; t += blockDim.x)
     bad |= a.tile_bad[t];
@@ -763,7 +765,9 @@ __device__ __forceinline__ int tile_or(const int32_t* __restrict__ bad, int t0, 
 }
 
 // One workgroup (any size): count the batch objects with rays whose gradient was not finite;
-// BF16 loss scaler. Each thread loads its object's id, rays, tiles and descriptor at once (an id
+// BF16 loss scaler. (On the split path an overflow that k_reduce_adam finds while summing finite
+// partials is flagged during this same launch, so it is counted only if its flag is already
+// visible; the per-tile reports of the training step are complete before the launch.) Each thread loads its object's id, rays, tiles and descriptor at once (an id
 // out of range reads object 0's descriptor and is then discarded), then its tiles' reports.
 __device__ void scaler_update(const OptArgs& a) {
   __shared__ int count;
@@ -2168,7 +2172,7 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
       a.m[i] = m;
       a.v[i] = v;
     } else {
-      atomicOr(&a.flags[k], 1);
+      atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
     }
     update_image(a, k, hidden, p, th);
   }
