@@ -869,11 +869,22 @@ __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_
       const int nr = o1 - o0;
       cnt = nr > 0 ? (nr + rpt - 1) / rpt : 0;
     }
-    int x = cnt;  // inclusive scan over the wave
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int y = __shfl_up(x, d);
-      if (lane >= d) x += y;
-    }
+    // inclusive scan over the wave by DPP: shifts within rows of 16, then lane 15 of each row
+    // into the next row and lane 31 into rows 2 and 3 (every move with the whole wave active)
+    int x = cnt;
+    const int lr = lane & 15;
+    int y = __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 1, 0xf, 0xf, false);
+    x += (lr >= 1) ? y : 0;
+    y = __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 2, 0xf, 0xf, false);
+    x += (lr >= 2) ? y : 0;
+    y = __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 4, 0xf, 0xf, false);
+    x += (lr >= 4) ? y : 0;
+    y = __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 8, 0xf, 0xf, false);
+    x += (lr >= 8) ? y : 0;
+    y = __builtin_amdgcn_update_dpp(0, x, kDppBcast15, 0xa, 0xf, false);
+    x += ((lane >> 4) & 1) ? y : 0;
+    y = __builtin_amdgcn_update_dpp(0, x, kDppBcast31, 0xc, 0xf, false);
+    x += (lane >= 32) ? y : 0;
     if (lane == kWave - 1) wtot[wave] = x;
     __syncthreads();
     int before = carry, total = 0;
@@ -936,13 +947,18 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
   // XCD-aware order only when every tile belongs to this launch (tiles of other widths would
   // crowd the XCDs that hold them)
   for (int tile = TABLE ? first_tile_of_block(n_tiles) : (int)blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    // object of this tile: largest j with first_tile(j) <= tile
-    int jlo = 0, jhi = a.n_objects;
-    while (jhi - jlo > 1) {
-      const int mid = (jlo + jhi) >> 1;
-      if (first_tile(mid) <= tile) jlo = mid; else jhi = mid;
+    // object of this tile: the j with first_tile(j) <= tile < first_tile(j + 1) (objects without
+    // rays have an empty range), 64 candidates per wave at a time
+    int j = 0;
+    for (int base = 0; base < a.n_objects; base += kWave) {
+      const int jj = base + lane;
+      const bool hit = jj < a.n_objects && first_tile(jj) <= tile && tile < first_tile(jj + 1);
+      const unsigned long long m = __ballot(hit);
+      if (m) {
+        j = base + __ffsll((long long)m) - 1;
+        break;
+      }
     }
-    const int j = jlo;
     const int k = TABLE ? tk[j] : a.object_ids[j];
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
     const int ray_lo = (TABLE ? tray[j] : a.ray_offsets[j]) + (tile - first_tile(j)) * rpt;
