@@ -1383,6 +1383,11 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
     float* lsum = reinterpret_cast<float*>(smem + L.loss_off);
     int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 8);
     if (tid == 0) *any_bad = 0;  // read after the barriers below
+    // lane, n and hf again, through an empty asm statement: the addresses below are then computed
+    // here, not hoisted to the kernel's start and kept (spilled) across the sub-tiles
+    int rl = lane;
+    asm volatile("" : "+v"(rl));
+    const int rn = rl & 31, rh = rl >> 5;
     for (int ph = 0; ph < (nw + 1) / 2; ++ph) {
       if ((wave >> 1) == ph) {
         const bool first = (ph == 0);
@@ -1399,35 +1404,35 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
               for (int ki = 0; ki < KB; ++ki)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                  const int idx = off + (mo * 32 + rowof(r, hf)) * K + ki * 32 + n;
+                  const int idx = off + (mo * 32 + rowof(r, rh)) * K + ki * 32 + rn;
                   red[idx] = (first ? 0.f : red[idx]) + accW[l][mo][ki][r];
                 }
             off += H * K;
-            if (hf == 0) {
+            if (rh == 0) {
 #pragma unroll
               for (int mo = 0; mo < MT; ++mo) {
-                const int idx = off + mo * 32 + n;
+                const int idx = off + mo * 32 + rn;
                 red[idx] = (first ? 0.f : red[idx]) + accDb[l][mo];
               }
             }
             off += H;
           }
           if constexpr (BF) {
-            if (lane < 16) {
+            if (rl < 16) {
 #pragma unroll
               for (int c = 0; c < kOut; ++c)
 #pragma unroll
                 for (int b = 0; b < H / 16; ++b) {
-                  const int idx = off + c * H + b * 16 + lane;
+                  const int idx = off + c * H + b * 16 + rl;
                   red[idx] = (first ? 0.f : red[idx]) + accWh[b][c];
                 }
             }
-          } else if (hf == 0) {
+          } else if (rh == 0) {
 #pragma unroll
             for (int c = 0; c < kOut; ++c)
 #pragma unroll
               for (int mt = 0; mt < MT; ++mt) {
-                const int idx = off + c * H + mt * 32 + n;
+                const int idx = off + c * H + mt * 32 + rn;
                 red[idx] = (first ? 0.f : red[idx]) + accH[c][mt];
               }
           }
