@@ -247,8 +247,9 @@ int vmap_param_layout(const vmap_ctx* ctx, int32_t object_id, int32_t* n_params,
 /* Use hipGraph replay for vmap_train_step (1) or plain launches (0, default). */
 int vmap_set_graph_mode(vmap_ctx* ctx, int32_t enabled);
 
-/* Launch shape of the step's tile kernel: rays per tile is fixed at init; waves per block and
- * grid size (0 = one block per tile) may change between steps. */
+/* Launch shape of the step's tile kernel: rays per tile is fixed at init; waves per block (1 to 4
+ * in FP32, 1 to 8 in BF16; objects wider than 32 always take 4) and grid size (0 = one block per
+ * tile) may change between steps. VMAP_EINVAL for a wave count out of range. */
 int vmap_set_launch(vmap_ctx* ctx, int32_t waves_per_block, int32_t grid_blocks);
 
 /* Average duration (ms) and count of the tile kernel launches timed with HIP events since the

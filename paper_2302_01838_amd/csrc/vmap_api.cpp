@@ -950,7 +950,9 @@ int vmap_set_graph_mode(vmap_ctx* c, int32_t enabled) {
 
 int vmap_set_launch(vmap_ctx* c, int32_t waves, int32_t grid_blocks) {
   if (!c) return VMAP_EINVAL;
-  if (waves < 1 || waves > 4) return c->fail(VMAP_EINVAL, "waves_per_block must be in [1, 4]");
+  const int max_waves = c->cfg.precision == VMAP_BF16 ? 8 : 4;  // FP32 needs > 256 registers
+  if (waves < 1 || waves > max_waves)
+    return c->fail(VMAP_EINVAL, "waves_per_block must be in [1, 4] (FP32) or [1, 8] (BF16)");
   if (grid_blocks < 0) return c->fail(VMAP_EINVAL, "grid_blocks must be >= 0");
   c->waves = waves;
   c->grid_blocks = grid_blocks;

@@ -78,6 +78,10 @@ __host__ __device__ constexpr int enc_cache_bytes(bool bf16) { return bf16 ? 2 *
 
 // Every offset except `total` is independent of the wave count, so kernels evaluate the layout at
 // compile time (immediate LDS offsets) and only the host needs `total`.
+// Copies of the tile's gradient in the width-32 tile kernel's end-of-tile reduction: wave w adds
+// into copy w mod copies, and the partial is the copies' sum in order.
+__host__ __device__ constexpr int red_copies(int nwaves) { return nwaves >= 8 ? 4 : (nwaves >= 2 ? 2 : 1); }
+
 __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves) {
   LdsLayout L{};
   const int es = bf16 ? 2 : 4;
@@ -107,13 +111,13 @@ __host__ __device__ constexpr LdsLayout lds_layout(int H, bool bf16, int nwaves)
   if (bf16) off = round_up(off + kLayers * H * 32, 16);
   L.B_off = off;
   off = round_up(off + 3 * kFeatures * 4, 16);
-  L.loss_off = off;
-  off = round_up(off + 16, 16);
+  L.loss_off = off;  // the tile's loss per gradient copy (up to 4), then its non-finite flag
+  off = round_up(off + 32, 16);
   L.scratch_wave = round_up(dz_tile_bytes(bf16) + 2 * tr_tile_bytes(H, bf16) + enc_cache_bytes(bf16), 16);
   L.scratch_off = off;
   int scratch = nwaves * L.scratch_wave;
-  // the tile's gradient at the end: one copy per pair of waves (two with two waves or more)
-  const int red = (nwaves > 1 ? 2 : 1) * round_up(n_params_of(H), 4) * 4;
+  // the tile's gradient at the end: red_copies(nwaves) copies, each summing a fixed set of waves
+  const int red = red_copies(nwaves) * round_up(n_params_of(H), 4) * 4;
   if (red > scratch) scratch = red;
   off = round_up(off + scratch, 16);
   L.total = off;

@@ -854,7 +854,7 @@ __device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th,
 // a tile finds its object and rays in LDS. Returns the tile count. Called by every thread of the
 // workgroup.
 __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_t* tk) {
-  __shared__ int wtot[4];
+  __shared__ int wtot[8];  // up to eight waves
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int rpt = a.rays_per_tile;
   int carry = 0;
@@ -903,7 +903,8 @@ __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_
 }
 
 template <int H, bool BF, int MODE>
-__global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(const StepArgs a_in) {
+// BF16 at width 32: up to eight waves per workgroup, 256 registers (two waves per SIMD).
+__global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(const StepArgs a_in) {
   StepArgs a = a_in;
   read_batch(a);
   constexpr int MT = H / 32;
@@ -1375,23 +1376,25 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         for (int mo = 0; mo < MT; ++mo) accDb[l][mo] += __shfl_xor(accDb[l][mo], 32);
     }
     __syncthreads();  // staging buffers are free: reuse them for the tile's gradient
-    // Two copies of the tile's gradient and loss: waves 0 and 1 write them, waves 2 and 3 then add
-    // theirs (copy c = waves c and c + 2, in that order); the partial is copy 0 + copy 1.
+    // nc copies of the tile's gradient and loss (two for two to seven waves, four for eight): the
+    // first nc waves write them, the others then add theirs in turn (copy c = waves c, c + nc, ...,
+    // in that order); the partial is the sum of the copies in order.
     constexpr int kRedWords = round_up(n_params_of(H), 4);
+    const int nc = red_copies(nw);
     float* red0 = reinterpret_cast<float*>(smem + L.scratch_off);
-    float* red = red0 + (wave & 1) * kRedWords;
+    float* red = red0 + (wave % nc) * kRedWords;
     float* lsum = reinterpret_cast<float*>(smem + L.loss_off);
-    int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 8);
+    int* any_bad = reinterpret_cast<int*>(smem + L.loss_off + 16);
     if (tid == 0) *any_bad = 0;  // read after the barriers below
     // lane, n and hf again, through an empty asm statement: the addresses below are then computed
     // here, not hoisted to the kernel's start and kept (spilled) across the sub-tiles
     int rl = lane;
     asm volatile("" : "+v"(rl));
     const int rn = rl & 31, rh = rl >> 5;
-    for (int ph = 0; ph < (nw + 1) / 2; ++ph) {
-      if ((wave >> 1) == ph) {
+    for (int ph = 0; ph < (nw + nc - 1) / nc; ++ph) {
+      if (wave / nc == ph) {
         const bool first = (ph == 0);
-        if (lane == 0) lsum[wave & 1] = (first ? 0.f : lsum[wave & 1]) + wave_loss;
+        if (rl == 0) lsum[wave % nc] = (first ? 0.f : lsum[wave % nc]) + wave_loss;
         if constexpr (TRAIN) {
           int off = 0;
 #pragma unroll
@@ -1450,10 +1453,11 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
       const int P = n_params_of(H);
       const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
       float* dst = a.partial + (size_t)tile * a.p_stride;
-      const bool two = nw > 1;
       int bad = 0;
       for (int e = tid; e < P; e += blockDim.x) {
-        const float g = (two ? red0[e] + red0[kRedWords + e] : red0[e]) * inv;
+        float g = red0[e];
+        for (int c = 1; c < nc; ++c) g += red0[c * kRedWords + e];
+        g *= inv;
         bad |= !isfinite(g);
         __builtin_nontemporal_store(g, &dst[e]);  // read once, by the next kernel
       }
@@ -1464,7 +1468,11 @@ __global__ void __launch_bounds__(256, (BF && H == 32) ? 2 : 1) k_step_tiles(con
         else if (*any_bad) atomicOr(&a.flags[k], 1);
       }
     }
-    if (tid == 0) a.tile_loss[tile] = nw > 1 ? lsum[0] + lsum[1] : lsum[0];
+    if (tid == 0) {
+      float l = lsum[0];
+      for (int c = 1; c < nc; ++c) l += lsum[c];
+      a.tile_loss[tile] = l;
+    }
     __syncthreads();
   }
 }

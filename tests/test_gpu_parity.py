@@ -312,6 +312,29 @@ def test_launch_shapes(rpt, waves, grid):
     check_step(errs, None, "fp32")
 
 
+@pytest.mark.parametrize("waves,rpt", [(8, 0), (8, 72), (6, 0), (5, 0)])
+def test_bf16_wide_workgroups(waves, rpt):
+    """BF16 workgroups of five to eight waves (two or four gradient copies in the end-of-tile
+    reduction, waves adding in two or three turns) against the oracle's BF16 bound."""
+    sc = SCENES["k50_div10"]()
+    objs, states = make_pair(sc, "bf16", rays_per_tile=rpt)
+    objs.set_launch(waves, 0)
+    batch = scenes.make_batch(sc, 0)
+    errs, errs16, _, _ = step_errors(objs, states, batch, "bf16", sc.B)
+    report(f"step bf16 rays_per_tile={rpt} waves={waves}", **errs)
+    report(f"step bf16 rays_per_tile={rpt} waves={waves} vs bf16 oracle", **errs16)
+    check_step(errs, errs16, "bf16")
+
+
+def test_fp32_rejects_eight_waves():
+    """FP32 tile kernels need more than 256 registers per lane: at most four waves per block."""
+    sc = scenes.make_scene("tiny_k4")
+    objs, _ = make_pair(sc, "fp32")
+    with pytest.raises(vm.VmapError):
+        objs.set_launch(8, 0)
+    objs.set_launch(4, 0)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_grid_size_does_not_change_results(precision):
     sc = SCENES["k50_div10"]()

@@ -68,10 +68,12 @@ def test_table_step_matches_split_launches(precision):
 
 
 @pytest.mark.parametrize("precision,rpt,waves,grid", [
-    ("fp32", 1, 4, 0), ("bf16", 5, 2, 0), ("bf16", 0, 3, 0), ("fp32", 0, 1, 3), ("bf16", 0, 4, 7)])
+    ("fp32", 1, 4, 0), ("bf16", 5, 2, 0), ("bf16", 0, 3, 0), ("fp32", 0, 1, 3), ("bf16", 0, 4, 7),
+    ("bf16", 72, 8, 0), ("bf16", 0, 6, 5)])
 def test_table_step_launch_shapes(precision, rpt, waves, grid):
-    """One-ray tiles, one- to four-wave workgroups (the table scan's wave count differs) and grids
-    smaller than the tile count (workgroups loop over tiles of several objects)."""
+    """One-ray tiles, one- to eight-wave workgroups (the table scan's wave count and the number of
+    gradient copies differ) and grids smaller than the tile count (workgroups loop over tiles of
+    several objects)."""
     sc = scaled(scenes.make_scene("k50_uneven"), 10)
     table, split = _pair(sc, precision, rays_per_tile=rpt)
     for o in (table, split):
