@@ -53,7 +53,7 @@ __all__ = [
     "splitmix64", "xavier_init", "normalise", "encode", "mlp_forward", "heads", "render",
     "render_vjp", "ray_losses", "object_forward", "object_loss_and_grad", "adam_update",
     "ObjectState", "step", "query", "bf16_round", "splitmix64_array", "depth_guided_samples",
-    "ray_box", "render_scene",
+    "ray_box", "render_scene", "mlp_backward",
 ]
 
 LAMBDA_COLOUR = 5.0   # lambda_1 of Eq. 7
@@ -141,12 +141,20 @@ def xavier_init(seed: int, H: int, L: int, E: int) -> np.ndarray:
 def bf16_round(x: np.ndarray) -> np.ndarray:
     """Round to the nearest BF16 value (ties to even), via FP32, returned as FP64.
 
-    Only for the optional BF16 diagnostic mode: it tells the error that BF16 products bring by
+    BF16 keeps the upper 16 bits of an IEEE binary32 value. Round to nearest, ties to even, adds
+    0x7FFF plus the lowest kept bit to the pattern and drops the lower half; a finite value whose
+    magnitude rounds past the largest BF16 value becomes an infinity of its sign. NaN stays NaN
+    (the carry would otherwise turn a small payload into an infinity or wrap the pattern).
+
+    Only for the optional BF16 diagnostic modes: they tell the error that BF16 products bring by
     themselves apart from the GPU's accumulation order. The default mode is pure FP64.
     """
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = np.asarray(x, dtype=np.float32)
+    u = np.ascontiguousarray(f).view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore"):  # NaN patterns, replaced below
+        out = u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(f.shape)
+    return np.where(np.isnan(f), np.nan, out)
 
 
 def _identity(x):
@@ -180,19 +188,21 @@ def encode(x: np.ndarray, B: np.ndarray, var: Optional[np.ndarray] = None) -> np
     return np.concatenate([np.sin(phi) * att, np.cos(phi) * att], axis=-1)
 
 
-def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int, rnd=_identity):
+def mlp_forward(theta: np.ndarray, gamma: np.ndarray, H: int, L: int, rnd=_identity,
+                relu_masks=None):
     """Rows of ``gamma`` through the object's MLP. Returns z [N, 4] and the pre-activations.
 
     ``rnd`` is applied to both operands of every product (identity: exact FP64; bf16_round:
-    the diagnostic BF16 mode).
+    the diagnostic BF16 mode). ``relu_masks`` (one boolean [N, H] per hidden layer) replaces the
+    ReLU's own decision a > 0 by a given one: h = a where the mask is set, else 0.
     """
     layers = unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
     h = gamma
     pre = []
-    for W, b in layers[:-1]:
+    for li, (W, b) in enumerate(layers[:-1]):
         a = rnd(h) @ rnd(W).T + b
         pre.append(a)
-        h = np.maximum(a, 0.0)
+        h = np.maximum(a, 0.0) if relu_masks is None else np.where(relu_masks[li], a, 0.0)
     W, b = layers[-1]
     return rnd(h) @ rnd(W).T + b, pre
 
@@ -259,49 +269,69 @@ def ray_losses(O, D, C, P_end, depth, rgb, mask):
 
 # --------------------------------------------------------------------------- one object
 
-def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identity, var=None):
+def object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd=_identity, var=None,
+                   relu_masks=None):
     """Encode + MLP + heads + render for one object's rays. Returns a dict of intermediates.
 
     ``var`` [R, S]: per-sample variance of the sample's Gaussian in world units squared (the
     integrated encoding), or None for point samples; the object frame divides it by s^2.
+    ``relu_masks``: given ReLU decisions (see ``mlp_forward``); ``masks`` in the result holds the
+    decisions used.
     """
     R, S = np.shape(t)
     x = normalise(rays_o, rays_d, t, centre, scale)
     vn = None if var is None else np.asarray(var, np.float64) / np.float64(scale) ** 2
     gamma = encode(x, B, vn)
-    z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L, rnd)
+    z, pre = mlp_forward(theta, gamma.reshape(R * S, -1), H, L, rnd, relu_masks)
+    masks = [a > 0.0 for a in pre] if relu_masks is None else list(relu_masks)
     c, o = heads(z)
     c = c.reshape(R, S, 3)
     o = o.reshape(R, S)
     tt = np.asarray(t, np.float64)
     O, D, C, T, P = render(o, c, tt)
-    return dict(x=x, gamma=gamma.reshape(R * S, -1), pre=pre, z=z, c=c, o=o, t=tt, O=O, D=D,
-                C=C, T=T, P=P)
+    return dict(x=x, gamma=gamma.reshape(R * S, -1), pre=pre, masks=masks, z=z, c=c, o=o, t=tt,
+                O=O, D=D, C=C, T=T, P=P)
 
 
 def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth, rgb, mask,
-                         upstream: float = 1.0, want_grad: bool = True, rnd=_identity, var=None):
+                         upstream: float = 1.0, want_grad: bool = True, rnd=_identity, var=None,
+                         decide=None):
     """L^k of Eq. 7 for one object and, optionally, upstream * dL^k/dtheta.
 
     Returns (loss, grad or None, forward dict). With ``rnd`` = bf16_round every product of the
     MLP (forward and backward, the output layer's seed dz included) takes BF16-rounded operands;
     bias gradients sum the rounded deltas, except the output layer's, which sums dz itself
     (diagnostic mode).
+
+    ``decide`` (a rounding function, e.g. bf16_round) takes the step's integer decisions -- each
+    ReLU's a > 0 and the sign of each L1 residual -- in a forward pass whose products round their
+    operands with it, and the arithmetic (``rnd``) then follows those decisions: the gradient of
+    the piece of the piecewise-smooth loss that the lower-precision forward selects, evaluated in
+    the precision of ``rnd``.
     """
     depth = np.asarray(depth, np.float64)
     rgb = np.asarray(rgb, np.float64)
     mask = np.asarray(mask, np.float64)
-    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd, var)
+    relu_masks = None
+    if decide is not None:
+        fd = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, decide, var)
+        relu_masks = fd["masks"]
+    fw = object_forward(theta, H, L, B, centre, scale, rays_o, rays_d, t, rnd, var, relu_masks)
     R, S = fw["o"].shape
     ld, lc, lo, rho = ray_losses(fw["O"], fw["D"], fw["C"], fw["P"][:, S], depth, rgb, mask)
     loss = float(np.sum(ld) + LAMBDA_COLOUR * np.sum(lc) + LAMBDA_OCC * np.sum(lo))
     if not want_grad:
         return loss, None, fw
     theta64 = np.asarray(theta, np.float64)
-    # cotangents of the rendered quantities (L1 subgradients)
-    gD = upstream * mask * _sgn(fw["D"] - depth)
-    gC = upstream * LAMBDA_COLOUR * mask[:, None] * _sgn(fw["C"] - rgb)
-    g_rho = upstream * LAMBDA_OCC * _sgn(rho)
+    # signs of the residuals (L1 subgradients), from the deciding forward if there is one
+    sD, sC, s_rho = _sgn(fw["D"] - depth), _sgn(fw["C"] - rgb), _sgn(rho)
+    if decide is not None:
+        _, _, _, rho_d = ray_losses(fd["O"], fd["D"], fd["C"], fd["P"][:, S], depth, rgb, mask)
+        sD, sC, s_rho = _sgn(fd["D"] - depth), _sgn(fd["C"] - rgb), _sgn(rho_d)
+    # cotangents of the rendered quantities
+    gD = upstream * mask * sD
+    gC = upstream * LAMBDA_COLOUR * mask[:, None] * sC
+    g_rho = upstream * LAMBDA_OCC * s_rho
     inside = mask == 1.0
     gO = np.where(inside, 0.0, g_rho)           # rho = O - M when M = 0
     gPend = np.where(inside, -g_rho, 0.0)       # rho = -P_{S+1} when M = 1
@@ -312,23 +342,31 @@ def object_loss_and_grad(theta, H, L, B, centre, scale, rays_o, rays_d, t, depth
     of = fw["o"].reshape(R * S)
     dz[:, :3] = dc.reshape(R * S, 3) * cf * (1.0 - cf)
     dz[:, 3] = do.reshape(R * S) * of * (1.0 - of)
-    # MLP backward, last layer first
-    layers = unpack(theta64, H, L, fw["gamma"].shape[-1])
-    hs = [fw["gamma"]] + [np.maximum(a, 0.0) for a in fw["pre"]]
+    g = mlp_backward(theta64, H, L, fw["gamma"], fw["pre"], fw["masks"], dz, rnd)
+    return loss, g, fw
+
+
+def mlp_backward(theta, H: int, L: int, gamma, pre, masks, dz, rnd=_identity):
+    """Reverse mode through the MLP, last layer first: the flat gradient for the seed dz [N, 4].
+
+    delta_out = dz; dW_l = delta_l^T h_{l-1}, db_l = sum over rows of delta_l; delta_{l-1} =
+    (delta_l W_l) * ReLU'(a_{l-1}), with ReLU' the forward's decision ``masks``. ``rnd`` rounds
+    both operands of every product; bias gradients sum the deltas as the products see them,
+    except at the output layer, whose seed dz is summed unrounded.
+    """
+    layers = unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
+    hs = [gamma] + [np.where(m, a, 0.0) for a, m in zip(pre, masks)]
     grads = []
     delta = dz
     last = len(layers) - 1
     for li in range(last, -1, -1):
         W, _ = layers[li]
         d_op = rnd(delta)
-        # bias gradients sum the deltas as the products see them, except at the output layer,
-        # whose seed dz is summed unrounded
         grads.append((d_op.T @ rnd(hs[li]), (delta if li == last else d_op).sum(0)))
         if li > 0:
-            delta = (d_op @ rnd(W)) * (fw["pre"][li - 1] > 0.0)
+            delta = (d_op @ rnd(W)) * masks[li - 1]
     grads.reverse()
-    g = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
-    return loss, g, fw
+    return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
 
 
 def adam_update(theta, m, v, g, step_count, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -389,11 +427,12 @@ class ObjectState:
 
 def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, beta2=0.999,
          eps=1e-8, apply_adam: bool = True, upstream: Optional[Sequence[float]] = None,
-         rnd=_identity):
+         rnd=_identity, decide=None):
     """One training step over a CSR batch; objects are independent and processed in order.
 
     Returns (losses [n] FP64, grads {id: g}, renders dict with O, D, C per ray). ``states`` is
     updated in place when ``apply_adam`` is true; objects with no rays are left untouched.
+    ``rnd`` and ``decide`` as in ``object_loss_and_grad``.
     """
     ids = [int(k) for k in batch["object_ids"]]
     offs = np.asarray(batch["ray_offsets"], np.int64)
@@ -414,7 +453,7 @@ def step(states: Dict[int, ObjectState], batch: dict, B, lr=1e-3, beta1=0.9, bet
         loss, g, fw = object_loss_and_grad(
             st.theta, st.H, st.L, B, st.centre, st.scale, batch["rays_o"][r0:r1],
             batch["rays_d"][r0:r1], batch["t"][r0:r1], batch["depth"][r0:r1],
-            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up, rnd=rnd,
+            batch["rgb"][r0:r1], batch["mask"][r0:r1], upstream=up, rnd=rnd, decide=decide,
             var=None if var is None else var[r0:r1])
         losses[j] = loss
         grads[k] = g

@@ -1,6 +1,6 @@
 """The tile kernels' BF16 packing helpers (paper_2302_01838_amd/csrc/vmap_bf16.h), compiled for
-the host with clang and compared with numpy: rounding to BF16 (nearest even), ReLU on packed
-BF16 pairs, and the ReLU derivative applied to packed deltas."""
+the host with clang and compared with torch's own float32 -> bfloat16 cast: rounding to BF16
+(nearest even), ReLU on packed BF16 pairs, and the ReLU derivative applied to packed deltas."""
 import os
 import shutil
 import subprocess
@@ -32,14 +32,14 @@ int main() {
 
 
 def _bf16_bits(x):
-    """Round float32 to BF16 (nearest even) and return the 16-bit patterns (finite inputs)."""
-    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
-    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return r.astype(np.uint16)
+    """The 16-bit patterns of torch's rounding of float32 values to BF16 (nearest even)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
 
 
 @pytest.mark.skipif(not os.path.exists(CLANG), reason="clang++ of ROCm not available")
-def test_bf16_helpers_against_numpy(tmp_path):
+def test_bf16_helpers_against_torch(tmp_path):
     src = tmp_path / "drv.cpp"
     src.write_text(DRIVER)
     exe = tmp_path / "drv"

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_bf16_pins as bf16_pins
 import test_oracle_pins as pins
 
 
@@ -30,6 +31,7 @@ _orig_adam = oracle.adam_update
 _orig_encode = oracle.encode
 _orig_ray_losses = oracle.ray_losses
 _orig_render_scene = oracle.render_scene
+_orig_mlp_backward = oracle.mlp_backward
 
 
 def _vjp_sign(o, c, t, gO, gD, gC, gPend):
@@ -41,7 +43,7 @@ def _heads_swapped(z):
     return _orig_heads(z[..., [3, 1, 2, 0]])
 
 
-def _mlp_no_relu(theta, gamma, H, L, rnd=None):
+def _mlp_no_relu(theta, gamma, H, L, rnd=None, relu_masks=None):
     layers = oracle.unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
     h = gamma
     pre = []
@@ -92,6 +94,29 @@ def _render_scene_no_threshold(*args, **kw):
     return _orig_render_scene(*args, **kw)
 
 
+def _bf16_truncate(x):
+    # rounding toward zero (the lower 16 bits dropped) instead of to nearest even
+    f = np.asarray(x, dtype=np.float32)
+    u = np.ascontiguousarray(f).view(np.uint32) & np.uint32(0xFFFF0000)
+    return u.view(np.float32).astype(np.float64).reshape(f.shape)
+
+
+def _mlp_backward_seed_unrounded(theta, H, L, gamma, pre, masks, dz, rnd=None):
+    # the output layer's seed dz enters its products unrounded
+    rnd = rnd or (lambda x: x)
+    layers = oracle.unpack(np.asarray(theta, np.float64), H, L, gamma.shape[-1])
+    hs = [gamma] + [np.where(m, a, 0.0) for a, m in zip(pre, masks)]
+    grads, delta, last = [], dz, len(layers) - 1
+    for li in range(last, -1, -1):
+        W, _ = layers[li]
+        d_op = delta if li == last else rnd(delta)
+        grads.append((d_op.T @ rnd(hs[li]), (delta if li == last else d_op).sum(0)))
+        if li > 0:
+            delta = (d_op @ rnd(W)) * masks[li - 1]
+    grads.reverse()
+    return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+
+
 MUTATIONS = {
     "render_index_off_by_one": ("render", _render_no_shift),
     "vjp_wrong_sign_of_leftover_transmittance": ("render_vjp", _vjp_sign),
@@ -103,6 +128,8 @@ MUTATIONS = {
     "colour_loss_not_masked": ("ray_losses", _losses_no_colour_mask),
     "ray_box_union_of_slabs": ("ray_box", _ray_box_union),
     "scene_ranking_ignores_occupancy": ("render_scene", _render_scene_no_threshold),
+    "bf16_truncates_instead_of_nearest_even": ("bf16_round", _bf16_truncate),
+    "bf16_output_seed_unrounded": ("mlp_backward", _mlp_backward_seed_unrounded),
 }
 
 PINS = [
@@ -120,6 +147,9 @@ PINS = [
     pins.test_ray_box_against_brute_force,
     pins.test_render_scene_ranks_constant_occupancy_objects,
     pins.test_integrated_encoding_is_the_gaussian_expectation,
+    bf16_pins.test_bf16_round_matches_torch_cast,
+    lambda: bf16_pins.test_bf16_mode_gradient_matches_torch_objective(0),
+    lambda: bf16_pins.test_decided_gradient_matches_torch_with_fixed_pieces(0),
 ]
 
 
