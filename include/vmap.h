@@ -24,9 +24,12 @@
  *     it and runs asynchronously unless a call says it synchronises. A context is not thread
  *     safe; use one stream per context.
  *   - Floating-point inputs are FP32; integer inputs are int32 unless stated.
- *   - Device-side preconditions (sorted samples, non-decreasing offsets, registered ids) are
- *     checked by the kernels where cheap: an object id that is out of range or unregistered is
- *     skipped and raises the device error flag reported by vmap_step_info().
+ *   - Device-side preconditions are checked by the kernels where cheap: an object id that is
+ *     out of range or unregistered is skipped, and a batch whose ray offsets are not a CSR over
+ *     its n_rays_total rays is not run; both raise a device error bit reported by
+ *     vmap_step_info(). Sorted samples and distinct ids are checked when the context was created
+ *     with the environment variable VMAP_DEBUG=1 (report only). No kernel reads or writes past a
+ *     buffer whatever the device-side inputs hold.
  */
 #ifndef VMAP_H
 #define VMAP_H
@@ -51,7 +54,7 @@ enum { VMAP_FP32 = 0, VMAP_BF16 = 1 };
 
 /* Which per-object array vmap_get_state / vmap_set_state move. */
 enum { VMAP_STATE_PARAMS = 0, VMAP_STATE_ADAM_M = 1, VMAP_STATE_ADAM_V = 2,
-       VMAP_STATE_GRAD = 3, VMAP_STATE_STEP = 4 };
+       VMAP_STATE_GRAD = 3, VMAP_STATE_STEP = 4, VMAP_STATE_SCALER = 5 };
 
 typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed by vmap_destroy */
 
@@ -89,7 +92,8 @@ typedef struct {
   double beta1, beta2, eps;     /* Adam moments (0.9, 0.999) and epsilon (1e-8) */
   double lambda_colour;         /* lambda_1 of Eq. 7 (5) */
   double lambda_occ;            /* lambda_2 of Eq. 7 (10) */
-  double loss_scale_init;       /* BF16: initial dynamic loss scale (4096); FP32 ignores it */
+  double loss_scale_init;       /* BF16: initial dynamic loss scale (4096), a power of two in
+                                 * [2^-125, 2^126]; FP32 ignores it */
 } vmap_config;
 
 /* One object to append to the stack (Sec. 3.2). */
@@ -164,8 +168,13 @@ int vmap_add_object(vmap_ctx* ctx, const vmap_object_desc* desc, const float* in
  * encode, MLP, render (Eq. 3), losses (Eqs. 4-7), backward, Adam. Objects with zero rays
  * keep parameters, moments and step count unchanged. In BF16 mode the loss is scaled before
  * the backward, gradients are unscaled, and an object whose gradient is not finite skips its
- * update while the scale halves. loss_out_dev (device, [n_objects], may be NULL) receives each
- * object's loss L^k of Eq. 7 (unscaled).
+ * update (parameters, moments and step count unchanged) while the scale halves; after
+ * config.scale_growth_interval consecutive steps without a skipped object the scale doubles.
+ * An object counts as not finite when a tile's partial gradient holds a non-finite element or
+ * one of magnitude 2^64 or more (the sum over its tiles can then not overflow unnoticed); the
+ * decision is taken for the whole object before any of its parameters is stored. The scale is a
+ * power of two and stays in [2^-125, 2^126]. loss_out_dev (device, [n_objects], may be NULL)
+ * receives each object's loss L^k of Eq. 7 (unscaled).
  */
 int vmap_train_step(vmap_ctx* ctx, const vmap_batch* batch, float* loss_out_dev, void* stream);
 
@@ -228,15 +237,31 @@ int vmap_backward(vmap_ctx* ctx, const vmap_batch* batch, const float* dloss_dev
 int vmap_adam_step(vmap_ctx* ctx, const vmap_batch* batch, void* stream);
 
 /* Copy one object's parameters / Adam m / Adam v / gradient (FP32, `bytes` = 4 * n_params) or
- * step count (int32, bytes = 4) to or from host memory. Synchronises `stream`. */
+ * step count (int32, bytes = 4) to or from host memory, or (VMAP_STATE_SCALER, object_id
+ * ignored, bytes = 8) the context's loss scaler: FP32 scale, int32 consecutive good steps. With
+ * these a training run stops and resumes where it was (Sec. 3.2: objects stop and resume without
+ * interference): saving every object's four entries and the scaler after N steps and restoring
+ * them into a fresh context gives, after M more steps, bitwise the state of N + M straight steps.
+ * A scaler written must hold a power-of-two scale in [2^-125, 2^126] (VMAP_EINVAL otherwise).
+ * Synchronises `stream`. */
 int vmap_get_state(vmap_ctx* ctx, int32_t object_id, int32_t which, void* host_dst,
                    size_t bytes, void* stream);
 int vmap_set_state(vmap_ctx* ctx, int32_t object_id, int32_t which, const void* host_src,
                    size_t bytes, void* stream);
 
 /* Loss scale, objects skipped by the last step (non-finite gradients) and the device error
- * flags (bit 0: a batch named an invalid object; bit 1: a scene render found more pairs than
- * its max_pairs). Sticky until the context is destroyed. Synchronises `stream`. */
+ * flags, sticky until the context is destroyed:
+ *   bit 0 (1)  a batch named an unregistered or out-of-range object id (that object is skipped);
+ *   bit 1 (2)  a scene render found more pairs than its max_pairs;
+ *   bit 2 (4)  a batch's ray offsets were not a CSR over its rays: ray_offsets[0] != 0, a
+ *              decreasing pair, or ray_offsets[n_objects] != n_rays_total. Checked on the device
+ *              before any tile runs; such a batch is not run at all: no object, Adam moment, step
+ *              count or loss scale changes, its losses are 0 and its renders are not written;
+ *   bit 3 (8)  (contexts created with environment VMAP_DEBUG=1) a ray's sample depths were not
+ *              ascending;
+ *   bit 4 (16) (VMAP_DEBUG=1) an object id appeared twice in a batch.
+ * The VMAP_DEBUG checks run one more kernel per call and only report: the step runs as usual.
+ * Synchronises `stream`. */
 int vmap_step_info(vmap_ctx* ctx, float* loss_scale, int32_t* skipped, int32_t* device_error,
                    void* stream);
 

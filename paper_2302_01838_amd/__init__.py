@@ -20,10 +20,13 @@ import numpy as np
 
 __all__ = ["VmapError", "load_library", "library_path", "ObjectSet", "DeviceBatch", "RenderLoss",
            "VMAP_FP32", "VMAP_BF16", "STATE_PARAMS", "STATE_ADAM_M", "STATE_ADAM_V",
-           "STATE_GRAD", "STATE_STEP", "EXPORTED"]
+           "STATE_GRAD", "STATE_STEP", "STATE_SCALER", "DERR_OBJECT", "DERR_PAIRS",
+           "DERR_OFFSETS", "DERR_T_ORDER", "DERR_DUP_ID", "EXPORTED"]
 
 VMAP_FP32, VMAP_BF16 = 0, 1
-STATE_PARAMS, STATE_ADAM_M, STATE_ADAM_V, STATE_GRAD, STATE_STEP = 0, 1, 2, 3, 4
+STATE_PARAMS, STATE_ADAM_M, STATE_ADAM_V, STATE_GRAD, STATE_STEP, STATE_SCALER = 0, 1, 2, 3, 4, 5
+# device error bits reported by step_info() (include/vmap.h, vmap_step_info)
+DERR_OBJECT, DERR_PAIRS, DERR_OFFSETS, DERR_T_ORDER, DERR_DUP_ID = 1, 2, 4, 8, 16
 _STATUS = {0: "VMAP_OK", 1: "VMAP_EINVAL", 2: "VMAP_ECAPACITY", 3: "VMAP_EHIP", 4: "VMAP_ESTATE",
            5: "VMAP_ENOTSUP"}
 
@@ -192,9 +195,13 @@ class ObjectSet:
                  betas=(0.9, 0.999), eps: float = 1e-8, lambda_colour: float = 5.0,
                  lambda_occ: float = 10.0, loss_scale_init: float = 4096.0,
                  scale_growth_interval: int = 2000, device=None, autotune: bool = True,
-                 split_step: bool = False):
+                 split_step: bool = False, log_path: Optional[str] = None):
         torch = _torch()
         self.lib = load_library()
+        # per-step JSON lines (step, per-object losses, total, loss scale, skipped objects, step
+        # time); each logged step synchronises the stream to read them
+        self.log_path = log_path
+        self.steps_taken = 0
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         # launch shape from the autotuner's cache when none is given
         self.tuned = None
@@ -279,10 +286,28 @@ class ObjectSet:
         torch = _torch()
         if losses is None:
             losses = torch.empty(batch.n_objects, dtype=torch.float32, device=self.device)
+        if self.log_path:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
         self._check(self.lib.vmap_train_step(self.ctx, ctypes.byref(batch.c),
                                              losses.data_ptr() if batch.n_objects else None,
                                              _stream()))
+        self.steps_taken += 1
+        if self.log_path:
+            ev[1].record()
+            ev[1].synchronize()
+            self._log_step(batch, losses, ev[0].elapsed_time(ev[1]))
         return losses
+
+    def _log_step(self, batch: DeviceBatch, losses, ms):
+        import json
+        scale, skipped, err = self.step_info()
+        lv = losses.cpu().numpy().astype(float)
+        rec = {"step": self.steps_taken, "objects": batch.object_ids.tolist(),
+               "loss": lv.tolist(), "total": float(lv.sum()), "loss_scale": scale,
+               "skipped": skipped, "device_error": err, "step_us": ms * 1e3}
+        with open(self.log_path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
     def forward(self, batch: DeviceBatch, renders: bool = True):
         torch = _torch()
@@ -378,7 +403,11 @@ class ObjectSet:
         return out
 
     # -- state I/O and diagnostics
-    def get_state(self, k: int, which: int = STATE_PARAMS) -> np.ndarray:
+    def get_state(self, k: int, which: int = STATE_PARAMS):
+        if which == STATE_SCALER:  # (scale, consecutive good steps); k is ignored
+            out = np.zeros(2, dtype=np.int32)
+            self._check(self.lib.vmap_get_state(self.ctx, -1, which, out.ctypes.data, 8, _stream()))
+            return float(out[:1].view(np.float32)[0]), int(out[1])
         if which == STATE_STEP:
             out = np.zeros(1, dtype=np.int32)
         else:
@@ -388,12 +417,42 @@ class ObjectSet:
         return out if which != STATE_STEP else int(out[0])
 
     def set_state(self, k: int, which: int, value) -> None:
-        if which == STATE_STEP:
+        if which == STATE_SCALER:
+            arr = np.zeros(2, dtype=np.int32)
+            arr[:1].view(np.float32)[0] = value[0]
+            arr[1] = value[1]
+            k = -1
+        elif which == STATE_STEP:
             arr = np.asarray([value], dtype=np.int32)
         else:
             arr = np.ascontiguousarray(value, dtype=np.float32)
         self._check(self.lib.vmap_set_state(self.ctx, k, which, arr.ctypes.data, arr.nbytes,
                                             _stream()))
+
+    def save(self, path: str) -> None:
+        """Checkpoint every object's parameters, Adam moments and step count, and the loss
+        scaler, to an .npz file (plain arrays, no pickled objects)."""
+        arrays = {}
+        for k in sorted(self.n_params):
+            arrays[f"theta_{k}"] = self.get_state(k, STATE_PARAMS)
+            arrays[f"m_{k}"] = self.get_state(k, STATE_ADAM_M)
+            arrays[f"v_{k}"] = self.get_state(k, STATE_ADAM_V)
+            arrays[f"step_{k}"] = np.asarray([self.get_state(k, STATE_STEP)], np.int32)
+        scale, good = self.get_state(-1, STATE_SCALER)
+        arrays["scaler_scale"] = np.asarray([scale], np.float32)
+        arrays["scaler_good"] = np.asarray([good], np.int32)
+        np.savez(path, **arrays)
+
+    def load(self, path: str) -> None:
+        """Restore a checkpoint written by save() into objects already added with the same ids
+        and widths."""
+        with np.load(path, allow_pickle=False) as z:
+            for k in sorted(self.n_params):
+                self.set_state(k, STATE_PARAMS, z[f"theta_{k}"])
+                self.set_state(k, STATE_ADAM_M, z[f"m_{k}"])
+                self.set_state(k, STATE_ADAM_V, z[f"v_{k}"])
+                self.set_state(k, STATE_STEP, int(z[f"step_{k}"][0]))
+            self.set_state(-1, STATE_SCALER, (float(z["scaler_scale"][0]), int(z["scaler_good"][0])))
 
     def step_info(self):
         s = ctypes.c_float()

@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -29,7 +31,7 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, t_next, batch, tile_bad, tile_loss, partial, wimage, img32, total;
+  size_t tile_start, flags, t_next, mark, batch, tile_bad, tile_loss, partial, wimage, img32, total;
   size_t wimage_stride;
   int max_tiles;
 };
@@ -57,7 +59,10 @@ const char* check_config(const vmap_config* c) {
     return "Adam settings out of range (lr > 0, 0 <= beta < 1, eps > 0)";
   if (!(c->lambda_colour >= 0.0) || !(c->lambda_occ >= 0.0)) return "loss weights must be >= 0";
   if (c->precision == VMAP_BF16) {
-    if (!(c->loss_scale_init > 0.0) || !std::isfinite(c->loss_scale_init)) return "loss_scale_init must be > 0";
+    int e2 = 0;
+    if (!(c->loss_scale_init > 0.0) || !std::isfinite(c->loss_scale_init) ||
+        std::frexp(c->loss_scale_init, &e2) != 0.5 || e2 - 1 < -125 || e2 - 1 > 126)
+      return "loss_scale_init must be a power of two in [2^-125, 2^126] (the unscale is then exact)";
     if (c->scale_growth_interval < 1) return "scale_growth_interval must be >= 1";
   }
   return nullptr;
@@ -114,6 +119,7 @@ WorkLayout work_layout(const vmap_config* c) {
   w.tile_start = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
   w.flags = off; off = align256(off + (size_t)c->max_objects * 4);
   w.t_next = off; off = align256(off + (size_t)c->max_objects * 4);
+  w.mark = off; off = align256(off + (size_t)c->max_objects * 4);  // debug validation of ids
   w.batch = off; off = align256(off + sizeof(BatchDev));
   w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.tile_bad = off; off = align256(off + (size_t)w.max_tiles * 4);
@@ -156,6 +162,7 @@ struct vmap_ctx {
   int waves = 4;
   int grid_blocks = 0;
   int device = 0;
+  bool debug = false;  // VMAP_DEBUG=1 at creation: device validation of every batch
   std::vector<HostObj> objs;
   int n_registered = 0;
   std::string err;
@@ -188,6 +195,7 @@ struct vmap_ctx {
   int32_t* tile_start() { return reinterpret_cast<int32_t*>(work + wl.tile_start); }
   int32_t* flags() { return reinterpret_cast<int32_t*>(work + wl.flags); }
   int32_t* t_next() { return reinterpret_cast<int32_t*>(work + wl.t_next); }
+  int32_t* mark() { return reinterpret_cast<int32_t*>(work + wl.mark); }
   BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
   int32_t* tile_bad() { return reinterpret_cast<int32_t*>(work + wl.tile_bad); }
   unsigned char* img32() { return work + wl.img32; }
@@ -240,6 +248,8 @@ std::vector<int> widths_present(vmap_ctx* c) {
 StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   StepArgs a{};
   a.n_objects = b->n_objects;
+  a.n_rays = b->n_rays_total;
+  a.max_tiles = c->wl.max_tiles;
   a.S = b->samples_per_ray;
   a.rays_per_tile = c->rays_per_tile;
   a.rays_per_tile_wide = c->rays_per_tile_wide;
@@ -270,6 +280,15 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   return a;
 }
 
+// Debug validation of the batch before its first kernel (contexts created with VMAP_DEBUG=1).
+int enqueue_debug(vmap_ctx* c, const vmap_batch* b, hipStream_t s, const BatchDev* bd = nullptr) {
+  if (!c->debug || b->n_objects == 0) return VMAP_OK;
+  StepArgs a = make_step_args(c, b);
+  a.bd = bd;
+  const hipError_t e = launch_debug_batch(a, c->mark(), s);
+  return e == hipSuccess ? VMAP_OK : c->hip_fail(e, "debug validation launch");
+}
+
 hipEvent_t pooled_event(vmap_ctx* c) {
   if (!c->event_pool.empty()) {
     hipEvent_t e = c->event_pool.back();
@@ -283,10 +302,9 @@ hipEvent_t pooled_event(vmap_ctx* c) {
 
 hipError_t enqueue_worklist(vmap_ctx* c, const vmap_batch* b, hipStream_t s,
                             const BatchDev* bd = nullptr) {
-  return launch_worklist(b->n_objects, b->object_ids, b->ray_offsets, c->rays_per_tile,
-                         c->rays_per_tile_wide,
-                         c->cfg.max_objects, c->desc(), c->tile_start(), c->flags(), c->t_next(),
-                         bd, s);
+  return launch_worklist(b->n_objects, b->n_rays_total, b->object_ids, b->ray_offsets,
+                         c->rays_per_tile, c->rays_per_tile_wide, c->cfg.max_objects, c->desc(),
+                         c->scaler(), c->tile_start(), c->flags(), c->t_next(), bd, s);
 }
 
 OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* grad_out,
@@ -317,6 +335,7 @@ OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* 
   a.eps = c->cfg.eps;
   a.bf16 = c->cfg.precision == VMAP_BF16;
   a.growth = c->cfg.scale_growth_interval;
+  a.max_tiles = c->wl.max_tiles;
   a.img32 = c->img32();
   return a;
 }
@@ -428,6 +447,7 @@ int enqueue_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t 
 
 int enqueue_train(vmap_ctx* c, const vmap_batch* b, float* loss_out, hipStream_t s, bool allow_timing,
                   const BatchDev* bd = nullptr) {
+  if (int rc = enqueue_debug(c, b, s, bd)) return rc;
   if (table_in_tiles(c, b)) return enqueue_step(c, b, loss_out, s, allow_timing, bd);
   hipError_t e = enqueue_worklist(c, b, s, bd);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
@@ -529,6 +549,8 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   c->rays_per_tile_wide = default_rays_per_tile_wide(cfg);
   c->min_rays_per_tile = min_rays_per_tile(cfg);
   c->objs.resize(cfg->max_objects);
+  const char* dbg = std::getenv("VMAP_DEBUG");
+  c->debug = dbg && dbg[0] && std::strcmp(dbg, "0") != 0;
   (void)hipGetDevice(&c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = launch_fill_zero(state_dev, sl.total, s);
@@ -627,20 +649,9 @@ int vmap_train_step(vmap_ctx* c, const vmap_batch* b, float* loss_out, void* str
     c->ring_used[slot] = true;
   }
   BatchDev& hb = c->ring[slot];
-  hb.n_objects = b->n_objects;
-  hb.S = b->samples_per_ray;
-  hb.n_rays = b->n_rays_total;
-  hb.pad = 0;
-  hb.object_ids = b->object_ids;
-  hb.ray_offsets = b->ray_offsets;
-  hb.rays_o = b->rays_o;
-  hb.rays_d = b->rays_d;
-  hb.t = b->t;
-  hb.depth = b->depth;
-  hb.rgb = b->rgb;
-  hb.mask = b->mask;
-  hb.var = b->var;
-  hb.loss_out = loss_out;
+  hb = make_batch_dev(b->n_objects, b->samples_per_ray, b->n_rays_total, b->object_ids,
+                      b->ray_offsets, b->rays_o, b->rays_d, b->t, b->depth, b->rgb, b->mask,
+                      loss_out, b->var);
   std::vector<int64_t> key = {b->n_objects, b->n_rays_total, b->samples_per_ray, c->waves,
                               c->grid_blocks, (int64_t)widths_present(c).size(),
                               loss_out ? 1 : 0};
@@ -684,6 +695,7 @@ int vmap_forward(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* depth
   if (rc) return rc;
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = enqueue_debug(c, b, s))) return rc;
   hipError_t e = enqueue_worklist(c, b, s);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
   rc = enqueue_tiles(c, b, MODE_FWD, nullptr, depth_out, rgb_out, occ_out, s, true);
@@ -795,6 +807,7 @@ int vmap_backward(vmap_ctx* c, const vmap_batch* b, const float* dloss, float* g
   if (!dloss && b->n_objects > 0) return c->fail(VMAP_EINVAL, "dloss must not be NULL");
   if (b->n_objects == 0) return VMAP_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = enqueue_debug(c, b, s))) return rc;
   hipError_t e = enqueue_worklist(c, b, s);
   if (e != hipSuccess) return c->hip_fail(e, "worklist launch");
   rc = enqueue_tiles(c, b, MODE_TRAIN, dloss, nullptr, nullptr, nullptr, s, true);
@@ -874,6 +887,12 @@ int vmap_sample_rays(vmap_ctx* c, int32_t n_rays, int32_t S, int32_t n_strat, co
 }
 
 static int state_ptr(vmap_ctx* c, int32_t k, int32_t which, size_t bytes, void** dev) {
+  if (which == VMAP_STATE_SCALER) {  // the context's loss scaler: scale (FP32), good steps (int32)
+    static_assert(offsetof(ScalerState, good_steps) == 4, "scale and good_steps are adjacent");
+    if (bytes != 8) return c->fail(VMAP_EINVAL, "scaler state is 8 bytes (float scale, int32 good steps)");
+    *dev = c->scaler();
+    return VMAP_OK;
+  }
   if (k < 0 || k >= c->cfg.max_objects || !c->objs[k].registered)
     return c->fail(VMAP_ESTATE, "object id is not registered");
   const size_t P = (size_t)c->objs[k].n_params;
@@ -913,6 +932,16 @@ int vmap_set_state(vmap_ctx* c, int32_t k, int32_t which, const void* host_src, 
   void* dev = nullptr;
   int rc = state_ptr(c, k, which, bytes, &dev);
   if (rc) return rc;
+  if (which == VMAP_STATE_SCALER) {
+    float sc;
+    int32_t good;
+    std::memcpy(&sc, host_src, 4);
+    std::memcpy(&good, static_cast<const char*>(host_src) + 4, 4);
+    int e2 = 0;
+    if (!(sc > 0.f) || !std::isfinite(sc) || std::frexp(sc, &e2) != 0.5f || e2 - 1 < -125 || e2 - 1 > 126 ||
+        good < 0)
+      return c->fail(VMAP_EINVAL, "scaler state: scale must be a power of two in [2^-125, 2^126], good steps >= 0");
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(dev, host_src, bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && which == VMAP_STATE_PARAMS) e = restage_image(c, k, s);

@@ -28,14 +28,74 @@ struct ObjDesc {
   int32_t n_params;    // parameters of this object
 };
 
+// Bits of ScalerState::device_error (sticky).
+enum DeviceError {
+  DERR_OBJECT = 1,    // a batch named an unregistered or out-of-range object id
+  DERR_PAIRS = 2,     // a scene render found more (ray, object) pairs than its capacity
+  DERR_OFFSETS = 4,   // ray offsets not a CSR over the batch's rays; the batch was not run
+  DERR_T_ORDER = 8,   // debug validation: sample depths not ascending within a ray
+  DERR_DUP_ID = 16,   // debug validation: an object id appears twice in a batch
+};
+
 // Loss scaler and step bookkeeping in device memory.
 struct ScalerState {
   float scale;          // dynamic loss scale (1 in FP32 mode)
   int32_t good_steps;   // consecutive steps without a skipped object
   int32_t skipped;      // objects skipped by the last Adam launch
-  int32_t device_error; // set when a batch names an invalid object
-  int32_t pad[12];
+  int32_t device_error; // DeviceError bits
+  int32_t batch_ok;     // the last work list's batch passed the offsets check (read by Adam)
+  int32_t pad[11];
 };
+
+// Device-side checks of a batch's ray offsets. The tile count and every ray index come from
+// offsets in device memory, which the host does not read; a batch is run only if every object's
+// segment satisfies 0 <= o0 <= o1 <= n_rays and the last offset equals the host's ray count. Then
+// the segments tile [0, n_rays) in order and the tile count is at most the workspace's (the host
+// checked ceil(n_rays / rays_per_tile) + n_objects against it); the clamps below keep every index
+// in bounds regardless.
+__host__ __device__ constexpr bool segment_ok(int o0, int o1, int n_rays) {
+  return 0 <= o0 && o0 <= o1 && o1 <= n_rays;
+}
+// Segment [o0, o1) of batch object j of n: inside [0, n_rays], in order, starting the batch at 0
+// (j = 0) and ending it at n_rays (j = n - 1). Every object passing means a CSR over n_rays rays.
+__host__ __device__ constexpr bool batch_segment_ok(int j, int n_objects, int o0, int o1, int n_rays) {
+  return segment_ok(o0, o1, n_rays) && (j != 0 || o0 == 0) && (j != n_objects - 1 || o1 == n_rays);
+}
+__host__ __device__ constexpr int clamp_tiles(int n_tiles, int max_tiles) {
+  return n_tiles < 0 ? 0 : (n_tiles > max_tiles ? max_tiles : n_tiles);
+}
+// Tile range [t0, t1) of one object, both in [0, n_tiles].
+struct TileRange {
+  int t0, t1;
+};
+__host__ __device__ constexpr TileRange clamp_tile_range(int t0, int t1, int n_tiles) {
+  const int a = t0 < 0 ? 0 : (t0 > n_tiles ? n_tiles : t0);
+  const int b = t1 < a ? a : (t1 > n_tiles ? n_tiles : t1);
+  return TileRange{a, b};
+}
+// Rays [lo, hi) of the tile that is number `tile_in_object` of an object whose segment is
+// [o0, o1): both in [0, n_rays] with lo <= hi whatever the inputs (64-bit intermediates).
+struct RayRange {
+  int lo, hi;
+};
+__host__ __device__ constexpr RayRange tile_ray_range(int o0, int o1, int tile_in_object, int rpt,
+                                                      int n_rays) {
+  const long long lo0 = (long long)o0 + (long long)tile_in_object * rpt;
+  const long long hi0 = lo0 + rpt < (long long)o1 ? lo0 + rpt : (long long)o1;
+  const long long lo = lo0 < 0 ? 0 : (lo0 > n_rays ? n_rays : lo0);
+  const long long hi = hi0 < lo ? lo : (hi0 > n_rays ? n_rays : hi0);
+  return RayRange{(int)lo, (int)hi};
+}
+// Tiles of an object of nr rays (0 for an empty or invalid segment).
+__host__ __device__ constexpr int tiles_of(int nr, int rpt) { return nr > 0 ? (nr + rpt - 1) / rpt : 0; }
+
+// A tile partial is reported non-finite also when an element's magnitude reaches this bound. An
+// object has T < 2^27 tiles and each rounded addition grows a running sum by at most a factor
+// (1 + 2^-24), so a sum of partials below 2^64 in magnitude stays below 2^27 * 2^64 * e^8 < 2^103
+// and cannot overflow FP32: the skip of an object is decided from its tiles' reports alone,
+// before any store.
+constexpr float kPartialLimit = 18446744073709551616.0f;  // 2^64
+__host__ __device__ inline bool partial_bad(float g) { return !(g > -kPartialLimit && g < kPartialLimit); }
 
 // Byte offsets of the LDS regions of the tile kernel (computed identically on host and device).
 struct LdsLayout {
@@ -188,6 +248,33 @@ struct BatchDev {
   float* loss_out;
   const float* var;
 };
+static_assert(sizeof(BatchDev) == 4 * 4 + 10 * 8, "make_batch_dev must set every field");
+
+// The whole descriptor from its fields, zero-initialised first: every writer (host ring, device
+// scene scan) stores it as one value, so no field is left holding a previous batch's bytes.
+__host__ __device__ inline BatchDev make_batch_dev(int n_objects, int S, int n_rays,
+                                                   const int32_t* object_ids,
+                                                   const int32_t* ray_offsets, const float* rays_o,
+                                                   const float* rays_d, const float* t,
+                                                   const float* depth, const float* rgb,
+                                                   const float* mask, float* loss_out,
+                                                   const float* var) {
+  BatchDev b{};
+  b.n_objects = n_objects;
+  b.S = S;
+  b.n_rays = n_rays;
+  b.object_ids = object_ids;
+  b.ray_offsets = ray_offsets;
+  b.rays_o = rays_o;
+  b.rays_d = rays_d;
+  b.t = t;
+  b.depth = depth;
+  b.rgb = rgb;
+  b.mask = mask;
+  b.loss_out = loss_out;
+  b.var = var;
+  return b;
+}
 
 // Arguments of the gradient / optimiser kernels.
 struct OptArgs {
@@ -214,12 +301,15 @@ struct OptArgs {
   double lr, beta1, beta2, eps;
   int bf16;
   int growth;
+  int max_tiles;              // tiles the workspace holds (bounds every tile range)
   const BatchDev* bd;         // if not NULL, n_objects, ids, offs and loss_out come from here
 };
 
 struct StepArgs {
   // batch
   int n_objects;
+  int n_rays;            // rays in the batch's arrays (the host's ray count)
+  int max_tiles;         // tiles the workspace holds
   int S;
   int rays_per_tile;
   int rays_per_tile_wide;     // tiles of objects wider than 32
@@ -316,13 +406,15 @@ struct SceneArgs {
 
 // Kernel launchers (vmap_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
-hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int rays_per_tile_wide, int max_objects,
-                           const ObjDesc* desc,
+hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
+                           const int32_t* ray_offsets, int rays_per_tile, int rays_per_tile_wide,
+                           int max_objects, const ObjDesc* desc, ScalerState* scaler,
                            int32_t* tile_start, int32_t* flags, int32_t* t_next,
                            const BatchDev* bd, hipStream_t s);
 hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwaves, int grid,
                         hipStream_t s);
+// Debug validation of a batch (distinct ids, ascending sample depths); mark: [max_objects] int32.
+hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s);
 enum OptKind { OPT_LOSS = 0, OPT_REDUCE = 1, OPT_ADAM = 2, OPT_REDUCE_ADAM = 3 };
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s);
 hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,

@@ -506,6 +506,7 @@ __device__ __forceinline__ void forward_pass(const float xt[4], const unsigned c
 __device__ __forceinline__ void read_batch(StepArgs& a) {
   if (const BatchDev* b = a.bd) {
     a.n_objects = b->n_objects;
+    a.n_rays = b->n_rays;
     a.S = b->S;
     a.object_ids = b->object_ids;
     a.ray_offsets = b->ray_offsets;
@@ -746,8 +747,8 @@ __device__ __forceinline__ bool obj_valid(const OptArgs& a, int k) {
 __device__ __forceinline__ bool object_bad(const OptArgs& a, int j, int k) {
   if (!a.tile_bad) return __syncthreads_or((a.flags[k] & 1) != 0) != 0;
   int bad = 0;
-  for (int t = a.tile_start[j] + (int)threadIdx.x; t < a.tile_start[j + 1]; t += blockDim.x)
-    bad |= a.tile_bad[t];
+  const TileRange tr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  for (int t = tr.t0 + (int)threadIdx.x; t < tr.t1; t += blockDim.x) bad |= a.tile_bad[t];
   return __syncthreads_or(bad) != 0;
 }
 
@@ -771,13 +772,15 @@ __device__ __forceinline__ int tile_or(const int32_t* __restrict__ bad, int t0, 
 // out of range reads object 0's descriptor and is then discarded), then its tiles' reports.
 __device__ void scaler_update(const OptArgs& a) {
   __shared__ int count;
+  if (!a.scaler->batch_ok) return;  // the batch did not run: the scaler stays as it is
   if (threadIdx.x == 0) count = 0;
   __syncthreads();
   int skipped = 0;
   for (int jj = threadIdx.x; jj < a.n_objects; jj += blockDim.x) {
     const int kk = a.ids[jj];
     const int r0 = a.offs[jj], r1 = a.offs[jj + 1];
-    const int t0 = a.tile_start[jj], t1 = a.tile_start[jj + 1];
+    const TileRange tr = clamp_tile_range(a.tile_start[jj], a.tile_start[jj + 1], a.max_tiles);
+    const int t0 = tr.t0, t1 = tr.t1;
     const bool in_range = kk >= 0 && kk < a.max_objects;
     const int kc = in_range ? kk : 0;
     const bool registered = a.desc[kc].registered != 0;
@@ -791,11 +794,13 @@ __device__ void scaler_update(const OptArgs& a) {
     const int total = count;
     a.scaler->skipped = total;
     if (a.bf16) {
+      // the scale stays a power of two in [2^-125, 2^126], so that it and its inverse are normal
+      const float sc = a.scaler->scale;
       if (total > 0) {
-        a.scaler->scale *= 0.5f;
+        if (sc >= 0x1p-124f) a.scaler->scale = sc * 0.5f;
         a.scaler->good_steps = 0;
       } else if (++a.scaler->good_steps >= a.growth) {
-        a.scaler->scale *= 2.0f;
+        if (sc <= 0x1p125f) a.scaler->scale = sc * 2.0f;
         a.scaler->good_steps = 0;
       }
     }
@@ -851,13 +856,14 @@ __device__ __forceinline__ void adam_elem(const AdamCoef& c, float g, float& th,
 // tbl[j] = first tile of batch object j, tbl[n_objects] = tiles: the exclusive scan of
 // ceil(rays_j / rays_per_tile) over the batch (the launch's objects share one width, so one tile
 // size); tray[j] = the batch's ray offsets (n_objects + 1 of them) and tk[j] = object ids, so that
-// a tile finds its object and rays in LDS. Returns the tile count. Called by every thread of the
-// workgroup.
+// a tile finds its object and rays in LDS. Returns the tile count, or -1 when the offsets fail
+// the check of segment_ok (ray_offsets[0] = 0, every segment inside [0, n_rays] and in order,
+// ray_offsets[n] = n_rays); then no tile runs. Called by every thread of the workgroup.
 __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_t* tk) {
   __shared__ int wtot[8];  // up to eight waves
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int rpt = a.rays_per_tile;
-  int carry = 0;
+  int carry = 0, bad = 0;
   for (int base = 0; base < a.n_objects; base += nt) {
     const int j = base + tid;
     int cnt = 0;
@@ -866,8 +872,9 @@ __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_
       tray[j] = o0;
       tk[j] = a.object_ids[j];
       if (j == a.n_objects - 1) tray[j + 1] = o1;
-      const int nr = o1 - o0;
-      cnt = nr > 0 ? (nr + rpt - 1) / rpt : 0;
+      const bool ok = batch_segment_ok(j, a.n_objects, o0, o1, a.n_rays);
+      bad |= !ok;
+      cnt = ok ? tiles_of(o1 - o0, rpt) : 0;
     }
     // inclusive scan over the wave by DPP: shifts within rows of 16, then lane 15 of each row
     // into the next row and lane 31 into rows 2 and 3 (every move with the whole wave active)
@@ -898,8 +905,7 @@ __device__ int step_table(const StepArgs& a, int32_t* tbl, int32_t* tray, int32_
     __syncthreads();
   }
   if (tid == 0) tbl[a.n_objects] = carry;
-  __syncthreads();
-  return carry;
+  return __syncthreads_or(bad) ? -1 : carry;
 }
 
 template <int H, bool BF, int MODE>
@@ -929,7 +935,11 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
   if constexpr (TABLE) {
     n_tiles = step_table(a, tbl, tray, tk);
     if (blockIdx.x == 0) {  // what k_worklist leaves for the optimiser
-      for (int j = tid; j <= a.n_objects; j += blockDim.x) a.tile_start_out[j] = tbl[j];
+      if (tid == 0) {
+        a.scaler->batch_ok = n_tiles >= 0;
+        if (n_tiles < 0) atomicOr(&a.scaler->device_error, DERR_OFFSETS);
+      }
+      for (int j = tid; j <= a.n_objects; j += blockDim.x) a.tile_start_out[j] = n_tiles >= 0 ? tbl[j] : 0;
       for (int j = tid; j < a.n_objects; j += blockDim.x) {
         const int k = tk[j];
         const bool valid = k >= 0 && k < a.max_objects;
@@ -940,6 +950,7 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
   } else {
     n_tiles = a.tile_start[a.n_objects];
   }
+  n_tiles = clamp_tiles(n_tiles, a.max_tiles);
 
   float* Bl = reinterpret_cast<float*>(smem + L.B_off);
   if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
@@ -962,8 +973,10 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
     }
     const int k = TABLE ? tk[j] : a.object_ids[j];
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
-    const int ray_lo = (TABLE ? tray[j] : a.ray_offsets[j]) + (tile - first_tile(j)) * rpt;
-    const int ray_hi = min(ray_lo + rpt, TABLE ? tray[j + 1] : a.ray_offsets[j + 1]);
+    const RayRange rr = tile_ray_range(TABLE ? tray[j] : a.ray_offsets[j],
+                                       TABLE ? tray[j + 1] : a.ray_offsets[j + 1],
+                                       tile - first_tile(j), rpt, a.n_rays);
+    const int ray_lo = rr.lo, ray_hi = rr.hi;
     const int nrays = ray_hi - ray_lo;
     const int nsub = (nrays + rpw - 1) / rpw;
     // The object's weight image goes to LDS before its descriptor is checked, so that the two are
@@ -1449,7 +1462,8 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
       __syncthreads();
     }
     if constexpr (TRAIN) {
-      // unscale (exact: the scale is a power of two) and flag a non-finite partial
+      // unscale (exact: the scale is a power of two) and report a partial that is not finite or
+      // too large to be summed safely (partial_bad)
       const int P = n_params_of(H);
       const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
       float* dst = a.partial + (size_t)tile * a.p_stride;
@@ -1458,7 +1472,7 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
         float g = red0[e];
         for (int c = 1; c < nc; ++c) g += red0[c * kRedWords + e];
         g *= inv;
-        bad |= !isfinite(g);
+        bad |= partial_bad(g);
         __builtin_nontemporal_store(g, &dst[e]);  // read once, by the next kernel
       }
       if (bad) *any_bad = 1;  // every writer stores the same value
@@ -1512,7 +1526,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
   const int m16 = lane & 15, kg = lane >> 4;
   const int S = a.S;
   const int rpw = kSlots / S;
-  const int n_tiles = a.tile_start[a.n_objects];
+  const int n_tiles = clamp_tiles(a.tile_start[a.n_objects], a.max_tiles);
   float* Bl = reinterpret_cast<float*>(smem + C.B_off);
   if (tid < 3 * kFeatures) Bl[tid] = a.B[tid];
   unsigned char* const scr0 = smem + C.scratch_off;
@@ -1533,8 +1547,9 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
     }
     if (a.desc[k].hidden != H) continue;
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
-    const int ray_lo = a.ray_offsets[j] + (tile - a.tile_start[j]) * rpt;
-    const int ray_hi = min(ray_lo + rpt, a.ray_offsets[j + 1]);
+    const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], tile - a.tile_start[j],
+                                       rpt, a.n_rays);
+    const int ray_lo = rr.lo, ray_hi = rr.hi;
     const unsigned char* wb = smem;
     if constexpr (GW) {
       wb = a.wimage + (size_t)k * a.wimage_stride;
@@ -1847,7 +1862,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
                   float v = acc[rb][cb][i];
                   if (last) {
                     v *= inv;
-                    bad |= !isfinite(v);
+                    bad |= partial_bad(v);
                   }
                   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), prs, lo, co, 0);
                 } else {
@@ -1940,7 +1955,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
     if constexpr (TRAIN) {
       auto put = [&](int idx, float g) {
         g *= inv;
-        bad |= !isfinite(g);
+        bad |= partial_bad(g);
         dst[idx] = g;
       };
 #pragma unroll
@@ -2048,10 +2063,13 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
 // Tile offsets per batch object (exclusive scan of ceil(rays / rays_per_tile)); clears the
 // non-finite flags of the batch's objects and records each object's next Adam step count, so
 // that the optimiser kernels read it from here while one of their blocks advances the count.
+// Checks the ray offsets as step_table does: a batch that fails gets no tiles, and the optimiser
+// kernels leave every object unchanged (ScalerState::batch_ok).
 
-__global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t* ids,
+__global__ void __launch_bounds__(1024) k_worklist(int n_objects, int n_rays, const int32_t* ids,
                                                    const int32_t* offs, int rpt, int rpt_wide,
                                                    int max_objects, const ObjDesc* __restrict__ desc,
+                                                   ScalerState* __restrict__ scaler,
                                                    int32_t* __restrict__ tile_start,
                                                    int32_t* __restrict__ flags,
                                                    int32_t* __restrict__ t_next,
@@ -2059,22 +2077,25 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
   __shared__ int part[1024];
   if (bd) {
     n_objects = bd->n_objects;
+    n_rays = bd->n_rays;
     ids = bd->object_ids;
     offs = bd->ray_offsets;
   }
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (n_objects + nt - 1) / nt;
   const int j0 = min(tid * per, n_objects), j1 = min(j0 + per, n_objects);
-  int local = 0;
+  int local = 0, bad = 0;
   // rays per tile of batch object j (by its width; invalid ids take the narrow size)
   auto rpt_of = [&](int j) {
     const int k = ids[j];
     return (k >= 0 && k < max_objects && desc[k].registered) ? tile_rays(desc[k].hidden, rpt, rpt_wide) : rpt;
   };
+  auto seg_ok = [&](int j, int o0, int o1) { return batch_segment_ok(j, n_objects, o0, o1, n_rays); };
   for (int j = j0; j < j1; ++j) {
-    const int nr = offs[j + 1] - offs[j];
-    const int rj = rpt_of(j);
-    local += (nr > 0) ? (nr + rj - 1) / rj : 0;
+    const int o0 = offs[j], o1 = offs[j + 1];
+    const bool ok = seg_ok(j, o0, o1);
+    bad |= !ok;
+    local += ok ? tiles_of(o1 - o0, rpt_of(j)) : 0;
     const int k = ids[j];
     const bool valid = k >= 0 && k < max_objects;
     if (valid) flags[k] = 0;
@@ -2082,7 +2103,7 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
     t_next[j] = (valid && desc[k].registered) ? desc[k].step + 1 : 0;
   }
   part[tid] = local;
-  __syncthreads();
+  const bool any_bad = __syncthreads_or(bad) != 0;
   for (int off = 1; off < nt; off <<= 1) {
     const int v = (tid >= off) ? part[tid - off] : 0;
     __syncthreads();
@@ -2091,12 +2112,15 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, const int32_t*
   }
   int run = part[tid] - local;
   for (int j = j0; j < j1; ++j) {
-    tile_start[j] = run;
-    const int nr = offs[j + 1] - offs[j];
-    const int rj = rpt_of(j);
-    run += (nr > 0) ? (nr + rj - 1) / rj : 0;
+    tile_start[j] = any_bad ? 0 : run;
+    const int o0 = offs[j], o1 = offs[j + 1];
+    run += seg_ok(j, o0, o1) ? tiles_of(o1 - o0, rpt_of(j)) : 0;
   }
-  if (tid == nt - 1) tile_start[n_objects] = part[nt - 1];
+  if (tid == nt - 1) {
+    tile_start[n_objects] = any_bad ? 0 : part[nt - 1];
+    scaler->batch_ok = !any_bad;
+    if (any_bad) atomicOr(&scaler->device_error, DERR_OFFSETS);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_reduce(const OptArgs a_in, int want_grad) {
@@ -2104,8 +2128,9 @@ __global__ void __launch_bounds__(256) k_reduce(const OptArgs a_in, int want_gra
   read_batch(a);
   const int j = blockIdx.y;
   const int k = a.ids[j];
-  const bool valid = obj_valid(a, k);
-  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
+  const bool valid = obj_valid(a, k) && a.scaler->batch_ok;
+  const TileRange tr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  const int t0 = tr.t0, t1 = tr.t1;
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
     float s = 0.f;
     if (valid)
@@ -2131,7 +2156,7 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
   const int j = blockIdx.y;
   if (blockIdx.x == 0 && j == 0) scaler_update(a);
   const int k = a.ids[j];
-  if (!obj_valid(a, k) || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
+  if (!a.scaler->batch_ok || !obj_valid(a, k) || a.offs[j + 1] <= a.offs[j] || a.flags[k]) return;
   const int t = a.t_next[j];
   const AdamCoef c = adam_coef(a, t);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2147,9 +2172,10 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.desc[k].step = t;
 }
 
-// Training step: gradient and update in one pass. A non-finite gradient element (possible only
-// if finite tile partials overflow when added) leaves its parameter unchanged and flags the
-// object for the skip count. Every load of a thread depends on at most the batch object's id, ray
+// Training step: gradient and update in one pass. The tiles report a partial holding an element
+// that is not finite or reaches 2^64 in magnitude (partial_bad), so an object none of whose tiles
+// reported has a finite summed gradient and its skip is decided, for the whole object, before any
+// store; the element test below is a guard that this bound makes unreachable. Every load of a thread depends on at most the batch object's id, ray
 // range and tile range, so a workgroup waits for device memory twice (those, then the object's
 // data); the validity checks only decide what is stored. Thread 0 works out the Adam
 // coefficients while the loads are in flight. The grid has one row of workgroups per batch object
@@ -2163,9 +2189,11 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     return;
   }
   const int k = a.ids[j];
-  const int t0 = a.tile_start[j], t1 = a.tile_start[j + 1];
+  const TileRange tr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  const int t0 = tr.t0, t1 = tr.t1;
   const int r0 = a.offs[j], r1 = a.offs[j + 1];
   const int t = a.t_next[j];
+  const int batch_ok = a.scaler->batch_ok;
   const bool in_range = k >= 0 && k < a.max_objects;
   const int kc = in_range ? k : 0;  // loads of an id out of range are discarded
   const ObjDesc& d = a.desc[kc];
@@ -2184,7 +2212,7 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   if (lead && a.loss_out) loss = tile_sum(a.tile_loss, 1, t0, t1, 0);
   __shared__ float sh[2];
   if (threadIdx.x == 0) adam_coef_store(a, t, sh);
-  const bool valid = in_range && registered != 0;
+  const bool valid = in_range && registered != 0 && batch_ok;
   if (lead && a.loss_out) a.loss_out[j] = valid ? loss : 0.f;
   if (!valid || r1 <= r0) return;
   // the barrier of object_bad also publishes the coefficients
@@ -2398,21 +2426,10 @@ __global__ void __launch_bounds__(1024) k_scene_scan(const SceneArgs a, int nblk
     a.ray_offsets[a.n_objects] = min(total, a.max_pairs);
     if (a.n_pairs_out) *a.n_pairs_out = total;
     if (total > a.max_pairs) atomicOr(&a.scaler->device_error, 2);
-    BatchDev* b = a.bd;
-    b->n_objects = a.n_objects;
-    b->S = a.S;
-    b->n_rays = min(total, a.max_pairs);
-    b->pad = 0;
-    b->object_ids = a.object_ids;
-    b->ray_offsets = a.ray_offsets;
-    b->rays_o = a.pair_o;
-    b->rays_d = a.pair_d;
-    b->t = a.pair_t;
-    b->depth = nullptr;
-    b->rgb = nullptr;
-    b->mask = nullptr;
-    b->loss_out = nullptr;
-    b->var = nullptr;  // point samples (the scratch holding the descriptor is not cleared)
+    // one store of the whole descriptor: every field is written (the scratch holding it is not
+    // cleared, and a field left out would be read as garbage); no targets or losses, point samples
+    *a.bd = make_batch_dev(a.n_objects, a.S, min(total, a.max_pairs), a.object_ids, a.ray_offsets,
+                           a.pair_o, a.pair_d, a.pair_t, nullptr, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
@@ -2495,6 +2512,42 @@ hipError_t launch_scene(int phase, const SceneArgs& a, hipStream_t s) {
     default:
       hipLaunchKernelGGL(k_scene_composite, dim3(nblk), dim3(256), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+// Debug validation of a batch (contexts created with VMAP_DEBUG=1), before its step: workgroup 0
+// checks that no object id appears twice (an id's mark takes the batch index of each occurrence in
+// turn; a mark that was not cleared names a repeat), the others that every ray's sample depths
+// ascend. Findings go to the sticky device error bits; the step itself is not changed.
+__global__ void __launch_bounds__(256) k_debug_batch(const StepArgs a_in, int32_t* __restrict__ mark) {
+  StepArgs a = a_in;
+  read_batch(a);
+  if (blockIdx.x == 0) {
+    for (int j = threadIdx.x; j < a.n_objects; j += blockDim.x) {
+      const int k = a.object_ids[j];
+      if (k >= 0 && k < a.max_objects) mark[k] = -1;
+    }
+    __syncthreads();
+    int dup = 0;
+    for (int j = threadIdx.x; j < a.n_objects; j += blockDim.x) {
+      const int k = a.object_ids[j];
+      if (k >= 0 && k < a.max_objects) dup |= atomicExch(&mark[k], j) != -1;
+    }
+    if (__syncthreads_or(dup) && threadIdx.x == 0) atomicOr(&a.scaler->device_error, DERR_DUP_ID);
+    return;
+  }
+  const int S = a.S;
+  int bad = 0;
+  for (int r = (blockIdx.x - 1) * blockDim.x + threadIdx.x; r < a.n_rays; r += (gridDim.x - 1) * blockDim.x) {
+    const float* tr = a.t + (size_t)r * S;
+    for (int i = 0; i + 1 < S; ++i) bad |= !(tr[i] <= tr[i + 1]);
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&a.scaler->device_error, DERR_T_ORDER);
+}
+
+hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s) {
+  const int blocks = 1 + std::max(1, std::min(1024, (a.n_rays + 255) / 256));
+  hipLaunchKernelGGL(k_debug_batch, dim3(blocks), dim3(256), 0, s, a, mark);
   return hipGetLastError();
 }
 
@@ -2633,13 +2686,14 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_worklist(int n_objects, const int32_t* object_ids, const int32_t* ray_offsets,
-                           int rays_per_tile, int rays_per_tile_wide, int max_objects,
-                           const ObjDesc* desc, int32_t* tile_start, int32_t* flags,
-                           int32_t* t_next, const BatchDev* bd, hipStream_t s) {
-  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, object_ids, ray_offsets,
-                     rays_per_tile, rays_per_tile_wide, max_objects, desc, tile_start, flags,
-                     t_next, bd);
+hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
+                           const int32_t* ray_offsets, int rays_per_tile, int rays_per_tile_wide,
+                           int max_objects, const ObjDesc* desc, ScalerState* scaler,
+                           int32_t* tile_start, int32_t* flags, int32_t* t_next,
+                           const BatchDev* bd, hipStream_t s) {
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, n_rays, object_ids,
+                     ray_offsets, rays_per_tile, rays_per_tile_wide, max_objects, desc, scaler,
+                     tile_start, flags, t_next, bd);
   return hipGetLastError();
 }
 

@@ -78,6 +78,19 @@ def test_invalid_config_rejected(lib, field, value):
     assert lib.vmap_last_error(None)
 
 
+@pytest.mark.parametrize("value,ok", [(4096.0, True), (2.0 ** -125, True), (2.0 ** 126, True),
+                                      (3000.0, False), (0.0, False), (-4096.0, False),
+                                      (2.0 ** -126, False), (2.0 ** 127, False),
+                                      (float("inf"), False), (float("nan"), False)])
+def test_loss_scale_init_is_a_bounded_power_of_two(lib, value, ok):
+    """BF16 unscaling multiplies by 1/scale, exact only for a power of two; the scaler keeps the
+    scale in [2^-125, 2^126] so that it and its inverse stay normal."""
+    cfg = vm.default_config(precision=vm.VMAP_BF16, loss_scale_init=value)
+    assert (lib.vmap_state_bytes(ctypes.byref(cfg)) > 0) == ok
+    cfg32 = vm.default_config(precision=vm.VMAP_FP32, loss_scale_init=value)
+    assert lib.vmap_state_bytes(ctypes.byref(cfg32)) > 0  # FP32 ignores the scale
+
+
 def test_init_argument_errors_before_device_use(lib):
     cfg = vm.default_config()
     ctx = ctypes.c_void_p()
