@@ -205,6 +205,26 @@ int vmap_render_scene(vmap_ctx* ctx, int32_t n_rays, const float* rays_o, const 
                       float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
                       int32_t* n_pairs_out, void* stream);
 
+/*
+ * vmap_render_scene without the scratch arguments, for callers that cannot allocate device
+ * memory per call: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation. The pairs go to a static array of VMAP_SCENE_STATIC_SCRATCH_BYTES bytes that the
+ * library holds on each GPU it runs on until the process ends (looked up once per GPU by
+ * vmap_init_objects); the call allocates nothing and frees nothing. Arguments, outputs and
+ * results are those of vmap_render_scene (bitwise: the same kernels run). A scene whose
+ * vmap_scene_scratch_bytes(n_rays, n_objects, max_pairs, S) exceeds the array returns
+ * VMAP_ECAPACITY with a message, before anything is enqueued. Every call on a GPU, from any
+ * context, uses that GPU's one array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller; a call needs nothing left in the array by
+ * an earlier one (every byte it reads it first writes).
+ */
+#define VMAP_SCENE_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+int vmap_render_scene_static(vmap_ctx* ctx, int32_t n_rays, const float* rays_o,
+                             const float* rays_d, int32_t n_objects, const int32_t* object_ids,
+                             int32_t S, float t_min, float occ_threshold, int32_t max_pairs,
+                             float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                             int32_t* n_pairs_out, void* stream);
+
 /* Occupancy [n] and, if rgb_out is not NULL, colour [n, 3] of n world-frame points (device
  * [n, 3]) under object `object_id`'s model (shape query inside its bound, Sec. 3.4). */
 int vmap_query_occupancy(vmap_ctx* ctx, int32_t object_id, const float* pts_world_dev,

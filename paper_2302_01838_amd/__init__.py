@@ -91,6 +91,8 @@ EXPORTED = {
     "vmap_render_scene": (ctypes.c_int, [_P, _I, _P, _P, _I, _P, _I, ctypes.c_float,
                                          ctypes.c_float, _I, _P, ctypes.c_size_t, _P, _P, _P,
                                          _P, _P, _P]),
+    "vmap_render_scene_static": (ctypes.c_int, [_P, _I, _P, _P, _I, _P, _I, ctypes.c_float,
+                                                ctypes.c_float, _I, _P, _P, _P, _P, _P, _P]),
     "vmap_sample_rays": (ctypes.c_int, [_P, _I, _I, _I, _P, _P, _P, ctypes.c_float, ctypes.c_uint64,
                                         _P, _P]),
     "vmap_forward": (ctypes.c_int, [_P, _BATCH, _P, _P, _P, _P, _P]),

@@ -553,7 +553,14 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   c->debug = dbg && dbg[0] && std::strcmp(dbg, "0") != 0;
   (void)hipGetDevice(&c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = launch_fill_zero(state_dev, sl.total, s);
+  // the allocation-free scene render's static scratch on this GPU (looked up once per GPU)
+  hipError_t e = static_scratch_init(c->device);
+  if (e != hipSuccess) {
+    g_init_error = std::string("looking up the static scene scratch: ") + hipGetErrorString(e);
+    delete c;
+    return VMAP_EHIP;
+  }
+  e = launch_fill_zero(state_dev, sl.total, s);
   if (e == hipSuccess) e = launch_fill_zero(workspace_dev, wl.total, s);
   if (e == hipSuccess) e = launch_init_scaler(c->scaler(), bf ? (float)cfg->loss_scale_init : 1.0f, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->B(), B_host, 3 * kFeatures * sizeof(float), hipMemcpyHostToDevice, s);
@@ -727,12 +734,12 @@ size_t vmap_scene_scratch_bytes(int32_t n_rays, int32_t n_objects, int32_t max_p
   return scene_layout(n_rays, n_objects, max_pairs, S).total;
 }
 
-int vmap_render_scene(vmap_ctx* c, int32_t n_rays, const float* rays_o, const float* rays_d,
-                      int32_t n_objects, const int32_t* object_ids, int32_t S, float t_min,
-                      float occ_threshold, int32_t max_pairs, void* scratch, size_t scratch_bytes,
-                      float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
-                      int32_t* n_pairs_out, void* stream) {
-  if (!c) return VMAP_EINVAL;
+// The scene render over a given scratch (caller-owned, or the library's static array).
+static int render_scene(vmap_ctx* c, int32_t n_rays, const float* rays_o, const float* rays_d,
+                        int32_t n_objects, const int32_t* object_ids, int32_t S, float t_min,
+                        float occ_threshold, int32_t max_pairs, void* scratch, size_t scratch_bytes,
+                        float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                        int32_t* n_pairs_out, void* stream) {
   if (n_rays < 0) return c->fail(VMAP_EINVAL, "n_rays must be >= 0");
   if (n_objects < 0 || n_objects > c->cfg.max_objects)
     return c->fail(VMAP_EINVAL, "n_objects must be in [0, max_objects]");
@@ -798,6 +805,42 @@ int vmap_render_scene(vmap_ctx* c, int32_t n_rays, const float* rays_o, const fl
   e = launch_scene(1, a, s);
   if (e != hipSuccess) return c->hip_fail(e, "scene composite launch");
   return VMAP_OK;
+}
+
+int vmap_render_scene(vmap_ctx* c, int32_t n_rays, const float* rays_o, const float* rays_d,
+                      int32_t n_objects, const int32_t* object_ids, int32_t S, float t_min,
+                      float occ_threshold, int32_t max_pairs, void* scratch, size_t scratch_bytes,
+                      float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                      int32_t* n_pairs_out, void* stream) {
+  if (!c) return VMAP_EINVAL;
+  return render_scene(c, n_rays, rays_o, rays_d, n_objects, object_ids, S, t_min, occ_threshold,
+                      max_pairs, scratch, scratch_bytes, depth_out, rgb_out, occ_out, id_out,
+                      n_pairs_out, stream);
+}
+
+int vmap_render_scene_static(vmap_ctx* c, int32_t n_rays, const float* rays_o,
+                             const float* rays_d, int32_t n_objects, const int32_t* object_ids,
+                             int32_t S, float t_min, float occ_threshold, int32_t max_pairs,
+                             float* depth_out, float* rgb_out, float* occ_out, int32_t* id_out,
+                             int32_t* n_pairs_out, void* stream) {
+  static_assert(VMAP_SCENE_STATIC_SCRATCH_BYTES == kStaticSceneScratchBytes,
+                "the header states the static scratch's size");
+  if (!c) return VMAP_EINVAL;
+  if (n_rays > 0 && n_objects > 0 && S >= 1 && S <= kSlots && max_pairs >= 0 &&
+      (int64_t)n_rays * n_objects <= ((int64_t)1 << 31) - 1) {
+    const size_t need = scene_layout(n_rays, n_objects, max_pairs, S).total;
+    if (need > kStaticSceneScratchBytes)
+      return c->fail(VMAP_ECAPACITY,
+                     "scene needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                         std::to_string(kStaticSceneScratchBytes) +
+                         " of the static array (fewer rays, objects or max_pairs, or "
+                         "vmap_render_scene with a caller scratch)");
+  }
+  void* ptr = static_scratch(c->device);
+  if (!ptr) return c->fail(VMAP_ESTATE, "static scene scratch not set up on this context's GPU");
+  return render_scene(c, n_rays, rays_o, rays_d, n_objects, object_ids, S, t_min, occ_threshold,
+                      max_pairs, ptr, kStaticSceneScratchBytes, depth_out, rgb_out, occ_out,
+                      id_out, n_pairs_out, stream);
 }
 
 int vmap_backward(vmap_ctx* c, const vmap_batch* b, const float* dloss, float* grad_out, void* stream) {

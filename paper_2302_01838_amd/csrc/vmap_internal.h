@@ -427,6 +427,12 @@ hipError_t launch_sample(int n_rays, int S, int n_strat, const float* t_near, co
                          const float* depth, float sigma, uint64_t seed, float* t_out,
                          hipStream_t s);
 int tiles_supported(int H, bool bf16);
+// The allocation-free scene render's scratch: a static device array per GPU of this many bytes.
+constexpr size_t kStaticSceneScratchBytes = (size_t)16 << 20;
+// Looks up the array's device address on `device`, which must be current (once per GPU).
+hipError_t static_scratch_init(int device);
+// The address found by static_scratch_init for `device`, or NULL before it ran.
+void* static_scratch(int device);
 // phase 0: pairs (count, scan, fill); phase 1: per-ray composite
 hipError_t launch_scene(int phase, const SceneArgs& a, hipStream_t s);
 int tile_lds_bytes(int H, bool bf16, int nwaves);

@@ -39,6 +39,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "vmap_internal.h"
@@ -2731,6 +2732,41 @@ hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,
 hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
   hipLaunchKernelGGL(k_init_scaler, dim3(1), dim3(64), 0, s, sc, scale);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of the allocation-free scene render: one array per GPU, held until the process ends,
+// shared by every call on that GPU. Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returned for the GPU, looked up once per GPU with that GPU current.
+static __device__ __align__(256) unsigned char scratch[kStaticSceneScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int current = -1;
+  hipError_t e = hipGetDevice(&current);
+  if (e != hipSuccess) return e;
+  if (current != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace vmapi
