@@ -139,6 +139,17 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     wall = time.perf_counter() - t0
     event_ms_per_step = ev0.elapsed_time(ev1) / steps
     losses = loss_hist.sum(1).cpu().numpy()
+    # per-step HIP events in a separate pass (an event between steps costs a few microseconds of
+    # idle GPU, so the headline loop above has none): the median over steps 10..end
+    n_ev = min(steps, 100) + 10
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev + 1)]
+    evs[0].record()
+    for i in range(n_ev):
+        objs.step(dev_batches[(warmup + i) % len(dev_batches)])
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = [evs[i].elapsed_time(evs[i + 1]) for i in range(10, n_ev)]
+    event_ms_median = statistics.median(per_step)
     samples = [dev_batches[(warmup + i) % len(dev_batches)].n_samples for i in range(steps)]
     active = [int(np.sum(np.diff(dev_batches[(warmup + i) % len(dev_batches)].ray_offsets) > 0))
               for i in range(steps)]
@@ -161,6 +172,7 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
         wall_s=wall,
         ms_per_step=1e3 * wall / steps,
         event_ms_per_step=event_ms_per_step,
+        event_ms_per_step_median=event_ms_median,
         ray_samples_per_s=sum(samples) / wall,
         object_steps_per_s=sum(active) / wall,
         final_loss=float(np.mean(losses[-10:])),
@@ -176,8 +188,70 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     )
 
 
+def sweep_hidden(widths, steps, n_objects=50, graph=False):
+    """Vectorised vs sequential training step over hidden widths (Sec. 4.3, Fig. "ablative
+    vectorised", right): n_objects objects of one width, 120 rays x 10 samples each, BF16. Widths
+    32, 64 and 128 run the fused tile kernels, the others the layered path. Returns ms per step."""
+    import dataclasses
+    import torch
+    import scenes
+    import paper_2302_01838_amd as vm
+    base = scenes.make_scene("tiny_k4")
+    out = []
+    for H in widths:
+        rng = np.random.default_rng(H)
+        objs_ = []
+        for k in range(n_objects):
+            o = base.objects[k % base.n_objects]
+            objs_.append(dataclasses.replace(o, centre=rng.uniform(-2, 2, size=3), hidden=H,
+                                             seed=(1 << 41) + k))
+        sc = dataclasses.replace(base, objects=objs_)
+        batches = [scenes.make_batch(sc, i) for i in range(3)]
+        full = [vm.DeviceBatch(b) for b in batches]
+        per_obj = []
+        for b in batches:
+            offs = b["ray_offsets"]
+            row = []
+            for j in range(n_objects):
+                sl = slice(offs[j], offs[j + 1])
+                sub = {f: b[f][sl] for f in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
+                sub["object_ids"] = b["object_ids"][j:j + 1]
+                sub["ray_offsets"] = np.array([0, offs[j + 1] - offs[j]], dtype=np.int32)
+                sub["S"] = b["S"]
+                row.append(vm.DeviceBatch(sub))
+            per_obj.append(row)
+        res = {"hidden": H, "path": "fused tile kernel" if H in (32, 64, 128) else "layered"}
+        for mode in ("vectorised", "sequential"):
+            objs = vm.ObjectSet(max_objects=n_objects, B=sc.B, hidden=H, precision="bf16",
+                                max_rays=full[0].n_rays, max_samples_per_ray=sc.S)
+            for ob in sc.objects:
+                objs.add(ob.norm_centre, ob.norm_scale, hidden=H, seed=ob.seed)
+            res["params_per_object"] = objs.n_params[0]
+            objs.set_graph_mode(graph)
+
+            def one(i):
+                if mode == "vectorised":
+                    objs.step(full[i % 3])
+                else:
+                    for db in per_obj[i % 3]:
+                        objs.step(db)
+            for i in range(3):
+                one(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                one(i)
+            torch.cuda.synchronize()
+            res[mode + "_ms"] = 1e3 * (time.perf_counter() - t0) / steps
+            objs.close()
+        log(f"sweep H={H}: vectorised {res['vectorised_ms']:.3f} ms, "
+            f"sequential {res['sequential_ms']:.3f} ms")
+        out.append(res)
+    return out
+
+
 def sweep_objects(counts, steps, precision, graph):
-    """Vectorised vs sequential training step over object counts (the paper's Sec. 4.5 ablation,
+    """Vectorised vs sequential training step over object counts (the paper's Sec. 4.3 ablation,
     on synthetic scenes shaped like its workload: 120 rays x 10 samples per object, hidden 32).
 
     Vectorised: one vmap_train_step over all objects. Sequential: one vmap_train_step per object
@@ -240,42 +314,92 @@ def sweep_objects(counts, steps, precision, graph):
     return out
 
 
-def cpu_baseline(scene, batches, budget_s=15.0, workload=WORKLOAD):
-    """The FP64 oracle (numpy; OpenBLAS threads as configured) on consecutive steps."""
-    import oracle
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_cores(cap: int = 16) -> int:
+    """Cores this process may use, at most ``cap`` (a one-GPU machine's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+# The oracle legs read the scene and batches from here (worker processes inherit them by fork).
+_ORACLE_INPUT = {}
+
+
+def _oracle_run(objects, budget_s):
+    """The FP64 oracle, one BLAS thread, on the given objects' steps in order (object k's step n
+    is its rays of batch n) until ``budget_s`` seconds have passed. Returns (samples, object
+    steps, seconds)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    scene, batches = _ORACLE_INPUT["scene"], _ORACLE_INPUT["batches"]
+    mine = set(objects)
     states = {k: oracle.ObjectState(oracle.xavier_init(o.seed, o.hidden, 4, 32), o.hidden, 4,
                                     o.norm_centre, o.norm_scale)
-              for k, o in enumerate(scene.objects)}
+              for k, o in enumerate(scene.objects) if k in mine}
+    samples = obj_steps = 0
     t0 = time.perf_counter()
-    n = samples = obj_steps = 0
-    done = False
-    while n < len(batches) and not done:
-        b = batches[n]
-        offs = b["ray_offsets"]
-        for j, k in enumerate(b["object_ids"]):
-            sl = slice(offs[j], offs[j + 1])
-            sub = {f: b[f][sl] for f in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
-            sub["object_ids"] = b["object_ids"][j:j + 1]
-            sub["ray_offsets"] = np.array([0, offs[j + 1] - offs[j]], dtype=np.int32)
-            sub["S"] = b["S"]
-            oracle.step(states, sub, scene.B)
-            samples += sub["t"].size
-            obj_steps += int(offs[j + 1] > offs[j])
-            if time.perf_counter() - t0 > budget_s:
-                done = True
-                break
-        n += 1
-    dt = time.perf_counter() - t0
-    return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
-                sample=f"{obj_steps} object-steps ({samples} samples) of the {workload} workload, "
-                       f"objects in batch order over consecutive steps from the initial models, "
-                       f"FP64 numpy",
-                seconds=dt, object_steps_per_s=obj_steps / dt)
+    with threadpool_limits(limits=1):
+        for b in batches:
+            offs = b["ray_offsets"]
+            for j, k in enumerate(b["object_ids"]):
+                if int(k) not in mine:
+                    continue
+                sl = slice(offs[j], offs[j + 1])
+                sub = {f: b[f][sl] for f in ("rays_o", "rays_d", "t", "depth", "rgb", "mask")}
+                sub["object_ids"] = b["object_ids"][j:j + 1]
+                sub["ray_offsets"] = np.array([0, offs[j + 1] - offs[j]], dtype=np.int32)
+                sub["S"] = b["S"]
+                oracle.step(states, sub, scene.B)
+                samples += sub["t"].size
+                obj_steps += int(offs[j + 1] > offs[j])
+                if time.perf_counter() - t0 > budget_s:
+                    return samples, obj_steps, time.perf_counter() - t0
+    return samples, obj_steps, time.perf_counter() - t0
+
+
+def _oracle_worker(args):
+    return _oracle_run(*args)
+
+
+def cpu_baseline(scene, batches, budget_s=15.0, workload=WORKLOAD):
+    """The FP64 oracle on the host in two legs of about budget_s / 2 seconds each: one thread
+    (objects one after another), and all cores (objects dealt to one worker process per core,
+    each with one BLAS thread, each running its objects' steps in order). Must run before the
+    GPU is initialised: the worker processes are forked."""
+    import multiprocessing as mp
+    _ORACLE_INPUT.update(scene=scene, batches=batches)
+    leg = budget_s / 2.0
+    all_ids = list(range(scene.n_objects))
+    s1, o1, t1 = _oracle_run(all_ids, leg)
+    P = min(host_cores(), scene.n_objects)
+    parts = [(all_ids[w::P], leg) for w in range(P)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(P) as pool:
+        res = pool.map(_oracle_worker, parts)
+    wall = time.perf_counter() - t0
+    sP, oP = sum(r[0] for r in res), sum(r[1] for r in res)
+    sample = (f"the {workload} workload's batches from the initial models, each object's steps in "
+              f"order; all cores: {oP} object-steps ({sP} samples) in {wall:.1f} s over {P} "
+              f"worker processes of one BLAS thread; one thread: {o1} object-steps ({s1} samples) "
+              f"in {t1:.1f} s; FP64 numpy")
+    return dict(value=sP / wall, unit="ray-samples/s", cores=P, kind="oracle", sample=sample,
+                object_steps_per_s=oP / wall, seconds=wall, cpu_model=cpu_model(),
+                one_thread={"value": s1 / t1, "unit": "ray-samples/s", "cores": 1,
+                            "object_steps_per_s": o1 / t1, "seconds": t1})
 
 
 def main():
@@ -300,6 +424,9 @@ def main():
                     help="k50_uneven is the headline workload; the others are reported in the docs")
     ap.add_argument("--sweep-objects", type=int, nargs="*", default=None,
                     help="only run the vectorised-vs-sequential sweep over these object counts")
+    ap.add_argument("--sweep-hidden", type=int, nargs="*", default=None,
+                    help="only run the vectorised-vs-sequential sweep over these hidden widths "
+                         "(BF16, 50 objects of 120 rays x 10 samples)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -315,6 +442,13 @@ def main():
         return
     if args.forms is None:
         args.forms = "bf16" if args.workload != WORKLOAD else "fp32,bf16"
+    if args.sweep_hidden is not None:
+        widths = args.sweep_hidden or [16, 32, 64, 128, 256, 512, 1024]
+        res = sweep_hidden(widths, max(1, min(args.steps, 20)), graph=bool(args.graph))
+        print(json.dumps({"sweep": "vectorised_vs_sequential_hidden", "precision": "bf16",
+                          "objects": 50, "rays_per_object": 120, "samples_per_ray": 10,
+                          "results": res}), flush=True)
+        return
     if args.sweep_objects is not None:
         counts = args.sweep_objects or [1, 10, 20, 30, 40, 50, 100, 150, 200]
         res = sweep_objects(counts, max(1, min(args.steps, 50)), args.forms.split(",")[-1],
@@ -329,15 +463,23 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import scenes
-    import paper_2302_01838_amd as vm
 
-    vm.load_library()
     scene = scenes.make_scene(args.workload)
     n_batches = args.distinct_batches or (args.warmup + args.steps)
     log(f"generating {n_batches} batches of {args.workload}")
     batches = gen_batches(scene, n_batches)
+    # the oracle first, before anything touches the GPU (its all-cores leg forks workers);
+    # --cpu-budget 0 skips it (profiled runs: a profiler initialises the GPU before the program)
+    cpu = None
+    if args.cpu_budget > 0:
+        log(f"cpu baseline: oracle for about {args.cpu_budget:.0f} s (one thread, then all cores)")
+        cpu = cpu_baseline(scene, batches, args.cpu_budget, args.workload)
+
+    import torch
+    import paper_2302_01838_amd as vm
+
+    vm.load_library()
     dev_batches = [vm.DeviceBatch(b) for b in batches]
     torch.cuda.synchronize()
 
@@ -364,15 +506,17 @@ def main():
     traffic = (measured_traffic(prec, shape.get("rays_per_tile", 0), shape.get("waves", 0),
                                 shape.get("split_step", False))
                if args.workload == WORKLOAD else None)
-    kname = ("tile kernel (encode+MLP+render+loss+backward; work list launched apart)"
-             if shape.get("split_step") else
-             "tile kernel (work list built in-kernel, encode+MLP+render+loss+backward)")
+    if args.workload != WORKLOAD:
+        kname = ("tile kernels of the step (cooperative kernel of the wide models, with the "
+                 "hidden-32 tile kernel where present), events around all of a step's tile launches")
+    elif shape.get("split_step"):
+        kname = "tile kernel (encode+MLP+render+loss+backward; work list launched apart)"
+    else:
+        kname = "tile kernel (work list built in-kernel, encode+MLP+render+loss+backward)"
     roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK[prec] / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK[prec], traffic=traffic,
                     kernel=kname,
                     kernel_avg_ms=head["kernel_ms"], flop_per_launch=flops)
-    log(f"cpu baseline: oracle for up to {args.cpu_budget:.0f} s")
-    cpu = cpu_baseline(scene, batches, args.cpu_budget, args.workload)
     out = {
         "metric": "object-steps/s and ray-samples/s at K=50, BF16 vs FP32, at matched final loss",
         "value": head["ray_samples_per_s"],
@@ -392,13 +536,14 @@ def main():
                    "launch": {k: v for k, v in head.get("launch", {}).items()}},
         "object_steps_per_s": head["object_steps_per_s"],
         "forms": {k: {kk: v[kk] for kk in ("ray_samples_per_s", "object_steps_per_s", "ms_per_step",
-                                           "event_ms_per_step", "final_loss", "first_loss",
+                                           "event_ms_per_step", "event_ms_per_step_median",
+                                           "final_loss", "first_loss",
                                            "loss_scale", "skipped_last", "device_error",
                                            "kernel_ms")} for k, v in forms.items()},
         "matched_final_loss": matched,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()},
+        "host": {"cpu": cpu_model(), "nproc": os.cpu_count(), "cores_used": host_cores()},
     }
     print(json.dumps(out), flush=True)
 

@@ -68,7 +68,11 @@ typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed
  * row-major as [out][in]; E = 2 * n_features. Supported: n_features = 16, n_hidden_layers = 4,
  * hidden in {32, 64} in both precisions and 128 in VMAP_BF16 (the background
  * model's width, Sec. 4, Implementation Details), 1 <= max_samples_per_ray <= 64. Objects of
- * different widths may share a stack and a batch (max_hidden bounds them).
+ * different widths may share a stack and a batch (max_hidden bounds them). In VMAP_BF16 the
+ * widths 16, 256, 512 and 1024 (the hidden-size range of Sec. 4.3's vectorised-vs-sequential
+ * study) are trained by a layered path (one launch per layer and direction, activations in the
+ * workspace) with the same rounding points; they need max_hidden in {16, 256, 512, 1024}, a stack
+ * holds objects of at most one of them, and vmap_query_occupancy does not take them.
  */
 typedef struct {
   int32_t max_objects;          /* capacity of the model stack, 1..65536 */

@@ -212,6 +212,11 @@ class ObjectSet:
             self.tuned = lookup(hidden, max_samples_per_ray, precision)
             if self.tuned:
                 rays_per_tile = int(self.tuned["rays_per_tile"])
+        if rays_per_tile_wide == 0 and autotune and (max_hidden or hidden) > 32:
+            from .tune import lookup
+            wide = lookup(max_hidden or hidden, max_samples_per_ray, precision)
+            if wide and wide.get("rays_per_tile_wide"):
+                rays_per_tile_wide = int(wide["rays_per_tile_wide"])
         self.cfg = default_config(
             max_objects=max_objects, hidden=hidden, max_hidden=max_hidden or hidden,
             max_samples_per_ray=max_samples_per_ray, max_rays=max_rays,

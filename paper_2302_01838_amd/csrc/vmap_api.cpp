@@ -34,6 +34,10 @@ struct WorkLayout {
   size_t tile_start, flags, t_next, mark, batch, tile_bad, tile_loss, partial, wimage, img32, total;
   size_t wimage_stride;
   int max_tiles;
+  // layered path (generic widths): row tiles, their losses, activations, deltas, z and dz
+  size_t gts, gen_loss, gact, gdelta, gz, gdz;
+  int max_gen_tiles;
+  int64_t gen_ld, gen_rows;
 };
 
 bool hidden_ok(int H, int precision) { return tiles_supported(H, precision == VMAP_BF16) != 0; }
@@ -45,9 +49,11 @@ const char* check_config(const vmap_config* c) {
   if (c->n_hidden_layers != kLayers) return "n_hidden_layers must be 4";
   if (c->precision != VMAP_FP32 && c->precision != VMAP_BF16) return "precision must be VMAP_FP32 or VMAP_BF16";
   if (!hidden_ok(c->hidden, c->precision))
-    return "hidden width not supported (32 or 64; 128 in BF16)";
+    return "hidden width not supported (32 or 64; 128, and 16, 256, 512, 1024 by the layered path, in BF16)";
   if (c->max_hidden < c->hidden || !hidden_ok(c->max_hidden, c->precision))
     return "max_hidden must be a supported width >= hidden";
+  if (generic_width(c->hidden) && !generic_width(c->max_hidden))
+    return "a hidden width of the layered path (16, 256, 512, 1024) needs max_hidden of the same set";
   if (c->max_samples_per_ray < 1 || c->max_samples_per_ray > kSlots) return "max_samples_per_ray must be in [1, 64]";
   if (c->max_rays < 0 || c->max_rays > (1 << 26)) return "max_rays must be in [0, 2^26]";
   if (c->rays_per_tile < 0 || c->rays_per_tile > (1 << 16)) return "rays_per_tile must be in [0, 65536]";
@@ -124,12 +130,27 @@ WorkLayout work_layout(const vmap_config* c) {
   w.tile_loss = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.tile_bad = off; off = align256(off + (size_t)w.max_tiles * 4);
   w.partial = off; off = align256(off + (size_t)w.max_tiles * ps * 4);
-  // weight images of wide objects (weights read from device memory by the tile kernel)
+  // weight images of hidden-128 objects (weights read from device memory by the tile kernel)
   const bool bf = c->precision == VMAP_BF16;
-  w.wimage_stride = weights_global(c->max_hidden) ? (size_t)image_bytes(c->max_hidden, bf) : 0;
+  w.wimage_stride = (bf && c->max_hidden >= 128) ? (size_t)image_bytes(128, true) : 0;
   w.wimage = off; off = align256(off + (size_t)c->max_objects * w.wimage_stride);
   // weight images of width-32 objects (staged by a plain copy)
   w.img32 = off; off = align256(off + (size_t)c->max_objects * img32_bytes(bf));
+  // layered path: when max_hidden is one of its widths, activations and deltas of every sample
+  // (rows = max_rays * max_samples_per_ray, ld = max(32, max_hidden) BF16 per row)
+  if (bf && generic_width(c->max_hidden)) {
+    const int rpw = std::max(1, kSlots / c->max_samples_per_ray);
+    w.max_gen_tiles = (c->max_rays + rpw - 1) / rpw + c->max_objects;
+    w.gen_ld = std::max(kEnc, c->max_hidden);
+    w.gen_rows = (int64_t)c->max_rays * c->max_samples_per_ray;
+    const size_t layer = (size_t)w.gen_rows * (size_t)w.gen_ld * 2;
+    w.gts = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
+    w.gen_loss = off; off = align256(off + (size_t)w.max_gen_tiles * 4);
+    w.gact = off; off = align256(off + (size_t)(kLayers + 1) * layer);
+    w.gdelta = off; off = align256(off + 2 * layer);
+    w.gz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
+    w.gdz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
+  }
   w.total = off;
   return w;
 }
@@ -162,6 +183,7 @@ struct vmap_ctx {
   int waves = 4;
   int grid_blocks = 0;
   int device = 0;
+  int gen_width = 0;  // the one layered-path width of the stack's objects (0: none yet)
   bool debug = false;  // VMAP_DEBUG=1 at creation: device validation of every batch
   std::vector<HostObj> objs;
   int n_registered = 0;
@@ -384,6 +406,28 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
     const int H = widths[i];
     hipStream_t si = (i == 0) ? s : c->side_stream;
     a.hidden = H;
+    if (generic_width(H)) {  // the layered path's chain of launches
+      GenArgs g{};
+      g.a = a;
+      g.H = H;
+      g.rpw = std::max(1, kSlots / b->samples_per_ray);
+      g.max_gen_tiles = c->wl.max_gen_tiles;
+      g.gts = reinterpret_cast<int32_t*>(c->work + c->wl.gts);
+      g.gen_loss = reinterpret_cast<float*>(c->work + c->wl.gen_loss);
+      g.act = reinterpret_cast<uint16_t*>(c->work + c->wl.gact);
+      const size_t layer = (size_t)c->wl.gen_rows * (size_t)c->wl.gen_ld;
+      g.delta[0] = reinterpret_cast<uint16_t*>(c->work + c->wl.gdelta);
+      g.delta[1] = g.delta[0] + layer;
+      g.z = reinterpret_cast<float*>(c->work + c->wl.gz);
+      g.dz = reinterpret_cast<float*>(c->work + c->wl.gdz);
+      g.ld = c->wl.gen_ld;
+      g.layer_elems = (int64_t)layer;
+      const int tiles_bound = (b->n_rays_total + g.rpw - 1) / g.rpw + b->n_objects;
+      if (tiles_bound > g.max_gen_tiles) return c->fail(VMAP_ECAPACITY, "batch needs more row tiles than the workspace holds");
+      hipError_t e = launch_generic(mode, g, tiles_bound, si);
+      if (e != hipSuccess) return c->hip_fail(e, "layered-path launch");
+      continue;
+    }
     hipError_t e = launch_stage_images(H, bf, a, -1, si);
     if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
     e = launch_tiles(H, bf, mode, a, c->waves, grid, si);
@@ -593,6 +637,10 @@ int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_pa
   const int H = d->hidden ? d->hidden : c->cfg.hidden;
   if (!hidden_ok(H, c->cfg.precision) || H > c->cfg.max_hidden)
     return c->fail(VMAP_ENOTSUP, "object hidden width not supported or above max_hidden");
+  if (generic_width(H) && !generic_width(c->cfg.max_hidden))
+    return c->fail(VMAP_ENOTSUP, "widths 16, 256, 512 and 1024 (layered path) need max_hidden of that set");
+  if (generic_width(H) && c->gen_width != 0 && c->gen_width != H)
+    return c->fail(VMAP_ENOTSUP, "a stack holds objects of at most one layered-path width");
   if (!(d->scale > 0.f) || !std::isfinite(d->scale)) return c->fail(VMAP_EINVAL, "desc.scale must be > 0");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(d->centre[i])) return c->fail(VMAP_EINVAL, "desc.centre must be finite");
@@ -626,6 +674,7 @@ int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_pa
   c->objs[k].hidden = H;
   c->objs[k].n_params = P;
   c->n_registered++;
+  if (generic_width(H)) c->gen_width = H;
   e = restage_image(c, k, s);
   if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
   *object_id_out = k;
@@ -892,6 +941,7 @@ int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, fl
   q.rgb = rgb_out;
   const bool bf = c->cfg.precision == VMAP_BF16;
   const int H = c->objs[k].hidden;
+  if (generic_width(H)) return c->fail(VMAP_ENOTSUP, "point queries of layered-path widths are not built");
   q.wimage = c->wimage();
   q.wimage_stride = (int64_t)c->wl.wimage_stride;
   q.max_objects = c->cfg.max_objects;

@@ -222,8 +222,19 @@ __host__ __device__ constexpr CoopLayout coop_layout(int H, bool bf16) {
 // optimiser kernels after each update.
 __host__ __device__ constexpr int img32_bytes(bool bf16) { return round_up(lds_layout(32, bf16, 1).B_off, 256); }
 
+// Widths without a fused tile kernel, trained (BF16) by the layered path: a chain of launches
+// over activations kept in device memory (encoding, one product launch per layer forward and per
+// layer and direction backward, rendering). The whole object is one work tile there: its
+// gradient is summed over all its rows by one product launch per layer.
+__host__ __device__ constexpr bool generic_width(int H) {
+  return H == 16 || H == 256 || H == 512 || H == 1024;
+}
+constexpr int kWholeObject = 1 << 26;  // rays per tile of a layered-path object (max_rays bound)
+
 // Rays per work tile of an object of width H.
-__host__ __device__ constexpr int tile_rays(int H, int rpt, int rpt_wide) { return H > 32 ? rpt_wide : rpt; }
+__host__ __device__ constexpr int tile_rays(int H, int rpt, int rpt_wide) {
+  return generic_width(H) ? kWholeObject : (H > 32 ? rpt_wide : rpt);
+}
 
 // Offset of layer l's weights in an object's parameter vector (l = kLayers: the output layer).
 __host__ __device__ constexpr int layer_param_off(int H, int l) {
@@ -355,6 +366,29 @@ struct StepArgs {
   int lds_table;
 };
 
+// The layered path (generic_width objects of one width H per launch chain). Row = sample:
+// row r * S + i is sample i of batch ray r. Row tiles are whole rays, floor(64 / S) of them (one
+// rendering sub-tile, at most 64 rows), listed per batch object in gts (exclusive scan).
+struct GenArgs {
+  StepArgs a;            // batch, model state and the fused path's work buffers
+  int H;                 // width of this chain's objects
+  int rpw;               // rays per row tile
+  int max_gen_tiles;     // row tiles the workspace holds
+  int32_t* gts;          // [n_objects + 1] first row tile of each batch object
+  float* gen_loss;       // [max_gen_tiles] loss per row tile
+  uint16_t* act;         // BF16 [kLayers + 1][rows][ld]: encoding (32 wide), then h_1 .. h_4
+  uint16_t* delta[2];    // BF16 [rows][ld] each: back-propagated deltas, alternately
+  float* z;              // [rows][4] output pre-activations
+  float* dz;             // [rows][4] their adjoints (times the seed's scale)
+  int64_t ld;            // elements per row of act and delta
+  int64_t layer_elems;   // elements per layer of act
+};
+// Kinds of the layered path's product kernel.
+enum GenKind { GEN_FWD = 0, GEN_DX = 1, GEN_DW = 2 };
+// LDS of the product kernel: two 64 x 32 BF16 operand tiles, rows padded to 40 elements.
+constexpr int kGenPitch = 40;
+constexpr int kGenLdsBytes = 2 * 64 * kGenPitch * 2;
+
 struct QueryArgs {
   const float* pts;
   int64_t n;
@@ -415,6 +449,11 @@ hipError_t launch_tiles(int H, bool bf16, int mode, const StepArgs& a, int nwave
                         hipStream_t s);
 // Debug validation of a batch (distinct ids, ascending sample depths); mark: [max_objects] int32.
 hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s);
+// The layered path's chain for the objects of width g.H of a batch: row tiles, encoding, forward
+// products, rendering (and loss), then in training the backward products, writing each object's
+// unscaled gradient into its one tile partial and its loss into that tile's loss. tiles_bound:
+// host bound on the row tiles (ceil(n_rays / rpw) + n_objects).
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream_t s);
 enum OptKind { OPT_LOSS = 0, OPT_REDUCE = 1, OPT_ADAM = 2, OPT_REDUCE_ADAM = 3 };
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s);
 hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,

@@ -2607,12 +2607,13 @@ static hipError_t launch_tiles_t(const StepArgs& a_in, int nwaves, int grid, hip
 }
 
 int tiles_supported(int H, bool bf16) {
-  return H == 32 || H == 64 || (H == 128 && bf16);
+  return H == 32 || H == 64 || (H == 128 && bf16) || (generic_width(H) && bf16);
 }
 
 int tile_waves(int H, int requested) { return H == 32 ? requested : 4; }
 
 int tile_lds_bytes(int H, bool bf16, int nwaves) {
+  if (generic_width(H)) return kGenLdsBytes;
   return H == 32 ? lds_layout(H, bf16, nwaves).total : coop_layout(H, bf16).total;
 }
 
@@ -2731,6 +2732,414 @@ hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,
 
 hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
   hipLaunchKernelGGL(k_init_scaler, dim3(1), dim3(64), 0, s, sc, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Layered path (widths without a fused tile kernel: hidden 16, 256, 512, 1024; BF16). The step
+// of Sec. 3.2-3.3 as a chain of launches over activations kept in device memory: row tiles,
+// encoding, one product launch per layer forward, rendering with its adjoint (the fused kernels'
+// own render_subtile), then per layer one launch for the weight gradient and one for the input
+// gradient. The arithmetic takes the BF16 tile kernels' rounding points: every operand of every
+// product is rounded to BF16 (encoding, activations, weights, deltas, the output layer's seed),
+// products accumulate in FP32 on v_mfma_f32_32x32x16_bf16; biases, sigmoids, rendering, losses
+// and the output layer's bias gradient stay FP32. An object's weight gradient is summed over all
+// its rows, in row order, by one workgroup per 64 x 64 block of each weight matrix: no partials
+// to reduce, and the result does not depend on the grid or on the other objects.
+//
+// Product kernel: a workgroup (four waves) computes a 64 x 64 block of D = A B, each wave a 32 x 32
+// quarter, over K in chunks of 32 staged in LDS as BF16: As[m][k] and Bs[n][k] (B transposed), so
+// that the A and B operands of an MFMA are each one 16-byte LDS read per lane (lane l: row or column
+// l mod 32, the eight k of half l / 32 of the 16-wide step). Accumulator element 4 jj + i of lane l
+// holds D[8 jj + 4 (l / 32) + i][l mod 32].
+//   forward  (GEN_FWD): rows = samples, n = outputs, k = inputs;   A = h_l,   B = W_l^T
+//   input gradient (GEN_DX): rows = samples, n = inputs, k = outputs;  A = delta, B = W_l
+//   weight gradient (GEN_DW): rows = outputs, n = inputs, k = samples; A = delta^T, B = h_l^T
+
+// Batch object of row tile t: the largest j with gts[j] <= t (objects without tiles have an empty
+// range and are passed over), by bisection.
+__device__ __forceinline__ int gen_object(const int32_t* __restrict__ gts, int n_objects, int t) {
+  int lo = 0, hi = n_objects;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (gts[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+struct GenTile {
+  int j, k, lo, hi;  // batch object, object id, rays [lo, hi)
+};
+
+// Row tile t of the chain, if it exists (t below the clamped tile count).
+__device__ __forceinline__ bool gen_tile(const GenArgs& g, const StepArgs& a, int t, GenTile& o) {
+  const int total = clamp_tiles(g.gts[a.n_objects], g.max_gen_tiles);
+  if (t >= total) return false;
+  const int j = gen_object(g.gts, a.n_objects, t);
+  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], t - g.gts[j], g.rpw,
+                                     a.n_rays);
+  o = GenTile{j, a.object_ids[j], rr.lo, rr.hi};
+  return true;
+}
+
+// Row tiles per batch object: ceil(rays / rpw) for the objects of width H, none for the others or
+// for a batch that failed the offsets check (ScalerState::batch_ok, from the work-list launch).
+__global__ void __launch_bounds__(1024) k_gen_tiles(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  __shared__ int part[1024];
+  const bool ok = a.scaler->batch_ok != 0;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (a.n_objects + nt - 1) / nt;
+  const int j0 = min(tid * per, a.n_objects), j1 = min(j0 + per, a.n_objects);
+  auto count = [&](int j) {
+    const int k = a.object_ids[j];
+    if (!ok || k < 0 || k >= a.max_objects) return 0;
+    if (!a.desc[k].registered || a.desc[k].hidden != g.H) return 0;
+    return tiles_of(a.ray_offsets[j + 1] - a.ray_offsets[j], g.rpw);
+  };
+  int local = 0;
+  for (int j = j0; j < j1; ++j) local += count(j);
+  part[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - local;
+  for (int j = j0; j < j1; ++j) {
+    g.gts[j] = run;
+    run += count(j);
+  }
+  if (tid == nt - 1) g.gts[a.n_objects] = part[nt - 1];
+}
+
+// Encoding of every sample of a row tile (one wave per tile): normalised point in FP64 rounded
+// once, Gaussian Fourier features (and the integrated encoding's attenuation) as in forward_pass,
+// rounded to BF16 in pairs, into layer 0 of the activations.
+__global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  const int lane = threadIdx.x & 63, t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  GenTile tl;
+  if (!gen_tile(g, a, t, tl)) return;
+  const int S = a.S, nslots = (tl.hi - tl.lo) * S;
+  if (lane >= nslots) return;
+  const ObjDesc& d = a.desc[tl.k];
+  const int64_t row = (int64_t)tl.lo * S + lane;
+  const int ray = tl.lo + lane / S;
+  const double tt = (double)a.t[row];
+  const float* o3 = a.rays_o + 3 * (size_t)ray;
+  const float* d3 = a.rays_d + 3 * (size_t)ray;
+  const double inv_s = d.inv_scale;
+  float xt[4];
+  xt[0] = (float)(((double)o3[0] + tt * (double)d3[0] - d.centre[0]) * inv_s);
+  xt[1] = (float)(((double)o3[1] + tt * (double)d3[1] - d.centre[1]) * inv_s);
+  xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - d.centre[2]) * inv_s);
+  xt[3] = a.var ? (float)((double)a.var[row] * inv_s * inv_s) : 0.f;
+  const float* Bm = a.B;
+  unsigned int* out = reinterpret_cast<unsigned int*>(g.act + row * g.ld);
+#pragma unroll
+  for (int f = 0; f < kFeatures; f += 2) {
+    float sv[2], cv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int ff = f + u;
+      const float phi = xt[0] * Bm[ff] + xt[1] * Bm[kFeatures + ff] + xt[2] * Bm[2 * kFeatures + ff];
+      vmap_sincosf(phi, &sv[u], &cv[u]);
+      if (a.var) {
+        const float nb = Bm[ff] * Bm[ff] + Bm[kFeatures + ff] * Bm[kFeatures + ff] +
+                         Bm[2 * kFeatures + ff] * Bm[2 * kFeatures + ff];
+        const float att = expf(-0.5f * xt[3] * nb);
+        sv[u] *= att;
+        cv[u] *= att;
+      }
+    }
+    out[f / 2] = pack2(sv[0], sv[1]);
+    out[(kFeatures + f) / 2] = pack2(cv[0], cv[1]);
+  }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * kGenPitch];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kGenPitch];
+  const int H = g.H;
+  const bool head = (l == kLayers);
+  const int K = (l == 0) ? kEnc : H;  // inputs of layer l
+  const int O = head ? kOut : H;      // outputs of layer l
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
+  const int64_t ld = g.ld;
+  const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
+  const uint16_t* dout = head ? nullptr : g.delta[(3 - l) & 1];  // delta at layer l's outputs
+  int k, m0 = 0, n0;
+  int64_t r0;      // first row (sample) of the rows this workgroup reads
+  int nrows;       // rows: of the row tile (GEN_FWD, GEN_DX) or of the whole object (GEN_DW)
+  int ts = 0;      // GEN_DW: the object's work tile (its partial)
+  if constexpr (KIND == GEN_DW) {
+    const int j = blockIdx.x;
+    if (j >= a.n_objects || !a.scaler->batch_ok) return;
+    k = a.object_ids[j];
+    if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
+    ts = a.tile_start[j];
+    if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;  // no rays: no tile
+    const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
+    r0 = (int64_t)rr.lo * a.S;
+    nrows = (rr.hi - rr.lo) * a.S;
+    const int nbi = (K + 63) / 64;
+    m0 = (blockIdx.y / nbi) * 64;
+    n0 = (blockIdx.y % nbi) * 64;
+  } else {
+    GenTile tl;
+    if (!gen_tile(g, a, blockIdx.x, tl)) return;
+    k = tl.k;
+    r0 = (int64_t)tl.lo * a.S;
+    nrows = (tl.hi - tl.lo) * a.S;
+    n0 = blockIdx.y * 64;
+  }
+  const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
+  const int ktot = (KIND == GEN_FWD) ? K : (KIND == GEN_DX ? O : nrows);
+
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  float db = 0.f;  // GEN_DW, first column block: bias gradient of output m0 + tid (tid < 64)
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  for (int k0 = 0; k0 < ktot; k0 += 32) {
+    __syncthreads();  // the previous chunk's operands have been read
+    if constexpr (KIND == GEN_FWD || KIND == GEN_DX) {
+      // A: 64 rows x 32 k of the row-major input (h_l, or the deltas at the outputs)
+      const int m = tid >> 2, kq = (tid & 3) * 8;
+      u4 v = {0u, 0u, 0u, 0u};
+      if (m < nrows && k0 + kq < ktot) {
+        const int64_t row = r0 + m;
+        if (KIND == GEN_DX && head) {  // the output layer's seed, FP32 [rows][4], rounded
+          if (kq == 0) {
+            const float* d4 = g.dz + row * kOut;
+            v[0] = pack2(d4[0], d4[1]);
+            v[1] = pack2(d4[2], d4[3]);
+          }
+        } else {
+          const uint16_t* src = (KIND == GEN_FWD) ? act_l : dout;
+          v = *reinterpret_cast<const u4*>(src + row * ld + k0 + kq);
+        }
+      }
+      *reinterpret_cast<u4*>(As + m * kGenPitch + kq) = v;
+      if constexpr (KIND == GEN_FWD) {
+        // B: Bs[n][k] = W[n0 + n][k0 + k]
+        const int n = tid >> 2;
+        u4 w = {0u, 0u, 0u, 0u};
+        if (n0 + n < O && k0 + kq < K) {
+          const float* src = W + (size_t)(n0 + n) * K + k0 + kq;
+          const float4 x0 = *reinterpret_cast<const float4*>(src);
+          const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+          w = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+        }
+        *reinterpret_cast<u4*>(Bs + n * kGenPitch + kq) = w;
+      } else {
+        // B: Bs[n][k] = W[k0 + k][n0 + n] (W transposed)
+        const int n = tid & 63, kb = (tid >> 6) * 8;
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int o = k0 + kb + e;
+          x[e] = (o < O && n0 + n < K) ? W[(size_t)o * K + n0 + n] : 0.f;
+        }
+        *reinterpret_cast<u4*>(Bs + n * kGenPitch + kb) =
+            u4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])};
+      }
+    } else {
+      // GEN_DW. A: As[m][k] = delta[r0 + k0 + k][m0 + m]; B: Bs[n][k] = h_l[r0 + k0 + k][n0 + n]
+      const int c = tid & 63, kb = (tid >> 6) * 8;
+      u4 va, vb;
+      unsigned short ea[8], eb[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int r = k0 + kb + e;
+        ea[e] = 0;
+        eb[e] = 0;
+        if (r < nrows) {
+          const int64_t row = r0 + r;
+          if (m0 + c < O) {
+            if (head) {
+              const float x = g.dz[row * kOut + m0 + c];
+              ea[e] = (unsigned short)(pack2(x, 0.f) & 0xffffu);
+            } else {
+              ea[e] = dout[row * ld + m0 + c];
+            }
+          }
+          if (n0 + c < K) eb[e] = act_l[row * ld + n0 + c];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        va[q] = (unsigned int)ea[2 * q] | ((unsigned int)ea[2 * q + 1] << 16);
+        vb[q] = (unsigned int)eb[2 * q] | ((unsigned int)eb[2 * q + 1] << 16);
+      }
+      *reinterpret_cast<u4*>(As + c * kGenPitch + kb) = va;
+      *reinterpret_cast<u4*>(Bs + c * kGenPitch + kb) = vb;
+    }
+    __syncthreads();
+    if constexpr (KIND == GEN_DW) {
+      // bias gradient: the deltas as the products see them (BF16), the output layer's seed FP32
+      if (n0 == 0 && tid < 64 && m0 + tid < O) {
+        const int kend = min(32, nrows - k0);
+        if (head) {
+          for (int r = 0; r < kend; ++r) db += g.dz[(r0 + k0 + r) * kOut + m0 + tid];
+        } else {
+          for (int r = 0; r < kend; ++r)
+            db += __builtin_bit_cast(float, (unsigned int)As[tid * kGenPitch + r] << 16);
+        }
+      }
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + m32) * kGenPitch + kc * 16 + kh * 8);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * kGenPitch + kc * 16 + kh * 8);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+  }
+
+  // epilogue: element 4 jj + i of this lane is D[wm 32 + 8 jj + 4 kh + i][wn 32 + m32]
+  const int col = n0 + wn * 32 + m32;
+  if constexpr (KIND == GEN_FWD) {
+    if (col >= O) return;
+    const float b = W[(size_t)O * K + col];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+      if (r >= nrows) continue;
+      const int64_t row = r0 + r;
+      const float y = acc[i] + b;
+      if (head) {
+        g.z[row * kOut + col] = y;
+      } else {
+        const float h = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
+        (g.act + (int64_t)(l + 1) * g.layer_elems)[row * ld + col] = (uint16_t)(pack2(h, 0.f) & 0xffffu);
+      }
+    }
+  } else if constexpr (KIND == GEN_DX) {
+    if (col >= K) return;
+    uint16_t* din = g.delta[(4 - l) & 1];  // delta at layer l - 1's outputs
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+      if (r >= nrows) continue;
+      const int64_t row = r0 + r;
+      // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive
+      const bool on = act_l[row * ld + col] != 0;
+      din[row * ld + col] = on ? (uint16_t)(pack2(acc[i], 0.f) & 0xffffu) : (uint16_t)0;
+    }
+  } else {
+    const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
+    float* dst = a.partial + (size_t)ts * a.p_stride + layer_param_off(H, l);
+    int bad = 0;
+    if (col < K) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int o = m0 + wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+        if (o >= O) continue;
+        const float v = acc[i] * inv;
+        bad |= partial_bad(v);
+        dst[(size_t)o * K + col] = v;
+      }
+    }
+    if (n0 == 0 && tid < 64 && m0 + tid < O) {
+      const float v = db * inv;
+      bad |= partial_bad(v);
+      dst[(size_t)O * K + m0 + tid] = v;
+    }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[k], 1);
+  }
+}
+
+// Rendering, loss and (training) the adjoint of one row tile per wave, by the fused kernels'
+// render_subtile; the tile's loss (a fixed-order wave sum) goes to gen_loss, dL/dz to dz.
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_gen_render(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  const int lane = threadIdx.x & 63, t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  GenTile tl;
+  if (!gen_tile(g, a, t, tl)) return;  // uniform over the wave
+  const int S = a.S, nslots = (tl.hi - tl.lo) * S;
+  const int64_t row0 = (int64_t)tl.lo * S;
+  float zs[kOut] = {0.f, 0.f, 0.f, 0.f};
+  if (lane < nslots) {
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) zs[c] = g.z[(row0 + lane) * kOut + c];
+  }
+  float wseed = 1.0f;
+  if constexpr (TRAIN) {
+    if (a.dloss) wseed = a.dloss[tl.j];
+    if (a.use_scale) wseed *= a.scaler->scale;
+  }
+  const RenderIn rin = render_inputs<TRAIN>(a, tl.lo, nslots);
+  float dzs[kOut] = {0.f, 0.f, 0.f, 0.f};
+  float loss = 0.f;
+  render_subtile<TRAIN>(a, tl.lo, nslots, wseed, rin, zs, dzs, loss);
+  if constexpr (TRAIN) {
+    if (lane < nslots) {
+#pragma unroll
+      for (int c = 0; c < kOut; ++c) g.dz[(row0 + lane) * kOut + c] = dzs[c];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
+  if (lane == 0) g.gen_loss[t] = loss;
+}
+
+// Loss of each object of the chain: its row tiles' losses in order, into its one work tile.
+__global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_objects) return;
+  const int total = clamp_tiles(g.gts[a.n_objects], g.max_gen_tiles);
+  const TileRange tr = clamp_tile_range(g.gts[j], g.gts[j + 1], total);
+  const int ts = a.tile_start[j];
+  if (tr.t1 <= tr.t0 || ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;
+  float s = 0.f;
+  for (int t = tr.t0; t < tr.t1; ++t) s += g.gen_loss[t];
+  a.tile_loss[ts] = s;
+}
+
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream_t s) {
+  if (tiles_bound <= 0 || g.a.n_objects <= 0) return hipSuccess;
+  if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots) return hipErrorInvalidValue;
+  const bool train = (mode == MODE_TRAIN);
+  const int H = g.H;
+  const int wave_blocks = (tiles_bound + 3) / 4;
+  auto blocks64 = [](int n) { return (n + 63) / 64; };
+  hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
+  hipLaunchKernelGGL(k_gen_encode, dim3(wave_blocks), dim3(256), 0, s, g);
+  for (int l = 0; l <= kLayers; ++l) {
+    const int O = (l == kLayers) ? kOut : H;
+    hipLaunchKernelGGL(k_gen_gemm<GEN_FWD>, dim3(tiles_bound, blocks64(O)), dim3(256), 0, s, g, l);
+  }
+  if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
+  if (train) {
+    for (int l = kLayers; l >= 0; --l) {
+      const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
+      hipLaunchKernelGGL(k_gen_gemm<GEN_DW>, dim3(g.a.n_objects, blocks64(O) * blocks64(K)),
+                         dim3(256), 0, s, g, l);
+      if (l > 0)
+        hipLaunchKernelGGL(k_gen_gemm<GEN_DX>, dim3(tiles_bound, blocks64(K)), dim3(256), 0, s, g, l);
+    }
+  }
   return hipGetLastError();
 }
 

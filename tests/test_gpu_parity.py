@@ -118,7 +118,8 @@ def test_backward_parity(precision, scene_name):
     sc = SCENES[scene_name]()
     objs, states = make_pair(sc, precision)
     rnd = oracle.bf16_round if precision == "bf16" else None
-    batch, dropped = away_from_kinks(states, scenes.make_batch(sc, 0), sc.B, rnd=rnd)
+    batch, dropped = away_from_kinks(states, scenes.make_batch(sc, 0), sc.B, rnd=rnd,
+                                     tau_res=1e-5 if precision == "fp32" else 2.0 ** -8)
     db = vm.DeviceBatch(batch)
     n = len(batch["object_ids"])
     up = np.linspace(0.5, 2.0, n).astype(np.float32)

@@ -67,12 +67,14 @@ def test_scene_render_parity(precision):
     sc = scaled(scenes.make_scene("room50_background"), 8)
     ids = list(range(12))
     objs, states = make_pair(sc, precision, ids=ids, max_rays=20000)
-    # a few training steps so that the models are not all alike
-    for step in range(3):
-        objs.step(vm.DeviceBatch(remap_batch(scenes.make_batch(sc, step, object_ids=ids), ids)))
-    torch.cuda.synchronize()
+    # models that differ from their initialisation and from each other: seeded perturbations of
+    # the initial parameters, set in both the library and the oracle (FP32 values)
+    rng = np.random.default_rng(17)
     for j in range(len(ids)):
-        states[j].theta = objs.get_state(j, vm.STATE_PARAMS).astype(np.float64)
+        th = states[j].theta
+        th = (th + 0.3 * np.abs(th).mean() * rng.standard_normal(th.shape)).astype(np.float32)
+        objs.set_state(j, vm.STATE_PARAMS, th)
+        states[j].theta = th.astype(np.float64)
     o, d = _view_rays(sc, ids, 3000, seed=4)
     S = 16
     got = objs.render_scene(o, d, object_ids=list(range(len(ids))), S=S)

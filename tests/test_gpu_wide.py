@@ -213,11 +213,11 @@ def test_objects_join_in_waves():
             assert np.array_equal(solo.get_state(0, w), objs.get_state(lid[k], w)), (k, w)
 
 
-def test_stress_full_size_sampled_objects():
+def test_stress_full_size_join_wave():
     """The stress workload at full size (256 objects of hidden 64, 256-4096 rays of 32 samples,
-    BF16) in one step; three objects (the smallest, the largest and one more) are checked against
-    the oracle, the others for finiteness. Objects are independent, so a sample of them checks
-    the launch that ran all of them."""
+    BF16) in one step; every object of the first join wave (32 objects) is checked against the
+    oracle on loss and parameters, the others for finiteness. Objects are independent, so a whole
+    wave of them checks the launch that ran all of them."""
     sc = scenes.make_scene("stress_k256")
     n = sc.n_objects
     objs = vm.ObjectSet(max_objects=n, B=sc.B, hidden=64, precision="bf16",
@@ -231,8 +231,10 @@ def test_stress_full_size_sampled_objects():
     torch.cuda.synchronize()
     assert np.all(np.isfinite(loss))
     counts = np.diff(batch["ray_offsets"])
-    sample = sorted({int(np.argmin(counts)), int(np.argmax(counts)), 17})
-    for k in sample:
+    wave = [k for k in range(n) if sc.objects[k].join_step == 0]
+    assert len(wave) == 32
+    worst_l = worst_t = 0.0
+    for k in wave:
         ob = sc.objects[k]
         th0 = oracle.xavier_init(ob.seed, 64, 4, 32)
         c32 = np.asarray(ob.norm_centre, np.float32).astype(np.float64)
@@ -242,9 +244,26 @@ def test_stress_full_size_sampled_objects():
         th = objs.get_state(k, vm.STATE_PARAMS)
         e_l = relerr(loss[k], l_ref[0])
         e_t = relerr(th, states[0].theta)
-        report(f"stress full size object {k} ({counts[k]} rays)", loss=e_l, theta=e_t)
-        assert e_l <= 2e-2 and e_t <= 2e-2
+        worst_l, worst_t = max(worst_l, e_l), max(worst_t, e_t)
+        assert e_l <= 2e-2 and e_t <= 2e-2, (k, e_l, e_t)
         assert objs.get_state(k, vm.STATE_STEP) == 1
+    report(f"stress full size, join wave 0 ({len(wave)} objects, {int(counts[wave].sum())} rays)",
+           loss=worst_l, theta=worst_t)
+
+
+def test_room_full_size_step():
+    """The room workload at full size: 50 objects of hidden 32 (lognormal ray counts) and the
+    hidden-128 background, BF16, one step, every object against the oracle (rays away from a
+    kink; the one-step BF16 tolerances)."""
+    sc = scenes.make_scene("room50_background")
+    objs, states = make_pair(sc, "bf16")
+    batch = scenes.make_batch(sc, 0)
+    print(f"[parity] room full size: {len(batch['object_ids'])} objects, "
+          f"{int(batch['ray_offsets'][-1])} rays", flush=True)
+    errs, errs16, _, _ = step_errors(objs, states, batch, "bf16", sc.B)
+    report("room full size step", **errs)
+    report("room full size step vs bf16 oracle", **errs16)
+    check_step(errs, errs16, "bf16")
 
 
 @pytest.mark.parametrize("name", ["h64-fp32", "h128-bf16"])

@@ -60,6 +60,23 @@ def test_wide_models_bf16_only(lib):
     assert lib.vmap_object_params(ctypes.byref(vm.default_config(hidden=32)), 128) == 0
 
 
+@pytest.mark.parametrize("H", [16, 256, 512, 1024])
+def test_layered_widths_bf16_only(lib, H):
+    """Widths of the layered path: BF16 only, a layered max_hidden, parameter counts of the
+    pinned layout (32H + H + 3(H^2 + H) + 4H + 4), and workspace for the activations of
+    max_rays x max_samples_per_ray samples (5 layers + 2 delta buffers of max(32, H) BF16)."""
+    cfg = vm.default_config(max_objects=4, hidden=H, precision=vm.VMAP_BF16, max_rays=1000,
+                            max_samples_per_ray=10)
+    assert lib.vmap_object_params(ctypes.byref(cfg), H) == 33 * H + 3 * (H * H + H) + 4 * H + 4
+    wb = lib.vmap_workspace_bytes(ctypes.byref(cfg))
+    assert wb >= 7 * 1000 * 10 * max(32, H) * 2
+    assert lib.vmap_state_bytes(ctypes.byref(vm.default_config(hidden=H))) == 0  # FP32
+    mixed = vm.default_config(hidden=32, max_hidden=H, precision=vm.VMAP_BF16)
+    assert (lib.vmap_state_bytes(ctypes.byref(mixed)) > 0) == (H > 32)
+    bad = vm.default_config(hidden=16, max_hidden=64, precision=vm.VMAP_BF16)
+    assert lib.vmap_state_bytes(ctypes.byref(bad)) == 0
+
+
 @pytest.mark.parametrize("field,value", [("max_objects", 0), ("n_features", 8),
                                          ("n_hidden_layers", 3), ("hidden", 48),
                                          ("max_samples_per_ray", 65), ("precision", 7),
