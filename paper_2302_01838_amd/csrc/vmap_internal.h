@@ -385,9 +385,13 @@ struct GenArgs {
 };
 // Kinds of the layered path's product kernel.
 enum GenKind { GEN_FWD = 0, GEN_DX = 1, GEN_DW = 2 };
-// LDS of the product kernel: two 64 x 32 BF16 operand tiles, rows padded to 40 elements.
+// LDS of the product kernels: k_gen_gemm stages two 64 x kGenKChunk BF16 operand tiles (rows
+// padded by 8 elements); k_gen_dw_small four waves' pairs of 32 x 32 tiles (rows of 40).
+constexpr int kGenKChunk = 64;
 constexpr int kGenPitch = 40;
-constexpr int kGenLdsBytes = 2 * 64 * kGenPitch * 2;
+constexpr int kGenLdsBytes = 2 * 64 * (kGenKChunk + 8) * 2 > 4 * 2 * 32 * kGenPitch * 2
+                                 ? 2 * 64 * (kGenKChunk + 8) * 2
+                                 : 4 * 2 * 32 * kGenPitch * 2;
 
 struct QueryArgs {
   const float* pts;

@@ -2870,8 +2870,9 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  __shared__ __attribute__((aligned(16))) uint16_t As[64 * kGenPitch];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kGenPitch];
+  constexpr int KC = kGenKChunk, PB = KC + 8;  // K per staged chunk, LDS row pitch (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * PB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * PB];
   const int H = g.H;
   const bool head = (l == kLayers);
   const int K = (l == 0) ? kEnc : H;  // inputs of layer l
@@ -2887,7 +2888,8 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   int ts = 0;      // GEN_DW: the object's work tile (its partial)
   if constexpr (KIND == GEN_DW) {
     const int j = blockIdx.x;
-    if (j >= a.n_objects || !a.scaler->batch_ok) return;
+    // layers of at most 32 outputs (the output layer among them) take k_gen_dw_small
+    if (head || O <= 32 || j >= a.n_objects || !a.scaler->batch_ok) return;
     k = a.object_ids[j];
     if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
     ts = a.tile_start[j];
@@ -2914,97 +2916,97 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   float db = 0.f;  // GEN_DW, first column block: bias gradient of output m0 + tid (tid < 64)
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  for (int k0 = 0; k0 < ktot; k0 += 32) {
+  for (int k0 = 0; k0 < ktot; k0 += KC) {
     __syncthreads();  // the previous chunk's operands have been read
     if constexpr (KIND == GEN_FWD || KIND == GEN_DX) {
-      // A: 64 rows x 32 k of the row-major input (h_l, or the deltas at the outputs)
-      const int m = tid >> 2, kq = (tid & 3) * 8;
-      u4 v = {0u, 0u, 0u, 0u};
+      // A: 64 rows x KC k of the row-major input (h_l, or the deltas at the outputs); ktot is a
+      // multiple of 16 (or the output layer's 4 seeds), so a 16-wide group is all in or all out
+      const int m = tid >> 2, kq = (tid & 3) * 16;
+      u4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
       if (m < nrows && k0 + kq < ktot) {
         const int64_t row = r0 + m;
         if (KIND == GEN_DX && head) {  // the output layer's seed, FP32 [rows][4], rounded
-          if (kq == 0) {
-            const float* d4 = g.dz + row * kOut;
-            v[0] = pack2(d4[0], d4[1]);
-            v[1] = pack2(d4[2], d4[3]);
-          }
+          const float* d4 = g.dz + row * kOut;
+          v0[0] = pack2(d4[0], d4[1]);
+          v0[1] = pack2(d4[2], d4[3]);
         } else {
-          const uint16_t* src = (KIND == GEN_FWD) ? act_l : dout;
-          v = *reinterpret_cast<const u4*>(src + row * ld + k0 + kq);
+          const uint16_t* src = ((KIND == GEN_FWD) ? act_l : dout) + row * ld + k0 + kq;
+          v0 = *reinterpret_cast<const u4*>(src);
+          v1 = *reinterpret_cast<const u4*>(src + 8);
         }
       }
-      *reinterpret_cast<u4*>(As + m * kGenPitch + kq) = v;
+      *reinterpret_cast<u4*>(As + m * PB + kq) = v0;
+      *reinterpret_cast<u4*>(As + m * PB + kq + 8) = v1;
       if constexpr (KIND == GEN_FWD) {
         // B: Bs[n][k] = W[n0 + n][k0 + k]
         const int n = tid >> 2;
-        u4 w = {0u, 0u, 0u, 0u};
+        u4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
         if (n0 + n < O && k0 + kq < K) {
           const float* src = W + (size_t)(n0 + n) * K + k0 + kq;
           const float4 x0 = *reinterpret_cast<const float4*>(src);
           const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-          w = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+          const float4 x2 = *reinterpret_cast<const float4*>(src + 8);
+          const float4 x3 = *reinterpret_cast<const float4*>(src + 12);
+          w0 = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+          w1 = u4{pack2(x2.x, x2.y), pack2(x2.z, x2.w), pack2(x3.x, x3.y), pack2(x3.z, x3.w)};
         }
-        *reinterpret_cast<u4*>(Bs + n * kGenPitch + kq) = w;
+        *reinterpret_cast<u4*>(Bs + n * PB + kq) = w0;
+        *reinterpret_cast<u4*>(Bs + n * PB + kq + 8) = w1;
       } else {
         // B: Bs[n][k] = W[k0 + k][n0 + n] (W transposed)
-        const int n = tid & 63, kb = (tid >> 6) * 8;
-        float x[8];
+        const int n = tid & 63, kb = (tid >> 6) * 16;
+        float x[16];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 16; ++e) {
           const int o = k0 + kb + e;
           x[e] = (o < O && n0 + n < K) ? W[(size_t)o * K + n0 + n] : 0.f;
         }
-        *reinterpret_cast<u4*>(Bs + n * kGenPitch + kb) =
-            u4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          *reinterpret_cast<u4*>(Bs + n * PB + kb + 8 * h) =
+              u4{pack2(x[8 * h], x[8 * h + 1]), pack2(x[8 * h + 2], x[8 * h + 3]),
+                 pack2(x[8 * h + 4], x[8 * h + 5]), pack2(x[8 * h + 6], x[8 * h + 7])};
       }
     } else {
       // GEN_DW. A: As[m][k] = delta[r0 + k0 + k][m0 + m]; B: Bs[n][k] = h_l[r0 + k0 + k][n0 + n]
-      const int c = tid & 63, kb = (tid >> 6) * 8;
-      u4 va, vb;
-      unsigned short ea[8], eb[8];
+      const int c = tid & 63, kb = (tid >> 6) * 16;
+      unsigned short ea[16], eb[16];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < 16; ++e) {
         const int r = k0 + kb + e;
         ea[e] = 0;
         eb[e] = 0;
         if (r < nrows) {
           const int64_t row = r0 + r;
-          if (m0 + c < O) {
-            if (head) {
-              const float x = g.dz[row * kOut + m0 + c];
-              ea[e] = (unsigned short)(pack2(x, 0.f) & 0xffffu);
-            } else {
-              ea[e] = dout[row * ld + m0 + c];
-            }
-          }
+          if (m0 + c < O) ea[e] = dout[row * ld + m0 + c];
           if (n0 + c < K) eb[e] = act_l[row * ld + n0 + c];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        va[q] = (unsigned int)ea[2 * q] | ((unsigned int)ea[2 * q + 1] << 16);
-        vb[q] = (unsigned int)eb[2 * q] | ((unsigned int)eb[2 * q + 1] << 16);
+      for (int h = 0; h < 2; ++h) {
+        u4 va, vb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          va[q] = (unsigned int)ea[8 * h + 2 * q] | ((unsigned int)ea[8 * h + 2 * q + 1] << 16);
+          vb[q] = (unsigned int)eb[8 * h + 2 * q] | ((unsigned int)eb[8 * h + 2 * q + 1] << 16);
+        }
+        *reinterpret_cast<u4*>(As + c * PB + kb + 8 * h) = va;
+        *reinterpret_cast<u4*>(Bs + c * PB + kb + 8 * h) = vb;
       }
-      *reinterpret_cast<u4*>(As + c * kGenPitch + kb) = va;
-      *reinterpret_cast<u4*>(Bs + c * kGenPitch + kb) = vb;
     }
     __syncthreads();
     if constexpr (KIND == GEN_DW) {
-      // bias gradient: the deltas as the products see them (BF16), the output layer's seed FP32
+      // bias gradient: the deltas as the products see them (BF16)
       if (n0 == 0 && tid < 64 && m0 + tid < O) {
-        const int kend = min(32, nrows - k0);
-        if (head) {
-          for (int r = 0; r < kend; ++r) db += g.dz[(r0 + k0 + r) * kOut + m0 + tid];
-        } else {
-          for (int r = 0; r < kend; ++r)
-            db += __builtin_bit_cast(float, (unsigned int)As[tid * kGenPitch + r] << 16);
-        }
+        const int kend = min(KC, nrows - k0);
+        for (int r = 0; r < kend; ++r)
+          db += __builtin_bit_cast(float, (unsigned int)As[tid * PB + r] << 16);
       }
     }
 #pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + m32) * kGenPitch + kc * 16 + kh * 8);
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * kGenPitch + kc * 16 + kh * 8);
+    for (int kc = 0; kc < KC / 16; ++kc) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + m32) * PB + kc * 16 + kh * 8);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * PB + kc * 16 + kh * 8);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
   }
@@ -3060,6 +3062,121 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
     }
     if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[k], 1);
   }
+}
+
+// Weight gradient of a layer with at most 32 outputs (every layer at hidden 16; the output layer
+// at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) of one object, and
+// its four waves take the object's rows in 32-row chunks in turn (chunk c to wave c mod 4), each
+// in its own LDS tiles, so the rows are summed four chunks at a time instead of one; the waves'
+// sums are then added in wave order. Deterministic, and independent of the grid.
+__global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  constexpr int kWaveTile = 2 * 32 * kGenPitch;  // one wave's A and B tiles (uint16 elements)
+  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kWaveTile];
+  const int H = g.H;
+  const bool head = (l == kLayers);
+  const int K = (l == 0) ? kEnc : H;
+  const int O = head ? kOut : H;  // at most 32 (the launch checks)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m32 = lane & 31, kh = lane >> 5;
+  const int64_t ld = g.ld;
+  const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;
+  const uint16_t* dout = head ? nullptr : g.delta[(3 - l) & 1];
+  const int j = blockIdx.x;
+  if (j >= a.n_objects || !a.scaler->batch_ok) return;
+  const int k = a.object_ids[j];
+  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
+  const int ts = a.tile_start[j];
+  if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;
+  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
+  const int64_t r0 = (int64_t)rr.lo * a.S;
+  const int nrows = (rr.hi - rr.lo) * a.S;
+  const int n0 = blockIdx.y * 32;
+  uint16_t* As = lds + wave * kWaveTile;
+  uint16_t* Bs = As + 32 * kGenPitch;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  float db = 0.f;  // this lane's rows of output m32's bias gradient (first column block)
+  for (int c = wave; c * 32 < nrows; c += 4) {
+    wave_lds_sync();  // this wave's previous chunk has been read
+    // lane: output / input index m32 of the tiles, rows c 32 + 16 kh .. + 15
+    unsigned short ea[16], eb[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = c * 32 + 16 * kh + e;
+      ea[e] = 0;
+      eb[e] = 0;
+      if (r < nrows) {
+        const int64_t row = r0 + r;
+        if (m32 < O) {
+          if (head) {
+            const float x = g.dz[row * kOut + m32];
+            ea[e] = (unsigned short)(pack2(x, 0.f) & 0xffffu);
+            if (n0 == 0) db += x;  // the output layer's seed, summed unrounded
+          } else {
+            ea[e] = dout[row * ld + m32];
+            if (n0 == 0) db += __builtin_bit_cast(float, (unsigned int)ea[e] << 16);
+          }
+        }
+        if (n0 + m32 < K) eb[e] = act_l[row * ld + n0 + m32];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u4 va, vb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        va[q] = (unsigned int)ea[8 * h + 2 * q] | ((unsigned int)ea[8 * h + 2 * q + 1] << 16);
+        vb[q] = (unsigned int)eb[8 * h + 2 * q] | ((unsigned int)eb[8 * h + 2 * q + 1] << 16);
+      }
+      *reinterpret_cast<u4*>(As + m32 * kGenPitch + 16 * kh + 8 * h) = va;
+      *reinterpret_cast<u4*>(Bs + m32 * kGenPitch + 16 * kh + 8 * h) = vb;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + m32 * kGenPitch + kc * 16 + kh * 8);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + m32 * kGenPitch + kc * 16 + kh * 8);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+  }
+  // the four waves' sums, added in wave order
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);  // [4 waves][16][64], then [4][64] bias parts
+  float* redb = red + 4 * 16 * 64;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) red[(wave * 16 + i) * 64 + lane] = acc[i];
+  redb[wave * 64 + lane] = db;
+  __syncthreads();
+  int bad = 0;
+  if (wave == 0) {
+    const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
+    float* dst = a.partial + (size_t)ts * a.p_stride + layer_param_off(H, l);
+    const int col = n0 + m32;
+    if (col < K) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int o = 8 * (i >> 2) + 4 * kh + (i & 3);
+        if (o >= O) continue;
+        float v = red[i * 64 + lane];
+        for (int w = 1; w < 4; ++w) v += red[(w * 16 + i) * 64 + lane];
+        v *= inv;
+        bad |= partial_bad(v);
+        dst[(size_t)o * K + col] = v;
+      }
+    }
+    if (n0 == 0 && lane < O) {
+      float v = 0.f;
+      for (int w = 0; w < 4; ++w) v += redb[w * 64 + lane] + redb[w * 64 + lane + 32];
+      v *= inv;
+      bad |= partial_bad(v);
+      dst[(size_t)O * K + lane] = v;
+    }
+  }
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[k], 1);
 }
 
 // Rendering, loss and (training) the adjoint of one row tile per wave, by the fused kernels'
@@ -3134,8 +3251,11 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream
   if (train) {
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
-      hipLaunchKernelGGL(k_gen_gemm<GEN_DW>, dim3(g.a.n_objects, blocks64(O) * blocks64(K)),
-                         dim3(256), 0, s, g, l);
+      if (O <= 32)
+        hipLaunchKernelGGL(k_gen_dw_small, dim3(g.a.n_objects, (K + 31) / 32), dim3(256), 0, s, g, l);
+      else
+        hipLaunchKernelGGL(k_gen_gemm<GEN_DW>, dim3(g.a.n_objects, blocks64(O) * blocks64(K)),
+                           dim3(256), 0, s, g, l);
       if (l > 0)
         hipLaunchKernelGGL(k_gen_gemm<GEN_DX>, dim3(tiles_bound, blocks64(K)), dim3(256), 0, s, g, l);
     }
