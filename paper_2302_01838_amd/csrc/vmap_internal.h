@@ -383,15 +383,18 @@ struct GenArgs {
   int64_t ld;            // elements per row of act and delta
   int64_t layer_elems;   // elements per layer of act
 };
-// Kinds of the layered path's product kernel.
-enum GenKind { GEN_FWD = 0, GEN_DX = 1, GEN_DW = 2 };
-// LDS of the product kernels: k_gen_gemm stages two 64 x kGenKChunk BF16 operand tiles (rows
-// padded by 8 elements); k_gen_dw_small four waves' pairs of 32 x 32 tiles (rows of 40).
+// Kinds of the layered path's row-tile product kernel (the weight gradients have their own).
+enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
+// LDS of the product kernels: k_gen_gemm and k_gen_dw stage two 64 x kGenKChunk BF16 operand
+// tiles (rows padded by 8 elements); k_gen_dw_small four waves' pairs of 32-row tiles (rows of
+// kGenPitch elements), then the waves' FP32 sums (16 accumulators and 8 bias parts per lane).
 constexpr int kGenKChunk = 64;
-constexpr int kGenPitch = 40;
-constexpr int kGenLdsBytes = 2 * 64 * (kGenKChunk + 8) * 2 > 4 * 2 * 32 * kGenPitch * 2
-                                 ? 2 * 64 * (kGenKChunk + 8) * 2
-                                 : 4 * 2 * 32 * kGenPitch * 2;
+constexpr int kGenPitch = 36;
+constexpr int kGenTileLds = 2 * 64 * (kGenKChunk + 8) * 2;
+constexpr int kGenSmallLds = (4 * 2 * 32 * kGenPitch * 2 > 4 * (4 * 16 * 64 + 4 * 64 * 8))
+                                 ? 4 * 2 * 32 * kGenPitch * 2
+                                 : 4 * (4 * 16 * 64 + 4 * 64 * 8);
+constexpr int kGenLdsBytes = kGenTileLds > kGenSmallLds ? kGenTileLds : kGenSmallLds;
 
 struct QueryArgs {
   const float* pts;

@@ -2744,17 +2744,18 @@ hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
 // product is rounded to BF16 (encoding, activations, weights, deltas, the output layer's seed),
 // products accumulate in FP32 on v_mfma_f32_32x32x16_bf16; biases, sigmoids, rendering, losses
 // and the output layer's bias gradient stay FP32. An object's weight gradient is summed over all
-// its rows, in row order, by one workgroup per 64 x 64 block of each weight matrix: no partials
-// to reduce, and the result does not depend on the grid or on the other objects.
+// its rows by one workgroup per block of each weight matrix, in an order fixed by the object's rows
+// alone: no partials to reduce, and the result does not depend on the grid or on the other objects.
 //
-// Product kernel: a workgroup (four waves) computes a 64 x 64 block of D = A B, each wave a 32 x 32
-// quarter, over K in chunks of 32 staged in LDS as BF16: As[m][k] and Bs[n][k] (B transposed), so
-// that the A and B operands of an MFMA are each one 16-byte LDS read per lane (lane l: row or column
-// l mod 32, the eight k of half l / 32 of the 16-wide step). Accumulator element 4 jj + i of lane l
-// holds D[8 jj + 4 (l / 32) + i][l mod 32].
+// Row-tile product kernel (k_gen_gemm): a workgroup (four waves) computes a 64 x 64 block of
+// D = A B over one row tile, each wave a 32 x 32 quarter, over K in chunks of 64 staged in LDS as
+// BF16. Accumulator element 4 jj + i of lane l holds D[8 jj + 4 (l / 32) + i][l mod 32].
 //   forward  (GEN_FWD): rows = samples, n = outputs, k = inputs;   A = h_l,   B = W_l^T
 //   input gradient (GEN_DX): rows = samples, n = inputs, k = outputs;  A = delta, B = W_l
-//   weight gradient (GEN_DW): rows = outputs, n = inputs, k = samples; A = delta^T, B = h_l^T
+// A is staged as its rows lie (k contiguous) and read as one 16-byte LDS read per lane; B is the
+// rows of W, staged as they lie, read directly (forward) or transposed (input gradient).
+// Weight gradients (k_gen_dw, k_gen_dw_small): rows = outputs, n = inputs, k = samples;
+// A = delta^T, B = h_l^T, both staged as the sample rows lie and read transposed.
 
 // Batch object of row tile t: the largest j with gts[j] <= t (objects without tiles have an empty
 // range and are passed over), by bisection.
@@ -2865,8 +2866,35 @@ __global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
   }
 }
 
+// Lane `lane`'s MFMA operand from a row-major BF16 tile T (pitch P elements, a multiple of 4): the
+// operand's K index runs down the rows kb + 8 (lane / 32) + 0..7 and its row or column index is
+// column cb + (lane mod 32). Lanes x, x + 4, x + 8 and x + 12 of each 16-lane group address four
+// consecutive rows at the same four-column run, so each ds_read_b64_tr_b16 hands every lane four
+// consecutive rows of its own column (the lane mapping the fused kernels' weight gradients use);
+// the second read, four rows further down, gives the other four of its eight.
+template <int P>
+__device__ __forceinline__ bf16x8 tr_operand(const uint16_t* T, int kb, int cb, int lane) {
+  typedef __attribute__((address_space(3))) v4i16 lds_v4;
+  const uint16_t* p = T + (kb + 8 * (lane >> 5) + ((lane & 15) >> 2)) * P + cb + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+  const v4i16 x = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(p));
+  const v4i16 y = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4*)(p + 4 * P));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// Sum of the eight BF16 of an MFMA operand, two at a time (v_dot2 against ones), added to s.
+__device__ __forceinline__ float operand_sum(bf16x8 v, float s) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  const u4 w = __builtin_bit_cast(u4, v);
+  const b2 ones = {(__bf16)1.0f, (__bf16)1.0f};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, (unsigned int)w[e]), ones, s, false);
+  return s;
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
+  static_assert(KIND == GEN_FWD || KIND == GEN_DX, "products over one row tile");
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
@@ -2882,45 +2910,25 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
   const uint16_t* dout = head ? nullptr : g.delta[(3 - l) & 1];  // delta at layer l's outputs
-  int k, m0 = 0, n0;
-  int64_t r0;      // first row (sample) of the rows this workgroup reads
-  int nrows;       // rows: of the row tile (GEN_FWD, GEN_DX) or of the whole object (GEN_DW)
-  int ts = 0;      // GEN_DW: the object's work tile (its partial)
-  if constexpr (KIND == GEN_DW) {
-    const int j = blockIdx.x;
-    // layers of at most 32 outputs (the output layer among them) take k_gen_dw_small
-    if (head || O <= 32 || j >= a.n_objects || !a.scaler->batch_ok) return;
-    k = a.object_ids[j];
-    if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
-    ts = a.tile_start[j];
-    if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;  // no rays: no tile
-    const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
-    r0 = (int64_t)rr.lo * a.S;
-    nrows = (rr.hi - rr.lo) * a.S;
-    const int nbi = (K + 63) / 64;
-    m0 = (blockIdx.y / nbi) * 64;
-    n0 = (blockIdx.y % nbi) * 64;
-  } else {
-    GenTile tl;
-    if (!gen_tile(g, a, blockIdx.x, tl)) return;
-    k = tl.k;
-    r0 = (int64_t)tl.lo * a.S;
-    nrows = (tl.hi - tl.lo) * a.S;
-    n0 = blockIdx.y * 64;
-  }
+  GenTile tl;
+  if (!gen_tile(g, a, blockIdx.x, tl)) return;
+  const int k = tl.k;
+  const int64_t r0 = (int64_t)tl.lo * a.S;  // first row (sample) of the tile
+  const int nrows = (tl.hi - tl.lo) * a.S;
+  const int n0 = blockIdx.y * 64;
   const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
-  const int ktot = (KIND == GEN_FWD) ? K : (KIND == GEN_DX ? O : nrows);
+  const int ktot = (KIND == GEN_FWD) ? K : O;
 
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  float db = 0.f;  // GEN_DW, first column block: bias gradient of output m0 + tid (tid < 64)
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u2w __attribute__((ext_vector_type(2)));
   for (int k0 = 0; k0 < ktot; k0 += KC) {
     __syncthreads();  // the previous chunk's operands have been read
-    if constexpr (KIND == GEN_FWD || KIND == GEN_DX) {
-      // A: 64 rows x KC k of the row-major input (h_l, or the deltas at the outputs); ktot is a
-      // multiple of 16 (or the output layer's 4 seeds), so a 16-wide group is all in or all out
+    // A: 64 rows x KC k of the row-major input (h_l, or the deltas at the outputs); ktot is a
+    // multiple of 16 (or the output layer's 4 seeds), so a 16-wide group is all in or all out
+    {
       const int m = tid >> 2, kq = (tid & 3) * 16;
       u4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
       if (m < nrows && k0 + kq < ktot) {
@@ -2937,76 +2945,45 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
       }
       *reinterpret_cast<u4*>(As + m * PB + kq) = v0;
       *reinterpret_cast<u4*>(As + m * PB + kq + 8) = v1;
-      if constexpr (KIND == GEN_FWD) {
-        // B: Bs[n][k] = W[n0 + n][k0 + k]
-        const int n = tid >> 2;
-        u4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
-        if (n0 + n < O && k0 + kq < K) {
-          const float* src = W + (size_t)(n0 + n) * K + k0 + kq;
-          const float4 x0 = *reinterpret_cast<const float4*>(src);
-          const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-          const float4 x2 = *reinterpret_cast<const float4*>(src + 8);
-          const float4 x3 = *reinterpret_cast<const float4*>(src + 12);
-          w0 = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
-          w1 = u4{pack2(x2.x, x2.y), pack2(x2.z, x2.w), pack2(x3.x, x3.y), pack2(x3.z, x3.w)};
-        }
-        *reinterpret_cast<u4*>(Bs + n * PB + kq) = w0;
-        *reinterpret_cast<u4*>(Bs + n * PB + kq + 8) = w1;
-      } else {
-        // B: Bs[n][k] = W[k0 + k][n0 + n] (W transposed)
-        const int n = tid & 63, kb = (tid >> 6) * 16;
-        float x[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int o = k0 + kb + e;
-          x[e] = (o < O && n0 + n < K) ? W[(size_t)o * K + n0 + n] : 0.f;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-          *reinterpret_cast<u4*>(Bs + n * PB + kb + 8 * h) =
-              u4{pack2(x[8 * h], x[8 * h + 1]), pack2(x[8 * h + 2], x[8 * h + 3]),
-                 pack2(x[8 * h + 4], x[8 * h + 5]), pack2(x[8 * h + 6], x[8 * h + 7])};
+    }
+    if constexpr (KIND == GEN_FWD) {
+      // B: Bs[n][k] = W[n0 + n][k0 + k] (a row of W per output, read as it lies)
+      const int n = tid >> 2, kq = (tid & 3) * 16;
+      u4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
+      if (n0 + n < O && k0 + kq < K) {
+        const float* src = W + (size_t)(n0 + n) * K + k0 + kq;
+        const float4 x0 = *reinterpret_cast<const float4*>(src);
+        const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
+        const float4 x2 = *reinterpret_cast<const float4*>(src + 8);
+        const float4 x3 = *reinterpret_cast<const float4*>(src + 12);
+        w0 = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+        w1 = u4{pack2(x2.x, x2.y), pack2(x2.z, x2.w), pack2(x3.x, x3.y), pack2(x3.z, x3.w)};
       }
+      *reinterpret_cast<u4*>(Bs + n * PB + kq) = w0;
+      *reinterpret_cast<u4*>(Bs + n * PB + kq + 8) = w1;
     } else {
-      // GEN_DW. A: As[m][k] = delta[r0 + k0 + k][m0 + m]; B: Bs[n][k] = h_l[r0 + k0 + k][n0 + n]
-      const int c = tid & 63, kb = (tid >> 6) * 16;
-      unsigned short ea[16], eb[16];
+      // B: Bs[o][n] = W[k0 + o][n0 + n], rows of W as they lie (four columns per 16-byte load),
+      // read transposed by tr_operand; O and K are multiples of 4
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int r = k0 + kb + e;
-        ea[e] = 0;
-        eb[e] = 0;
-        if (r < nrows) {
-          const int64_t row = r0 + r;
-          if (m0 + c < O) ea[e] = dout[row * ld + m0 + c];
-          if (n0 + c < K) eb[e] = act_l[row * ld + n0 + c];
+      for (int q = 0; q < 4; ++q) {
+        const int p = tid + 256 * q, o = p >> 4, c4 = (p & 15) * 4;
+        u2w w = {0u, 0u};
+        if (k0 + o < O && n0 + c4 < K) {
+          const float4 x = *reinterpret_cast<const float4*>(W + (size_t)(k0 + o) * K + n0 + c4);
+          w = u2w{pack2(x.x, x.y), pack2(x.z, x.w)};
         }
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        u4 va, vb;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          va[q] = (unsigned int)ea[8 * h + 2 * q] | ((unsigned int)ea[8 * h + 2 * q + 1] << 16);
-          vb[q] = (unsigned int)eb[8 * h + 2 * q] | ((unsigned int)eb[8 * h + 2 * q + 1] << 16);
-        }
-        *reinterpret_cast<u4*>(As + c * PB + kb + 8 * h) = va;
-        *reinterpret_cast<u4*>(Bs + c * PB + kb + 8 * h) = vb;
+        *reinterpret_cast<u2w*>(Bs + o * PB + c4) = w;
       }
     }
     __syncthreads();
-    if constexpr (KIND == GEN_DW) {
-      // bias gradient: the deltas as the products see them (BF16)
-      if (n0 == 0 && tid < 64 && m0 + tid < O) {
-        const int kend = min(KC, nrows - k0);
-        for (int r = 0; r < kend; ++r)
-          db += __builtin_bit_cast(float, (unsigned int)As[tid * PB + r] << 16);
-      }
-    }
 #pragma unroll
     for (int kc = 0; kc < KC / 16; ++kc) {
       const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + m32) * PB + kc * 16 + kh * 8);
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * PB + kc * 16 + kh * 8);
+      bf16x8 bv;
+      if constexpr (KIND == GEN_FWD)
+        bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * PB + kc * 16 + kh * 8);
+      else
+        bv = tr_operand<PB>(Bs, 16 * kc, 32 * wn, lane);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
   }
@@ -3029,7 +3006,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
         (g.act + (int64_t)(l + 1) * g.layer_elems)[row * ld + col] = (uint16_t)(pack2(h, 0.f) & 0xffffu);
       }
     }
-  } else if constexpr (KIND == GEN_DX) {
+  } else {
     if (col >= K) return;
     uint16_t* din = g.delta[(4 - l) & 1];  // delta at layer l - 1's outputs
 #pragma unroll
@@ -3041,120 +3018,243 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
       const bool on = act_l[row * ld + col] != 0;
       din[row * ld + col] = on ? (uint16_t)(pack2(acc[i], 0.f) & 0xffffu) : (uint16_t)0;
     }
-  } else {
-    const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
-    float* dst = a.partial + (size_t)ts * a.p_stride + layer_param_off(H, l);
-    int bad = 0;
-    if (col < K) {
+  }
+}
+
+// Object j of the batch whose weight gradient a workgroup of the layered path computes: its id,
+// work tile and rows, if it is one of the chain's objects with rows (else false).
+struct GenObj {
+  int k, ts;
+  int64_t r0;  // first row
+  int nrows;
+};
+__device__ __forceinline__ bool gen_object_rows(const GenArgs& g, const StepArgs& a, int j, GenObj& o) {
+  if (j >= a.n_objects || !a.scaler->batch_ok) return false;
+  const int k = a.object_ids[j];
+  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != g.H) return false;
+  const int ts = a.tile_start[j];
+  if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return false;  // no rays: no tile
+  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
+  o = GenObj{k, ts, (int64_t)rr.lo * a.S, (rr.hi - rr.lo) * a.S};
+  return true;
+}
+
+// Weight gradient of a hidden layer of more than 32 outputs: dW_l[o][i] = sum over the object's
+// rows r of delta_l[r][o] h_l[r][i], and the bias gradient sum_r delta_l[r][o] (the deltas as the
+// products see them, BF16). A workgroup computes the 64 x 64 block (outputs m0.., inputs n0..) of
+// one object, each wave a 32 x 32 quarter, over the object's rows in chunks of 64 taken in row
+// order. A chunk's rows are staged as they lie in memory (16-byte loads; the next chunk's loads are
+// in flight while the current chunk's products run) and the operands are read transposed; rows
+// past the object's end are staged as zeros.
+__global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  constexpr int R = 64, P = 72;  // rows per chunk; LDS pitch: 64 columns + 8 (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t As[R * P];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[R * P];
+  const int H = g.H;
+  const int K = (l == 0) ? kEnc : H, O = H;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
+  GenObj ob;
+  if (l >= kLayers || O <= 32 || !gen_object_rows(g, a, blockIdx.x, ob)) return;
+  const int64_t ld = g.ld;
+  const int nrows = ob.nrows;
+  const int nbi = (K + 63) / 64;
+  const int m0 = (blockIdx.y / nbi) * 64, n0 = (blockIdx.y % nbi) * 64;
+  // this thread's two 16-byte pieces of a chunk: rows prow and prow + 32, columns c8 .. c8 + 7
+  const int prow = tid >> 3, c8 = (tid & 7) * 8;
+  const uint16_t* dsrc = g.delta[(3 - l) & 1] + ob.r0 * ld + m0 + c8;
+  const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0 + c8;
+  const bool aok = m0 + c8 < O, bok = n0 + c8 < K;  // O and K are multiples of 8
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 va[2], vb[2];
+  auto fetch = [&](int k0) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int o = m0 + wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-        if (o >= O) continue;
-        const float v = acc[i] * inv;
-        bad |= partial_bad(v);
-        dst[(size_t)o * K + col] = v;
+    for (int q = 0; q < 2; ++q) {
+      const int r = k0 + prow + 32 * q;
+      va[q] = u4{0u, 0u, 0u, 0u};
+      vb[q] = u4{0u, 0u, 0u, 0u};
+      if (r < nrows) {
+        if (aok) va[q] = *reinterpret_cast<const u4*>(dsrc + (int64_t)r * ld);
+        if (bok) vb[q] = *reinterpret_cast<const u4*>(hsrc + (int64_t)r * ld);
       }
     }
-    if (n0 == 0 && tid < 64 && m0 + tid < O) {
-      const float v = db * inv;
-      bad |= partial_bad(v);
-      dst[(size_t)O * K + m0 + tid] = v;
+  };
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  // bias gradient (first column block, the waves of columns 0..31): this lane's rows of output
+  // m0 + 32 wm + m32
+  const bool bias = (n0 == 0 && wn == 0);
+  float db = 0.f;
+  fetch(0);
+  for (int k0 = 0; k0 < nrows; k0 += R) {
+    __syncthreads();  // the previous chunk's operands have been read
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<u4*>(As + (prow + 32 * q) * P + c8) = va[q];
+      *reinterpret_cast<u4*>(Bs + (prow + 32 * q) * P + c8) = vb[q];
     }
-    if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[k], 1);
+    if (k0 + R < nrows) fetch(k0 + R);
+    __syncthreads();
+#pragma unroll
+    for (int kc = 0; kc < R / 16; ++kc) {
+      const bf16x8 av = tr_operand<P>(As, 16 * kc, 32 * wm, lane);
+      const bf16x8 bv = tr_operand<P>(Bs, 16 * kc, 32 * wn, lane);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+      if (bias) db = operand_sum(av, db);
+    }
   }
+  const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
+  float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
+  int bad = 0;
+  const int col = n0 + wn * 32 + m32;
+  if (col < K) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int o = m0 + wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+      if (o >= O) continue;
+      const float v = acc[i] * inv;
+      bad |= partial_bad(v);
+      dst[(size_t)o * K + col] = v;
+    }
+  }
+  if (bias) {
+    const float other = __shfl(db, lane + 32);  // the output's other eight rows of each step
+    const int o = m0 + wm * 32 + m32;
+    if (kh == 0 && o < O) {
+      const float v = (db + other) * inv;
+      bad |= partial_bad(v);
+      dst[(size_t)O * K + o] = v;
+    }
+  }
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
 }
 
 // Weight gradient of a layer with at most 32 outputs (every layer at hidden 16; the output layer
 // at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) of one object, and
 // its four waves take the object's rows in 32-row chunks in turn (chunk c to wave c mod 4), each
-// in its own LDS tiles, so the rows are summed four chunks at a time instead of one; the waves'
-// sums are then added in wave order. Deterministic, and independent of the grid.
+// in its own LDS tiles, staged as the rows lie in memory (16-byte loads, the wave's next chunk in
+// flight during the current chunk's products) and read transposed. The waves' sums are added in
+// wave order, so the result does not depend on the grid. Bias gradient: the deltas as the products
+// see them (BF16), or the output layer's FP32 seed unrounded, summed per lane over its staged rows
+// and then over lanes and waves in a fixed order.
 __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  constexpr int kWaveTile = 2 * 32 * kGenPitch;  // one wave's A and B tiles (uint16 elements)
-  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kWaveTile];
+  constexpr int P = kGenPitch;                   // 32 columns + 4 (elements)
+  constexpr int kWaveTile = 2 * 32 * P;          // one wave's A and B tiles (uint16 elements)
+  constexpr int kRed = 4 * 16 * 64 + 4 * 64 * 8;  // floats of the final sums: accumulators, bias parts
+  __shared__ __attribute__((aligned(16))) uint16_t lds[(4 * kWaveTile > 2 * kRed) ? 4 * kWaveTile : 2 * kRed];
   const int H = g.H;
   const bool head = (l == kLayers);
   const int K = (l == 0) ? kEnc : H;
-  const int O = head ? kOut : H;  // at most 32 (the launch checks)
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m32 = lane & 31, kh = lane >> 5;
+  const int O = head ? kOut : H;  // 4, or a hidden width of 8, 16 or 32 (the launch checks)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  GenObj ob;
+  if (!gen_object_rows(g, a, blockIdx.x, ob)) return;
   const int64_t ld = g.ld;
-  const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;
-  const uint16_t* dout = head ? nullptr : g.delta[(3 - l) & 1];
-  const int j = blockIdx.x;
-  if (j >= a.n_objects || !a.scaler->batch_ok) return;
-  const int k = a.object_ids[j];
-  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
-  const int ts = a.tile_start[j];
-  if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;
-  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
-  const int64_t r0 = (int64_t)rr.lo * a.S;
-  const int nrows = (rr.hi - rr.lo) * a.S;
+  const int nrows = ob.nrows;
   const int n0 = blockIdx.y * 32;
+  const bool bias = (n0 == 0);
   uint16_t* As = lds + wave * kWaveTile;
-  uint16_t* Bs = As + 32 * kGenPitch;
+  uint16_t* Bs = As + 32 * P;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u2w __attribute__((ext_vector_type(2)));
+  // columns that no piece covers (A's past O) stay zero
+  for (int i = lane; i < kWaveTile / 8; i += 64) *reinterpret_cast<u4*>(As + 8 * i) = u4{0u, 0u, 0u, 0u};
+  // pieces of a 32-row chunk: B (h_l, columns n0..n0+31): p = lane + 64 q, row p / 4, columns
+  // 8 (p mod 4); A hidden (delta, columns 0..O-1): p = lane + 64 q below 32 per, row p / per,
+  // columns 8 (p mod per), per = O / 8; A of the output layer (the FP32 seed [rows][4]): lane < 32,
+  // row lane. A lane's columns are the same in every chunk.
+  const int lp = head ? 0 : (O >= 32 ? 2 : (O >= 16 ? 1 : 0)), per = 1 << lp;  // per = O / 8
+  const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0;
+  const uint16_t* dsrc = head ? nullptr : g.delta[(3 - l) & 1] + ob.r0 * ld;
+  const float* zsrc = g.dz + ob.r0 * kOut;
+  u4 va[2], vb[2];
+  float4 vz;
+  auto fetch = [&](int c) {
+    const int rb = c * 32;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = lane + 64 * q, r = rb + (p >> 2), cc = 8 * (p & 3);
+      vb[q] = u4{0u, 0u, 0u, 0u};
+      if (r < nrows && n0 + cc < K) vb[q] = *reinterpret_cast<const u4*>(hsrc + (int64_t)r * ld + cc);
+    }
+    if (head) {
+      vz = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (lane < 32 && rb + lane < nrows) vz = *reinterpret_cast<const float4*>(zsrc + (int64_t)(rb + lane) * kOut);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int p = lane + 64 * q, r = rb + (p >> lp);
+        va[q] = u4{0u, 0u, 0u, 0u};
+        if (p < 32 * per && r < nrows) va[q] = *reinterpret_cast<const u4*>(dsrc + (int64_t)r * ld + 8 * (p & (per - 1)));
+      }
+    }
+  };
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  float db = 0.f;  // this lane's rows of output m32's bias gradient (first column block)
+  float dbv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this lane's columns' bias parts
+  if (wave * 32 < nrows) fetch(wave);
   for (int c = wave; c * 32 < nrows; c += 4) {
     wave_lds_sync();  // this wave's previous chunk has been read
-    // lane: output / input index m32 of the tiles, rows c 32 + 16 kh .. + 15
-    unsigned short ea[16], eb[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = c * 32 + 16 * kh + e;
-      ea[e] = 0;
-      eb[e] = 0;
-      if (r < nrows) {
-        const int64_t row = r0 + r;
-        if (m32 < O) {
-          if (head) {
-            const float x = g.dz[row * kOut + m32];
-            ea[e] = (unsigned short)(pack2(x, 0.f) & 0xffffu);
-            if (n0 == 0) db += x;  // the output layer's seed, summed unrounded
-          } else {
-            ea[e] = dout[row * ld + m32];
-            if (n0 == 0) db += __builtin_bit_cast(float, (unsigned int)ea[e] << 16);
+    for (int q = 0; q < 2; ++q) {
+      const int p = lane + 64 * q;
+      *reinterpret_cast<u4*>(Bs + (p >> 2) * P + 8 * (p & 3)) = vb[q];
+    }
+    if (head) {
+      if (lane < 32) {
+        *reinterpret_cast<u2w*>(As + lane * P) = u2w{pack2(vz.x, vz.y), pack2(vz.z, vz.w)};
+        if (bias) {
+          dbv[0] += vz.x;
+          dbv[1] += vz.y;
+          dbv[2] += vz.z;
+          dbv[3] += vz.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int p = lane + 64 * q;
+        if (p < 32 * per) {
+          *reinterpret_cast<u4*>(As + (p >> lp) * P + 8 * (p & (per - 1))) = va[q];
+          if (bias) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              dbv[e] += __builtin_bit_cast(float, ((va[q][e >> 1] >> (16 * (e & 1))) & 0xffffu) << 16);
           }
         }
-        if (n0 + m32 < K) eb[e] = act_l[row * ld + n0 + m32];
       }
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      u4 va, vb;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        va[q] = (unsigned int)ea[8 * h + 2 * q] | ((unsigned int)ea[8 * h + 2 * q + 1] << 16);
-        vb[q] = (unsigned int)eb[8 * h + 2 * q] | ((unsigned int)eb[8 * h + 2 * q + 1] << 16);
-      }
-      *reinterpret_cast<u4*>(As + m32 * kGenPitch + 16 * kh + 8 * h) = va;
-      *reinterpret_cast<u4*>(Bs + m32 * kGenPitch + 16 * kh + 8 * h) = vb;
-    }
+    if ((c + 4) * 32 < nrows) fetch(c + 4);
     wave_lds_sync();
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + m32 * kGenPitch + kc * 16 + kh * 8);
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bs + m32 * kGenPitch + kc * 16 + kh * 8);
+      const bf16x8 av = tr_operand<P>(As, 16 * kc, 0, lane);
+      const bf16x8 bv = tr_operand<P>(Bs, 16 * kc, 0, lane);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
   }
   // the four waves' sums, added in wave order
   __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);  // [4 waves][16][64], then [4][64] bias parts
+  float* red = reinterpret_cast<float*>(lds);  // [4 waves][16][64], then [4 waves][64 lanes][8]
   float* redb = red + 4 * 16 * 64;
 #pragma unroll
   for (int i = 0; i < 16; ++i) red[(wave * 16 + i) * 64 + lane] = acc[i];
-  redb[wave * 64 + lane] = db;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) redb[(wave * 64 + lane) * 8 + e] = dbv[e];
   __syncthreads();
   int bad = 0;
   if (wave == 0) {
     const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
-    float* dst = a.partial + (size_t)ts * a.p_stride + layer_param_off(H, l);
+    float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
+    const int m32 = lane & 31, kh = lane >> 5;
     const int col = n0 + m32;
     if (col < K) {
 #pragma unroll
@@ -3168,15 +3268,19 @@ __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l)
         dst[(size_t)o * K + col] = v;
       }
     }
-    if (n0 == 0 && lane < O) {
+    if (bias && lane < O) {
+      // output o: lanes whose pieces hold its column (head: lanes 0..31, element o), in order
+      const int o = lane;
+      const int chunk = head ? 0 : (o >> 3), e = head ? o : (o & 7), nl = head ? 32 : 64;
       float v = 0.f;
-      for (int w = 0; w < 4; ++w) v += redb[w * 64 + lane] + redb[w * 64 + lane + 32];
+      for (int w = 0; w < 4; ++w)
+        for (int L = chunk; L < nl; L += per) v += redb[(w * 64 + L) * 8 + e];
       v *= inv;
       bad |= partial_bad(v);
-      dst[(size_t)O * K + lane] = v;
+      dst[(size_t)O * K + o] = v;
     }
   }
-  if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[k], 1);
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
 }
 
 // Rendering, loss and (training) the adjoint of one row tile per wave, by the fused kernels'
@@ -3235,6 +3339,8 @@ __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
 hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream_t s) {
   if (tiles_bound <= 0 || g.a.n_objects <= 0) return hipSuccess;
   if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots) return hipErrorInvalidValue;
+  // k_gen_dw_small stages a narrow hidden layer's deltas in 8-column runs, 1, 2 or 4 per row
+  if (g.H <= 32 && g.H != 8 && g.H != 16 && g.H != 32) return hipErrorInvalidValue;
   const bool train = (mode == MODE_TRAIN);
   const int H = g.H;
   const int wave_blocks = (tiles_bound + 3) / 4;
@@ -3254,8 +3360,7 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream
       if (O <= 32)
         hipLaunchKernelGGL(k_gen_dw_small, dim3(g.a.n_objects, (K + 31) / 32), dim3(256), 0, s, g, l);
       else
-        hipLaunchKernelGGL(k_gen_gemm<GEN_DW>, dim3(g.a.n_objects, blocks64(O) * blocks64(K)),
-                           dim3(256), 0, s, g, l);
+        hipLaunchKernelGGL(k_gen_dw, dim3(g.a.n_objects, blocks64(O) * blocks64(K)), dim3(256), 0, s, g, l);
       if (l > 0)
         hipLaunchKernelGGL(k_gen_gemm<GEN_DX>, dim3(tiles_bound, blocks64(K)), dim3(256), 0, s, g, l);
     }
