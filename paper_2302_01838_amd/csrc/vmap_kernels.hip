@@ -2181,6 +2181,7 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
 // data); the validity checks only decide what is stored. Thread 0 works out the Adam
 // coefficients while the loads are in flight. The grid has one row of workgroups per batch object
 // and a last row whose first workgroup updates the loss scaler (its own chain of loads).
+template <int V>
 __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   OptArgs a = a_in;
   read_batch(a);
@@ -2199,14 +2200,41 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   const int kc = in_range ? k : 0;  // loads of an id out of range are discarded
   const ObjDesc& d = a.desc[kc];
   const int registered = d.registered, n_params = d.n_params, hidden = d.hidden;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = (blockIdx.x * blockDim.x + threadIdx.x) * V;  // p_stride is a multiple of V
   const size_t i = (size_t)kc * a.p_stride + p;
-  float th = 0.f, m = 0.f, v = 0.f, g = 0.f;
+  float th[V], m[V], v[V], g[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) th[e] = m[e] = v[e] = g[e] = 0.f;
   if (p < a.p_stride) {
-    th = a.theta[i];
-    m = a.m[i];
-    v = a.v[i];
-    g = tile_sum(a.partial, a.p_stride, t0, t1, p);
+    if constexpr (V == 1) {
+      th[0] = a.theta[i];
+      m[0] = a.m[i];
+      v[0] = a.v[i];
+      g[0] = tile_sum(a.partial, a.p_stride, t0, t1, p);
+    } else {
+      const float4 x = *reinterpret_cast<const float4*>(a.theta + i);
+      const float4 y = *reinterpret_cast<const float4*>(a.m + i);
+      const float4 z = *reinterpret_cast<const float4*>(a.v + i);
+      th[0] = x.x, th[1] = x.y, th[2] = x.z, th[3] = x.w;
+      m[0] = y.x, m[1] = y.y, m[2] = y.z, m[3] = y.w;
+      v[0] = z.x, v[1] = z.y, v[2] = z.z, v[3] = z.w;
+      // the tiles' partials at p .. p + 3, each summed in tile order from zero as tile_sum does
+      for (int tt = t0; tt < t1; tt += 8) {
+        float4 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          q[u] = (tt + u < t1) ? *reinterpret_cast<const float4*>(a.partial + (size_t)(tt + u) * a.p_stride + p)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (tt + u < t1) {
+            g[0] += q[u].x;
+            g[1] += q[u].y;
+            g[2] += q[u].z;
+            g[3] += q[u].w;
+          }
+      }
+    }
   }
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   float loss = 0.f;
@@ -2222,17 +2250,20 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     return;
   }
   const AdamCoef c = adam_coef_load(a, sh);
-  if (p < n_params) {
-    a.grad[i] = g;
-    if (isfinite(g)) {
-      adam_elem(c, g, th, m, v);
-      a.theta[i] = th;
-      a.m[i] = m;
-      a.v[i] = v;
-    } else {
-      atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    if (p + e < n_params) {
+      a.grad[i + e] = g[e];
+      if (isfinite(g[e])) {
+        adam_elem(c, g[e], th[e], m[e], v[e]);
+        a.theta[i + e] = th[e];
+        a.m[i + e] = m[e];
+        a.v[i + e] = v[e];
+      } else {
+        atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
+      }
+      update_image(a, k, hidden, p + e, th[e]);
     }
-    update_image(a, k, hidden, p, th);
   }
   if (lead) a.desc[k].step = t;
 }
@@ -2699,13 +2730,20 @@ hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
   return hipGetLastError();
 }
 
+// Parameter slots per object from which k_reduce_adam takes four parameters per thread (objects of
+// hidden 256 and up: their update streams whole vectors of theta, m, v and the partials; below,
+// one per thread keeps more workgroups in flight for the few-thousand-parameter objects).
+constexpr int kReduceWide = 65536;
+
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
   if (a.n_objects <= 0) return hipSuccess;
   const dim3 grid((a.p_stride + 255) / 256, a.n_objects);
   if (kind == OPT_REDUCE) hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, 1);
   else if (kind == OPT_LOSS) hipLaunchKernelGGL(k_reduce, dim3(1, a.n_objects), dim3(256), 0, s, a, 0);
   else if (kind == OPT_ADAM) hipLaunchKernelGGL(k_adam, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_reduce_adam, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
+  else if (a.p_stride >= kReduceWide && a.p_stride % 4 == 0)  // four parameters per thread
+    hipLaunchKernelGGL(k_reduce_adam<4>, dim3((a.p_stride / 4 + 255) / 256, a.n_objects + 1), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_reduce_adam<1>, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2915,6 +2953,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int k = tl.k;
   const int64_t r0 = (int64_t)tl.lo * a.S;  // first row (sample) of the tile
   const int nrows = (tl.hi - tl.lo) * a.S;
+  if (nrows <= 0) return;  // (a validated batch has no empty tile)
   const int n0 = blockIdx.y * 64;
   const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
   const int ktot = (KIND == GEN_FWD) ? K : O;
@@ -3009,14 +3048,19 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   } else {
     if (col >= K) return;
     uint16_t* din = g.delta[(4 - l) & 1];  // delta at layer l - 1's outputs
+    // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive. All
+    // sixteen loads go out before the first store (rows past the tile read its last row instead)
+    uint16_t hv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = min(wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3), nrows - 1);
+      hv[i] = act_l[(r0 + r) * ld + col];
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int r = wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
       if (r >= nrows) continue;
-      const int64_t row = r0 + r;
-      // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive
-      const bool on = act_l[row * ld + col] != 0;
-      din[row * ld + col] = on ? (uint16_t)(pack2(acc[i], 0.f) & 0xffffu) : (uint16_t)0;
+      din[(r0 + r) * ld + col] = hv[i] != 0 ? (uint16_t)(pack2(acc[i], 0.f) & 0xffffu) : (uint16_t)0;
     }
   }
 }
