@@ -2807,6 +2807,12 @@ __device__ __forceinline__ int gen_object(const int32_t* __restrict__ gts, int n
   return lo;
 }
 
+// Delta buffer i mod 2 (a select: indexing the kernel argument's array by a run-time value would
+// put the whole argument block in per-lane scratch memory).
+__device__ __forceinline__ uint16_t* gen_delta(const GenArgs& g, int i) {
+  return (i & 1) ? g.delta[1] : g.delta[0];
+}
+
 struct GenTile {
   int j, k, lo, hi;  // batch object, object id, rays [lo, hi)
 };
@@ -2947,7 +2953,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
-  const uint16_t* dout = head ? nullptr : g.delta[(3 - l) & 1];  // delta at layer l's outputs
+  const uint16_t* dout = head ? nullptr : gen_delta(g, 3 - l);  // delta at layer l's outputs
   GenTile tl;
   if (!gen_tile(g, a, blockIdx.x, tl)) return;
   const int k = tl.k;
@@ -3047,7 +3053,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
     }
   } else {
     if (col >= K) return;
-    uint16_t* din = g.delta[(4 - l) & 1];  // delta at layer l - 1's outputs
+    uint16_t* din = gen_delta(g, 4 - l);  // delta at layer l - 1's outputs
     // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive. All
     // sixteen loads go out before the first store (rows past the tile read its last row instead)
     uint16_t hv[16];
@@ -3109,7 +3115,7 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
   const int m0 = (blockIdx.y / nbi) * 64, n0 = (blockIdx.y % nbi) * 64;
   // this thread's two 16-byte pieces of a chunk: rows prow and prow + 32, columns c8 .. c8 + 7
   const int prow = tid >> 3, c8 = (tid & 7) * 8;
-  const uint16_t* dsrc = g.delta[(3 - l) & 1] + ob.r0 * ld + m0 + c8;
+  const uint16_t* dsrc = gen_delta(g, 3 - l) + ob.r0 * ld + m0 + c8;
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0 + c8;
   const bool aok = m0 + c8 < O, bok = n0 + c8 < K;  // O and K are multiples of 8
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -3216,7 +3222,7 @@ __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l)
   // row lane. A lane's columns are the same in every chunk.
   const int lp = head ? 0 : (O >= 32 ? 2 : (O >= 16 ? 1 : 0)), per = 1 << lp;  // per = O / 8
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0;
-  const uint16_t* dsrc = head ? nullptr : g.delta[(3 - l) & 1] + ob.r0 * ld;
+  const uint16_t* dsrc = head ? nullptr : gen_delta(g, 3 - l) + ob.r0 * ld;
   const float* zsrc = g.dz + ob.r0 * kOut;
   u4 va[2], vb[2];
   float4 vz;
