@@ -35,8 +35,8 @@ struct WorkLayout {
   size_t wimage_stride;
   int max_tiles;
   // layered path (generic widths): row tiles, their losses, activations, deltas, z and dz
-  size_t gts, gen_loss, gact, gdelta, gz, gdz;
-  int max_gen_tiles;
+  size_t gts, gbs, gen_loss, gact, gdelta, gz, gdz;
+  int max_gen_tiles, max_gen_blocks;
   int64_t gen_ld, gen_rows;
 };
 
@@ -144,7 +144,9 @@ WorkLayout work_layout(const vmap_config* c) {
     w.gen_ld = std::max(kEnc, c->max_hidden);
     w.gen_rows = (int64_t)c->max_rays * c->max_samples_per_ray;
     const size_t layer = (size_t)w.gen_rows * (size_t)w.gen_ld * 2;
+    w.max_gen_blocks = (int)((w.gen_rows + kGenBlockRows - 1) / kGenBlockRows) + c->max_objects;
     w.gts = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
+    w.gbs = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
     w.gen_loss = off; off = align256(off + (size_t)w.max_gen_tiles * 4);
     w.gact = off; off = align256(off + (size_t)(kLayers + 1) * layer);
     w.gdelta = off; off = align256(off + 2 * layer);
@@ -413,6 +415,8 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       g.rpw = std::max(1, kSlots / b->samples_per_ray);
       g.max_gen_tiles = c->wl.max_gen_tiles;
       g.gts = reinterpret_cast<int32_t*>(c->work + c->wl.gts);
+      g.gbs = reinterpret_cast<int32_t*>(c->work + c->wl.gbs);
+      g.max_gen_blocks = c->wl.max_gen_blocks;
       g.gen_loss = reinterpret_cast<float*>(c->work + c->wl.gen_loss);
       g.act = reinterpret_cast<uint16_t*>(c->work + c->wl.gact);
       const size_t layer = (size_t)c->wl.gen_rows * (size_t)c->wl.gen_ld;
@@ -424,7 +428,10 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       g.layer_elems = (int64_t)layer;
       const int tiles_bound = (b->n_rays_total + g.rpw - 1) / g.rpw + b->n_objects;
       if (tiles_bound > g.max_gen_tiles) return c->fail(VMAP_ECAPACITY, "batch needs more row tiles than the workspace holds");
-      hipError_t e = launch_generic(mode, g, tiles_bound, si);
+      const long long rows = (long long)b->n_rays_total * b->samples_per_ray;
+      const long long blocks_bound = (rows + kGenBlockRows - 1) / kGenBlockRows + b->n_objects;
+      if (blocks_bound > g.max_gen_blocks) return c->fail(VMAP_ECAPACITY, "batch needs more row blocks than the workspace holds");
+      hipError_t e = launch_generic(mode, g, tiles_bound, (int)blocks_bound, si);
       if (e != hipSuccess) return c->hip_fail(e, "layered-path launch");
       continue;
     }

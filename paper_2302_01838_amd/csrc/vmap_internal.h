@@ -382,15 +382,21 @@ struct GenArgs {
   float* dz;             // [rows][4] their adjoints (times the seed's scale)
   int64_t ld;            // elements per row of act and delta
   int64_t layer_elems;   // elements per layer of act
+  int max_gen_blocks;    // 128-row blocks the block table holds
+  int32_t* gbs;          // [n_objects + 1] first 128-row block of each batch object
 };
-// Kinds of the layered path's row-tile product kernel (the weight gradients have their own).
+// Kinds of the layered path's row-block product kernel (the weight gradients have their own).
 enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
-// LDS of the product kernels: k_gen_gemm and k_gen_dw stage two 64 x kGenKChunk BF16 operand
-// tiles (rows padded by 8 elements); k_gen_dw_small four waves' pairs of 32-row tiles (rows of
-// kGenPitch elements), then the waves' FP32 sums (16 accumulators and 8 bias parts per lane).
+// Rows of a block of the wide products (128 x 128 output blocks): an object's rows in order, cut
+// every kGenBlockRows rows regardless of ray boundaries (rows are independent in those products).
+constexpr int kGenBlockRows = 128;
+// LDS of the product kernels: k_gen_gemm and k_gen_dw stage two BF16 operand tiles of up to
+// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small four waves' pairs of
+// 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16 accumulators and 8 bias
+// parts per lane).
 constexpr int kGenKChunk = 64;
 constexpr int kGenPitch = 36;
-constexpr int kGenTileLds = 2 * 64 * (kGenKChunk + 8) * 2;
+constexpr int kGenTileLds = 2 * 128 * (kGenKChunk + 8) * 2;
 constexpr int kGenSmallLds = (4 * 2 * 32 * kGenPitch * 2 > 4 * (4 * 16 * 64 + 4 * 64 * 8))
                                  ? 4 * 2 * 32 * kGenPitch * 2
                                  : 4 * (4 * 16 * 64 + 4 * 64 * 8);
@@ -460,7 +466,7 @@ hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s);
 // products, rendering (and loss), then in training the backward products, writing each object's
 // unscaled gradient into its one tile partial and its loss into that tile's loss. tiles_bound:
 // host bound on the row tiles (ceil(n_rays / rpw) + n_objects).
-hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream_t s);
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s);
 enum OptKind { OPT_LOSS = 0, OPT_REDUCE = 1, OPT_ADAM = 2, OPT_REDUCE_ADAM = 3 };
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s);
 hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,

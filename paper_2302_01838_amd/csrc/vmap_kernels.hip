@@ -2731,9 +2731,10 @@ hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
 }
 
 // Parameter slots per object from which k_reduce_adam takes four parameters per thread (objects of
-// hidden 256 and up: their update streams whole vectors of theta, m, v and the partials; below,
-// one per thread keeps more workgroups in flight for the few-thousand-parameter objects).
-constexpr int kReduceWide = 65536;
+// hidden 128 and up: their update streams whole vectors of theta, m, v and the partials; measured
+// 5 % faster on a step with a hidden-128 object). Below, one per thread keeps more workgroups in
+// flight for the few-thousand-parameter objects (four per thread measured 2 % slower at hidden 32).
+constexpr int kReduceWide = 32768;
 
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
   if (a.n_objects <= 0) return hipSuccess;
@@ -2828,39 +2829,55 @@ __device__ __forceinline__ bool gen_tile(const GenArgs& g, const StepArgs& a, in
   return true;
 }
 
-// Row tiles per batch object: ceil(rays / rpw) for the objects of width H, none for the others or
-// for a batch that failed the offsets check (ScalerState::batch_ok, from the work-list launch).
+// Row tiles per batch object, ceil(rays / rpw), and 128-row product blocks, ceil(rays S / 128), for
+// the objects of width H; none for the others or for a batch that failed the offsets check
+// (ScalerState::batch_ok, from the work-list launch). gts and gbs: their exclusive scans.
 __global__ void __launch_bounds__(1024) k_gen_tiles(const GenArgs g_in) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  __shared__ int part[1024];
+  __shared__ int part[2][1024];
   const bool ok = a.scaler->batch_ok != 0;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (a.n_objects + nt - 1) / nt;
   const int j0 = min(tid * per, a.n_objects), j1 = min(j0 + per, a.n_objects);
-  auto count = [&](int j) {
+  auto rays = [&](int j) {
     const int k = a.object_ids[j];
     if (!ok || k < 0 || k >= a.max_objects) return 0;
     if (!a.desc[k].registered || a.desc[k].hidden != g.H) return 0;
-    return tiles_of(a.ray_offsets[j + 1] - a.ray_offsets[j], g.rpw);
+    const int nr = a.ray_offsets[j + 1] - a.ray_offsets[j];
+    return nr > 0 ? nr : 0;
   };
-  int local = 0;
-  for (int j = j0; j < j1; ++j) local += count(j);
-  part[tid] = local;
+  auto nblk = [&](int nr) { return (int)(((long long)nr * a.S + kGenBlockRows - 1) / kGenBlockRows); };
+  int lt = 0, lb = 0;
+  for (int j = j0; j < j1; ++j) {
+    const int nr = rays(j);
+    lt += tiles_of(nr, g.rpw);
+    lb += nblk(nr);
+  }
+  part[0][tid] = lt;
+  part[1][tid] = lb;
   __syncthreads();
   for (int off = 1; off < nt; off <<= 1) {
-    const int v = (tid >= off) ? part[tid - off] : 0;
+    const int vt = (tid >= off) ? part[0][tid - off] : 0;
+    const int vb = (tid >= off) ? part[1][tid - off] : 0;
     __syncthreads();
-    part[tid] += v;
+    part[0][tid] += vt;
+    part[1][tid] += vb;
     __syncthreads();
   }
-  int run = part[tid] - local;
+  int rt = part[0][tid] - lt, rb = part[1][tid] - lb;
   for (int j = j0; j < j1; ++j) {
-    g.gts[j] = run;
-    run += count(j);
+    const int nr = rays(j);
+    g.gts[j] = rt;
+    g.gbs[j] = rb;
+    rt += tiles_of(nr, g.rpw);
+    rb += nblk(nr);
   }
-  if (tid == nt - 1) g.gts[a.n_objects] = part[nt - 1];
+  if (tid == nt - 1) {
+    g.gts[a.n_objects] = part[0][nt - 1];
+    g.gbs[a.n_objects] = part[1][nt - 1];
+  }
 }
 
 // Encoding of every sample of a row tile (one wave per tile): normalised point in FP64 rounded
@@ -2936,15 +2953,52 @@ __device__ __forceinline__ float operand_sum(bf16x8 v, float s) {
   return s;
 }
 
-template <int KIND>
+// Rows of product block b of the layered chain: T = 64, row tile b (at most 64 rows, whole rays);
+// T = 128, the 128-row block b of the block table (an object's rows in order, cut every 128 rows).
+// False if b is past the chain's blocks or holds no row.
+template <int T>
+__device__ __forceinline__ bool gen_rows(const GenArgs& g, const StepArgs& a, int b, int& k, int64_t& r0, int& nrows) {
+  if constexpr (T == 64) {
+    GenTile tl;
+    if (!gen_tile(g, a, b, tl)) return false;
+    k = tl.k;
+    r0 = (int64_t)tl.lo * a.S;
+    nrows = (tl.hi - tl.lo) * a.S;
+  } else {
+    static_assert(T == kGenBlockRows, "row blocks of 128");
+    const int total = clamp_tiles(g.gbs[a.n_objects], g.max_gen_blocks);
+    if (b >= total) return false;
+    const int j = gen_object(g.gbs, a.n_objects, b);
+    const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
+    const int64_t first = (int64_t)(b - g.gbs[j]) * T;
+    const int64_t rows = (int64_t)(rr.hi - rr.lo) * a.S;
+    k = a.object_ids[j];
+    r0 = (int64_t)rr.lo * a.S + first;
+    nrows = (int)(rows - first < T ? rows - first : T);
+  }
+  return nrows > 0;  // (a validated batch has no empty block)
+}
+
+// Forward and input-gradient products of one row block: a workgroup (four waves, 2 x 2) computes
+// a T x T block of D = A B (T = 64 or 128), each wave a T/2 x T/2 quarter as (T/64)^2 32 x 32
+// MFMA tiles, over K in chunks of 64. A (h_l, or the deltas at layer l's outputs) is staged as its
+// rows lie; B is rows of W (FP32, rounded to BF16 as staged), read directly (forward: W rows are
+// the output columns, k contiguous) or transposed (input gradient: W rows are the k index). The
+// next chunk's loads are in flight while the current chunk's products run.
+template <int KIND, int T>
 __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
-  static_assert(KIND == GEN_FWD || KIND == GEN_DX, "products over one row tile");
+  static_assert(KIND == GEN_FWD || KIND == GEN_DX, "products over one row block");
+  static_assert(T == 64 || T == 128, "block sizes");
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  constexpr int KC = kGenKChunk, PB = KC + 8;  // K per staged chunk, LDS row pitch (elements)
-  __shared__ __attribute__((aligned(16))) uint16_t As[64 * PB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * PB];
+  constexpr int KC = kGenKChunk, PA = KC + 8;  // K per chunk; pitch of k-contiguous tiles
+  constexpr int PT = T + T / 8;                // pitch of the transposed W tile (rows = k)
+  constexpr int WT = T / 2, NS = WT / 32;      // wave tile, 32 x 32 MFMA tiles per dimension
+  constexpr int NA = T * KC / 8 / 256;         // A pieces (8 BF16) per thread and chunk
+  constexpr int NB = T * KC / 4 / 256;         // W pieces (4 FP32) per thread and chunk
+  __shared__ __attribute__((aligned(16))) uint16_t As[T * PA];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[(KIND == GEN_FWD) ? T * PA : KC * PT];
   const int H = g.H;
   const bool head = (l == kLayers);
   const int K = (l == 0) ? kEnc : H;  // inputs of layer l
@@ -2954,119 +3008,134 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
   const uint16_t* dout = head ? nullptr : gen_delta(g, 3 - l);  // delta at layer l's outputs
-  GenTile tl;
-  if (!gen_tile(g, a, blockIdx.x, tl)) return;
-  const int k = tl.k;
-  const int64_t r0 = (int64_t)tl.lo * a.S;  // first row (sample) of the tile
-  const int nrows = (tl.hi - tl.lo) * a.S;
-  if (nrows <= 0) return;  // (a validated batch has no empty tile)
-  const int n0 = blockIdx.y * 64;
+  int k, nrows;
+  int64_t r0;
+  if (!gen_rows<T>(g, a, blockIdx.x, k, r0, nrows)) return;
+  const int n0 = blockIdx.y * T;
   const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
   const int ktot = (KIND == GEN_FWD) ? K : O;
-
-  f32x16 acc;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   typedef unsigned int u2w __attribute__((ext_vector_type(2)));
+  // A piece p = tid + 256 q: row p / 8, k columns 8 (p mod 8); ktot is a multiple of 8, or the
+  // output layer's 4 seeds (FP32 [rows][4], rounded here)
+  u4 va[NA];
+  float4 vw[NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int p = tid + 256 * q, m = p >> 3, c = (p & 7) * 8;
+      va[q] = u4{0u, 0u, 0u, 0u};
+      if (m < nrows && k0 + c < ktot) {
+        const int64_t row = r0 + m;
+        if (KIND == GEN_DX && head) {
+          const float4 d4 = *reinterpret_cast<const float4*>(g.dz + row * kOut);
+          va[q] = u4{pack2(d4.x, d4.y), pack2(d4.z, d4.w), 0u, 0u};
+        } else {
+          va[q] = *reinterpret_cast<const u4*>(((KIND == GEN_FWD) ? act_l : dout) + row * ld + k0 + c);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int p = tid + 256 * q;
+      vw[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (KIND == GEN_FWD) {  // W rows n0 + n, k0 + c .. + 3
+        const int n = p >> 4, c = (p & 15) * 4;
+        if (n0 + n < O && k0 + c < K) vw[q] = *reinterpret_cast<const float4*>(W + (size_t)(n0 + n) * K + k0 + c);
+      } else {  // W rows k0 + o, columns n0 + c .. + 3
+        const int o = p / (T / 4), c = (p % (T / 4)) * 4;
+        if (k0 + o < O && n0 + c < K) vw[q] = *reinterpret_cast<const float4*>(W + (size_t)(k0 + o) * K + n0 + c);
+      }
+    }
+  };
+  f32x16 acc[NS][NS];
+#pragma unroll
+  for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NS; ++ni)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[mi][ni][i] = 0.f;
+  fetch(0);
   for (int k0 = 0; k0 < ktot; k0 += KC) {
     __syncthreads();  // the previous chunk's operands have been read
-    // A: 64 rows x KC k of the row-major input (h_l, or the deltas at the outputs); ktot is a
-    // multiple of 16 (or the output layer's 4 seeds), so a 16-wide group is all in or all out
-    {
-      const int m = tid >> 2, kq = (tid & 3) * 16;
-      u4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-      if (m < nrows && k0 + kq < ktot) {
-        const int64_t row = r0 + m;
-        if (KIND == GEN_DX && head) {  // the output layer's seed, FP32 [rows][4], rounded
-          const float* d4 = g.dz + row * kOut;
-          v0[0] = pack2(d4[0], d4[1]);
-          v0[1] = pack2(d4[2], d4[3]);
-        } else {
-          const uint16_t* src = ((KIND == GEN_FWD) ? act_l : dout) + row * ld + k0 + kq;
-          v0 = *reinterpret_cast<const u4*>(src);
-          v1 = *reinterpret_cast<const u4*>(src + 8);
-        }
-      }
-      *reinterpret_cast<u4*>(As + m * PB + kq) = v0;
-      *reinterpret_cast<u4*>(As + m * PB + kq + 8) = v1;
-    }
-    if constexpr (KIND == GEN_FWD) {
-      // B: Bs[n][k] = W[n0 + n][k0 + k] (a row of W per output, read as it lies)
-      const int n = tid >> 2, kq = (tid & 3) * 16;
-      u4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
-      if (n0 + n < O && k0 + kq < K) {
-        const float* src = W + (size_t)(n0 + n) * K + k0 + kq;
-        const float4 x0 = *reinterpret_cast<const float4*>(src);
-        const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-        const float4 x2 = *reinterpret_cast<const float4*>(src + 8);
-        const float4 x3 = *reinterpret_cast<const float4*>(src + 12);
-        w0 = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
-        w1 = u4{pack2(x2.x, x2.y), pack2(x2.z, x2.w), pack2(x3.x, x3.y), pack2(x3.z, x3.w)};
-      }
-      *reinterpret_cast<u4*>(Bs + n * PB + kq) = w0;
-      *reinterpret_cast<u4*>(Bs + n * PB + kq + 8) = w1;
-    } else {
-      // B: Bs[o][n] = W[k0 + o][n0 + n], rows of W as they lie (four columns per 16-byte load),
-      // read transposed by tr_operand; O and K are multiples of 4
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = tid + 256 * q, o = p >> 4, c4 = (p & 15) * 4;
-        u2w w = {0u, 0u};
-        if (k0 + o < O && n0 + c4 < K) {
-          const float4 x = *reinterpret_cast<const float4*>(W + (size_t)(k0 + o) * K + n0 + c4);
-          w = u2w{pack2(x.x, x.y), pack2(x.z, x.w)};
-        }
-        *reinterpret_cast<u2w*>(Bs + o * PB + c4) = w;
-      }
+    for (int q = 0; q < NA; ++q) {
+      const int p = tid + 256 * q;
+      *reinterpret_cast<u4*>(As + (p >> 3) * PA + (p & 7) * 8) = va[q];
     }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int p = tid + 256 * q;
+      const u2w w = u2w{pack2(vw[q].x, vw[q].y), pack2(vw[q].z, vw[q].w)};
+      if constexpr (KIND == GEN_FWD) *reinterpret_cast<u2w*>(Bs + (p >> 4) * PA + (p & 15) * 4) = w;
+      else *reinterpret_cast<u2w*>(Bs + (p / (T / 4)) * PT + (p % (T / 4)) * 4) = w;
+    }
+    if (k0 + KC < ktot) fetch(k0 + KC);
     __syncthreads();
 #pragma unroll
     for (int kc = 0; kc < KC / 16; ++kc) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (wm * 32 + m32) * PB + kc * 16 + kh * 8);
-      bf16x8 bv;
-      if constexpr (KIND == GEN_FWD)
-        bv = *reinterpret_cast<const bf16x8*>(Bs + (wn * 32 + m32) * PB + kc * 16 + kh * 8);
-      else
-        bv = tr_operand<PB>(Bs, 16 * kc, 32 * wn, lane);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+      bf16x8 av[NS], bv[NS];
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi)
+        av[mi] = *reinterpret_cast<const bf16x8*>(As + (wm * WT + mi * 32 + m32) * PA + kc * 16 + kh * 8);
+#pragma unroll
+      for (int ni = 0; ni < NS; ++ni) {
+        if constexpr (KIND == GEN_FWD)
+          bv[ni] = *reinterpret_cast<const bf16x8*>(Bs + (wn * WT + ni * 32 + m32) * PA + kc * 16 + kh * 8);
+        else
+          bv[ni] = tr_operand<PT>(Bs, 16 * kc, wn * WT + ni * 32, lane);
+      }
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NS; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
     }
   }
 
-  // epilogue: element 4 jj + i of this lane is D[wm 32 + 8 jj + 4 kh + i][wn 32 + m32]
-  const int col = n0 + wn * 32 + m32;
-  if constexpr (KIND == GEN_FWD) {
-    if (col >= O) return;
-    const float b = W[(size_t)O * K + col];
+  // epilogue: element 4 jj + i of a tile is D[row 8 jj + 4 kh + i][column m32] of that tile
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-      if (r >= nrows) continue;
-      const int64_t row = r0 + r;
-      const float y = acc[i] + b;
-      if (head) {
-        g.z[row * kOut + col] = y;
-      } else {
-        const float h = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
-        (g.act + (int64_t)(l + 1) * g.layer_elems)[row * ld + col] = (uint16_t)(pack2(h, 0.f) & 0xffffu);
-      }
-    }
-  } else {
-    if (col >= K) return;
-    uint16_t* din = gen_delta(g, 4 - l);  // delta at layer l - 1's outputs
-    // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive. All
-    // sixteen loads go out before the first store (rows past the tile read its last row instead)
-    uint16_t hv[16];
+  for (int ni = 0; ni < NS; ++ni) {
+    const int col = n0 + wn * WT + ni * 32 + m32;
+    if constexpr (KIND == GEN_FWD) {
+      if (col >= O) continue;
+      const float b = W[(size_t)O * K + col];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = min(wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3), nrows - 1);
-      hv[i] = act_l[(r0 + r) * ld + col];
-    }
+      for (int mi = 0; mi < NS; ++mi)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-      if (r >= nrows) continue;
-      din[(r0 + r) * ld + col] = hv[i] != 0 ? (uint16_t)(pack2(acc[i], 0.f) & 0xffffu) : (uint16_t)0;
+        for (int i = 0; i < 16; ++i) {
+          const int r = wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+          if (r >= nrows) continue;
+          const int64_t row = r0 + r;
+          const float y = acc[mi][ni][i] + b;
+          if (head) {
+            g.z[row * kOut + col] = y;
+          } else {
+            const float h = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
+            (g.act + (int64_t)(l + 1) * g.layer_elems)[row * ld + col] = (uint16_t)(pack2(h, 0.f) & 0xffffu);
+          }
+        }
+    } else {
+      if (col >= K) continue;
+      uint16_t* din = gen_delta(g, 4 - l);  // delta at layer l - 1's outputs
+      // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive. The
+      // column's loads all go out before the first store (rows past the block read its last row)
+      uint16_t hv[NS][16];
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = min(wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3), nrows - 1);
+          hv[mi][i] = act_l[(r0 + r) * ld + col];
+        }
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+          if (r >= nrows) continue;
+          din[(r0 + r) * ld + col] = hv[mi][i] != 0 ? (uint16_t)(pack2(acc[mi][ni][i], 0.f) & 0xffffu) : (uint16_t)0;
+        }
     }
   }
 }
@@ -3091,16 +3160,21 @@ __device__ __forceinline__ bool gen_object_rows(const GenArgs& g, const StepArgs
 
 // Weight gradient of a hidden layer of more than 32 outputs: dW_l[o][i] = sum over the object's
 // rows r of delta_l[r][o] h_l[r][i], and the bias gradient sum_r delta_l[r][o] (the deltas as the
-// products see them, BF16). A workgroup computes the 64 x 64 block (outputs m0.., inputs n0..) of
-// one object, each wave a 32 x 32 quarter, over the object's rows in chunks of 64 taken in row
-// order. A chunk's rows are staged as they lie in memory (16-byte loads; the next chunk's loads are
-// in flight while the current chunk's products run) and the operands are read transposed; rows
-// past the object's end are staged as zeros.
+// products see them, BF16). A workgroup computes the T x T block (outputs m0.., inputs n0..) of
+// one object (T = 64 or 128), each wave a T/2 x T/2 quarter, over the object's rows in chunks of
+// 64 taken in row order. A chunk's rows are staged as they lie in memory (16-byte loads; the next
+// chunk's loads are in flight while the current chunk's products run) and the operands are read
+// transposed; rows past the object's end are staged as zeros.
+template <int T>
 __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
+  static_assert(T == 64 || T == 128, "block sizes");
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  constexpr int R = 64, P = 72;  // rows per chunk; LDS pitch: 64 columns + 8 (elements)
+  constexpr int R = 64, P = T + T / 8;      // rows per chunk; LDS pitch (elements)
+  constexpr int WT = T / 2, NS = WT / 32;   // wave tile, 32 x 32 MFMA tiles per dimension
+  constexpr int CPR = T / 8;                // 16-byte pieces per staged row
+  constexpr int NP = R * CPR / 256;         // pieces per thread and operand
   __shared__ __attribute__((aligned(16))) uint16_t As[R * P];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[R * P];
   const int H = g.H;
@@ -3111,19 +3185,20 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
   if (l >= kLayers || O <= 32 || !gen_object_rows(g, a, blockIdx.x, ob)) return;
   const int64_t ld = g.ld;
   const int nrows = ob.nrows;
-  const int nbi = (K + 63) / 64;
-  const int m0 = (blockIdx.y / nbi) * 64, n0 = (blockIdx.y % nbi) * 64;
-  // this thread's two 16-byte pieces of a chunk: rows prow and prow + 32, columns c8 .. c8 + 7
-  const int prow = tid >> 3, c8 = (tid & 7) * 8;
+  const int nbi = (K + T - 1) / T;
+  const int m0 = (blockIdx.y / nbi) * T, n0 = (blockIdx.y % nbi) * T;
+  // this thread's pieces of a chunk: p = tid + 256 q, row p / CPR, columns 8 (p mod CPR) .. + 7,
+  // the same columns in every chunk
+  const int c8 = (tid % CPR) * 8;
   const uint16_t* dsrc = gen_delta(g, 3 - l) + ob.r0 * ld + m0 + c8;
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0 + c8;
   const bool aok = m0 + c8 < O, bok = n0 + c8 < K;  // O and K are multiples of 8
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  u4 va[2], vb[2];
+  u4 va[NP], vb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int r = k0 + prow + 32 * q;
+    for (int q = 0; q < NP; ++q) {
+      const int r = k0 + (tid + 256 * q) / CPR;
       va[q] = u4{0u, 0u, 0u, 0u};
       vb[q] = u4{0u, 0u, 0u, 0u};
       if (r < nrows) {
@@ -3132,52 +3207,76 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
       }
     }
   };
-  f32x16 acc;
+  f32x16 acc[NS][NS];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  // bias gradient (first column block, the waves of columns 0..31): this lane's rows of output
-  // m0 + 32 wm + m32
+  for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NS; ++ni)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[mi][ni][i] = 0.f;
+  // bias gradient (first column block, the waves of its first half): this lane's rows of
+  // outputs m0 + wm WT + 32 mi + m32
   const bool bias = (n0 == 0 && wn == 0);
-  float db = 0.f;
+  float db[NS];
+#pragma unroll
+  for (int mi = 0; mi < NS; ++mi) db[mi] = 0.f;
   fetch(0);
   for (int k0 = 0; k0 < nrows; k0 += R) {
     __syncthreads();  // the previous chunk's operands have been read
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      *reinterpret_cast<u4*>(As + (prow + 32 * q) * P + c8) = va[q];
-      *reinterpret_cast<u4*>(Bs + (prow + 32 * q) * P + c8) = vb[q];
+    for (int q = 0; q < NP; ++q) {
+      const int row = (tid + 256 * q) / CPR;
+      *reinterpret_cast<u4*>(As + row * P + c8) = va[q];
+      *reinterpret_cast<u4*>(Bs + row * P + c8) = vb[q];
     }
     if (k0 + R < nrows) fetch(k0 + R);
     __syncthreads();
 #pragma unroll
     for (int kc = 0; kc < R / 16; ++kc) {
-      const bf16x8 av = tr_operand<P>(As, 16 * kc, 32 * wm, lane);
-      const bf16x8 bv = tr_operand<P>(Bs, 16 * kc, 32 * wn, lane);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-      if (bias) db = operand_sum(av, db);
+      bf16x8 av[NS], bv[NS];
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi) av[mi] = tr_operand<P>(As, 16 * kc, wm * WT + 32 * mi, lane);
+#pragma unroll
+      for (int ni = 0; ni < NS; ++ni) bv[ni] = tr_operand<P>(Bs, 16 * kc, wn * WT + 32 * ni, lane);
+#pragma unroll
+      for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NS; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+      if (bias) {
+#pragma unroll
+        for (int mi = 0; mi < NS; ++mi) db[mi] = operand_sum(av[mi], db[mi]);
+      }
     }
   }
   const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
   float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
   int bad = 0;
-  const int col = n0 + wn * 32 + m32;
-  if (col < K) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int o = m0 + wm * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-      if (o >= O) continue;
-      const float v = acc[i] * inv;
-      bad |= partial_bad(v);
-      dst[(size_t)o * K + col] = v;
-    }
+  for (int ni = 0; ni < NS; ++ni) {
+    const int col = n0 + wn * WT + ni * 32 + m32;
+    if (col >= K) continue;
+#pragma unroll
+    for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int o = m0 + wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+        if (o >= O) continue;
+        const float v = acc[mi][ni][i] * inv;
+        bad |= partial_bad(v);
+        dst[(size_t)o * K + col] = v;
+      }
   }
   if (bias) {
-    const float other = __shfl(db, lane + 32);  // the output's other eight rows of each step
-    const int o = m0 + wm * 32 + m32;
-    if (kh == 0 && o < O) {
-      const float v = (db + other) * inv;
-      bad |= partial_bad(v);
-      dst[(size_t)O * K + o] = v;
+#pragma unroll
+    for (int mi = 0; mi < NS; ++mi) {
+      const float other = __shfl(db[mi], lane + 32);  // the output's other eight rows of each step
+      const int o = m0 + wm * WT + mi * 32 + m32;
+      if (kh == 0 && o < O) {
+        const float v = (db[mi] + other) * inv;
+        bad |= partial_bad(v);
+        dst[(size_t)O * K + o] = v;
+      }
     }
   }
   if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
@@ -3386,21 +3485,29 @@ __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
   a.tile_loss[ts] = s;
 }
 
-hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream_t s) {
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s) {
   if (tiles_bound <= 0 || g.a.n_objects <= 0) return hipSuccess;
-  if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots) return hipErrorInvalidValue;
+  if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots || blocks_bound <= 0) return hipErrorInvalidValue;
   // k_gen_dw_small stages a narrow hidden layer's deltas in 8-column runs, 1, 2 or 4 per row
   if (g.H <= 32 && g.H != 8 && g.H != 16 && g.H != 32) return hipErrorInvalidValue;
   const bool train = (mode == MODE_TRAIN);
   const int H = g.H;
   const int wave_blocks = (tiles_bound + 3) / 4;
-  auto blocks64 = [](int n) { return (n + 63) / 64; };
+  auto blocks = [](int n, int t) { return (n + t - 1) / t; };
+  // a product whose output columns number at least 128 takes 128 x 128 blocks over 128-row blocks;
+  // narrower ones 64 x 64 blocks over the row tiles
+  auto fwd_dx = [&](int kind, int ncols, int l) {
+    if (ncols >= 128) {
+      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 128>), dim3(blocks_bound, blocks(ncols, 128)), dim3(256), 0, s, g, l);
+      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 128>), dim3(blocks_bound, blocks(ncols, 128)), dim3(256), 0, s, g, l);
+    } else {
+      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 64>), dim3(tiles_bound, blocks(ncols, 64)), dim3(256), 0, s, g, l);
+      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 64>), dim3(tiles_bound, blocks(ncols, 64)), dim3(256), 0, s, g, l);
+    }
+  };
   hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
   hipLaunchKernelGGL(k_gen_encode, dim3(wave_blocks), dim3(256), 0, s, g);
-  for (int l = 0; l <= kLayers; ++l) {
-    const int O = (l == kLayers) ? kOut : H;
-    hipLaunchKernelGGL(k_gen_gemm<GEN_FWD>, dim3(tiles_bound, blocks64(O)), dim3(256), 0, s, g, l);
-  }
+  for (int l = 0; l <= kLayers; ++l) fwd_dx(GEN_FWD, (l == kLayers) ? kOut : H, l);
   if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
   else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
   hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
@@ -3408,11 +3515,12 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, hipStream
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
       if (O <= 32)
-        hipLaunchKernelGGL(k_gen_dw_small, dim3(g.a.n_objects, (K + 31) / 32), dim3(256), 0, s, g, l);
+        hipLaunchKernelGGL(k_gen_dw_small, dim3(g.a.n_objects, blocks(K, 32)), dim3(256), 0, s, g, l);
+      else if (O >= 128 && K >= 128)
+        hipLaunchKernelGGL(k_gen_dw<128>, dim3(g.a.n_objects, blocks(O, 128) * blocks(K, 128)), dim3(256), 0, s, g, l);
       else
-        hipLaunchKernelGGL(k_gen_dw, dim3(g.a.n_objects, blocks64(O) * blocks64(K)), dim3(256), 0, s, g, l);
-      if (l > 0)
-        hipLaunchKernelGGL(k_gen_gemm<GEN_DX>, dim3(tiles_bound, blocks64(K)), dim3(256), 0, s, g, l);
+        hipLaunchKernelGGL(k_gen_dw<64>, dim3(g.a.n_objects, blocks(O, 64) * blocks(K, 64)), dim3(256), 0, s, g, l);
+      if (l > 0) fwd_dx(GEN_DX, K, l);
     }
   }
   return hipGetLastError();
