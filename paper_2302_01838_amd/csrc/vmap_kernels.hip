@@ -111,6 +111,20 @@ __device__ __forceinline__ int first_tile_of_block(int n_tiles) {
   return start + b / kXcds;
 }
 
+// Logical index of this workgroup in a two-dimensional grid, x fastest in the result, such that
+// each XCD (workgroups are dealt to the eight XCDs in turn by linear index) takes one contiguous
+// range of logical indices: blocks that share operands (the same rows or the same object) then
+// share one L2.
+__device__ __forceinline__ int xcd_grouped_index() {
+  constexpr int kXcds = 8;
+  const int n = (int)(gridDim.x * gridDim.y);
+  const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int x = b % kXcds;
+  int start = 0;
+  for (int y = 0; y < x; ++y) start += (n - y + kXcds - 1) / kXcds;  // workgroups of XCD y
+  return start + b / kXcds;
+}
+
 // Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
 // division costs a dozen instructions). exp(-z) overflows to +inf for z < -88, giving 0.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
@@ -2997,8 +3011,12 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   constexpr int WT = T / 2, NS = WT / 32;      // wave tile, 32 x 32 MFMA tiles per dimension
   constexpr int NA = T * KC / 8 / 256;         // A pieces (8 BF16) per thread and chunk
   constexpr int NB = T * KC / 4 / 256;         // W pieces (4 FP32) per thread and chunk
-  __shared__ __attribute__((aligned(16))) uint16_t As[T * PA];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[(KIND == GEN_FWD) ? T * PA : KC * PT];
+  constexpr int PC = T + 8;                    // pitch of the staged result block
+  constexpr int kA = T * PA, kB = (KIND == GEN_FWD) ? T * PA : KC * PT;
+  static_assert(T * PC <= kA + kB, "the result block fits the operand tiles");
+  __shared__ __attribute__((aligned(16))) uint16_t lds[kA + kB];
+  uint16_t* As = lds;
+  uint16_t* Bs = lds + kA;
   const int H = g.H;
   const bool head = (l == kLayers);
   const int K = (l == 0) ? kEnc : H;  // inputs of layer l
@@ -3008,10 +3026,14 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
   const uint16_t* dout = head ? nullptr : gen_delta(g, 3 - l);  // delta at layer l's outputs
+  // logical block: column blocks fastest, so that an XCD's consecutive blocks share rows of A
+  // and an object's W
+  const int lb = xcd_grouped_index();
+  const int bx = lb / (int)gridDim.y, by = lb % (int)gridDim.y;
   int k, nrows;
   int64_t r0;
-  if (!gen_rows<T>(g, a, blockIdx.x, k, r0, nrows)) return;
-  const int n0 = blockIdx.y * T;
+  if (!gen_rows<T>(g, a, bx, k, r0, nrows)) return;
+  const int n0 = by * T;
   const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
   const int ktot = (KIND == GEN_FWD) ? K : O;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -3094,10 +3116,10 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   }
 
   // epilogue: element 4 jj + i of a tile is D[row 8 jj + 4 kh + i][column m32] of that tile
+  if (KIND == GEN_FWD && head) {  // the output layer's pre-activations, FP32 [rows][4]
 #pragma unroll
-  for (int ni = 0; ni < NS; ++ni) {
-    const int col = n0 + wn * WT + ni * 32 + m32;
-    if constexpr (KIND == GEN_FWD) {
+    for (int ni = 0; ni < NS; ++ni) {
+      const int col = n0 + wn * WT + ni * 32 + m32;
       if (col >= O) continue;
       const float b = W[(size_t)O * K + col];
 #pragma unroll
@@ -3105,38 +3127,53 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int r = wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-          if (r >= nrows) continue;
-          const int64_t row = r0 + r;
-          const float y = acc[mi][ni][i] + b;
-          if (head) {
-            g.z[row * kOut + col] = y;
-          } else {
-            const float h = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
-            (g.act + (int64_t)(l + 1) * g.layer_elems)[row * ld + col] = (uint16_t)(pack2(h, 0.f) & 0xffffu);
-          }
-        }
-    } else {
-      if (col >= K) continue;
-      uint16_t* din = gen_delta(g, 4 - l);  // delta at layer l - 1's outputs
-      // ReLU' of layer l - 1: its BF16 output h_l is +0 exactly where the unit is inactive. The
-      // column's loads all go out before the first store (rows past the block read its last row)
-      uint16_t hv[NS][16];
-#pragma unroll
-      for (int mi = 0; mi < NS; ++mi)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = min(wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3), nrows - 1);
-          hv[mi][i] = act_l[(r0 + r) * ld + col];
-        }
-#pragma unroll
-      for (int mi = 0; mi < NS; ++mi)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-          if (r >= nrows) continue;
-          din[(r0 + r) * ld + col] = hv[mi][i] != 0 ? (uint16_t)(pack2(acc[mi][ni][i], 0.f) & 0xffffu) : (uint16_t)0;
+          if (r < nrows) g.z[(r0 + r) * kOut + col] = acc[mi][ni][i] + b;
         }
     }
+    return;
+  }
+  // Hidden outputs (forward: ReLU(D + b); input gradient: D) rounded to BF16 into a T x T block in
+  // LDS, then written as rows, 16 bytes at a time; the input gradient multiplies by ReLU' of layer
+  // l - 1 (its BF16 output h_l is +0 exactly where the unit is inactive), read as rows too.
+  __syncthreads();  // every wave is done with the operand tiles
+  uint16_t* Cs = lds;
+  const int ncols = (KIND == GEN_FWD) ? O : K;
+#pragma unroll
+  for (int ni = 0; ni < NS; ++ni) {
+    const int cl = wn * WT + ni * 32 + m32;
+    float b = 0.f;
+    if constexpr (KIND == GEN_FWD) b = (n0 + cl < O) ? W[(size_t)O * K + n0 + cl] : 0.f;
+#pragma unroll
+    for (int mi = 0; mi < NS; ++mi)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rl = wm * WT + mi * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+        float y = acc[mi][ni][i];
+        if constexpr (KIND == GEN_FWD) {
+          y += b;
+          y = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
+        }
+        Cs[rl * PC + cl] = (uint16_t)(pack2(y, 0.f) & 0xffffu);
+      }
+  }
+  __syncthreads();
+  uint16_t* dst = (KIND == GEN_FWD) ? g.act + (int64_t)(l + 1) * g.layer_elems : gen_delta(g, 4 - l);
+  constexpr int CPR = T / 8;  // 16-byte pieces per row
+#pragma unroll
+  for (int q = 0; q < T * CPR / 256; ++q) {
+    const int p = tid + 256 * q, r = p / CPR, c = (p % CPR) * 8;
+    if (r >= nrows || n0 + c >= ncols) continue;  // ncols is a multiple of 8
+    u4 v = *reinterpret_cast<const u4*>(Cs + r * PC + c);
+    const int64_t off = (r0 + r) * ld + n0 + c;
+    if constexpr (KIND == GEN_DX) {
+      const u4 h = *reinterpret_cast<const u4*>(act_l + off);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const unsigned int lo = (h[e] & 0xffffu) ? 0xffffu : 0u, hi = (h[e] >> 16) ? 0xffff0000u : 0u;
+        v[e] &= lo | hi;
+      }
+    }
+    *reinterpret_cast<u4*>(dst + off) = v;
   }
 }
 
@@ -3181,12 +3218,15 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
   const int K = (l == 0) ? kEnc : H, O = H;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
+  // logical block: an object's blocks consecutive, so that an XCD works on few objects' rows
+  const int lb = xcd_grouped_index();
+  const int bj = lb / (int)gridDim.y, by = lb % (int)gridDim.y;
   GenObj ob;
-  if (l >= kLayers || O <= 32 || !gen_object_rows(g, a, blockIdx.x, ob)) return;
+  if (l >= kLayers || O <= 32 || !gen_object_rows(g, a, bj, ob)) return;
   const int64_t ld = g.ld;
   const int nrows = ob.nrows;
   const int nbi = (K + T - 1) / T;
-  const int m0 = (blockIdx.y / nbi) * T, n0 = (blockIdx.y % nbi) * T;
+  const int m0 = (by / nbi) * T, n0 = (by % nbi) * T;
   // this thread's pieces of a chunk: p = tid + 256 q, row p / CPR, columns 8 (p mod CPR) .. + 7,
   // the same columns in every chunk
   const int c8 = (tid % CPR) * 8;
