@@ -2195,7 +2195,6 @@ __global__ void __launch_bounds__(256) k_adam(const OptArgs a_in) {
 // data); the validity checks only decide what is stored. Thread 0 works out the Adam
 // coefficients while the loads are in flight. The grid has one row of workgroups per batch object
 // and a last row whose first workgroup updates the loss scaler (its own chain of loads).
-template <int V>
 __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   OptArgs a = a_in;
   read_batch(a);
@@ -2214,41 +2213,14 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
   const int kc = in_range ? k : 0;  // loads of an id out of range are discarded
   const ObjDesc& d = a.desc[kc];
   const int registered = d.registered, n_params = d.n_params, hidden = d.hidden;
-  const int p = (blockIdx.x * blockDim.x + threadIdx.x) * V;  // p_stride is a multiple of V
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t i = (size_t)kc * a.p_stride + p;
-  float th[V], m[V], v[V], g[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) th[e] = m[e] = v[e] = g[e] = 0.f;
+  float th = 0.f, m = 0.f, v = 0.f, g = 0.f;
   if (p < a.p_stride) {
-    if constexpr (V == 1) {
-      th[0] = a.theta[i];
-      m[0] = a.m[i];
-      v[0] = a.v[i];
-      g[0] = tile_sum(a.partial, a.p_stride, t0, t1, p);
-    } else {
-      const float4 x = *reinterpret_cast<const float4*>(a.theta + i);
-      const float4 y = *reinterpret_cast<const float4*>(a.m + i);
-      const float4 z = *reinterpret_cast<const float4*>(a.v + i);
-      th[0] = x.x, th[1] = x.y, th[2] = x.z, th[3] = x.w;
-      m[0] = y.x, m[1] = y.y, m[2] = y.z, m[3] = y.w;
-      v[0] = z.x, v[1] = z.y, v[2] = z.z, v[3] = z.w;
-      // the tiles' partials at p .. p + 3, each summed in tile order from zero as tile_sum does
-      for (int tt = t0; tt < t1; tt += 8) {
-        float4 q[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          q[u] = (tt + u < t1) ? *reinterpret_cast<const float4*>(a.partial + (size_t)(tt + u) * a.p_stride + p)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (tt + u < t1) {
-            g[0] += q[u].x;
-            g[1] += q[u].y;
-            g[2] += q[u].z;
-            g[3] += q[u].w;
-          }
-      }
-    }
+    th = a.theta[i];
+    m = a.m[i];
+    v = a.v[i];
+    g = tile_sum(a.partial, a.p_stride, t0, t1, p);
   }
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   float loss = 0.f;
@@ -2264,19 +2236,105 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     return;
   }
   const AdamCoef c = adam_coef_load(a, sh);
+  if (p < n_params) {
+    a.grad[i] = g;
+    if (isfinite(g)) {
+      adam_elem(c, g, th, m, v);
+      a.theta[i] = th;
+      a.m[i] = m;
+      a.v[i] = v;
+    } else {
+      atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
+    }
+    update_image(a, k, hidden, p, th);
+  }
+  if (lead) a.desc[k].step = t;
+}
+
+// k_reduce_adam for objects of many parameters: a row of workgroups per batch object (its width
+// capped by the launch) walks the object's parameters four at a time per thread, so that the
+// object's descriptor, tile range, skip test and Adam coefficients are settled once per workgroup
+// rather than once per 256 parameters. Per parameter the same arithmetic in the same order:
+// the tiles' partials summed in tile order from zero, then one Adam update.
+__global__ void __launch_bounds__(256) k_reduce_adam_wide(const OptArgs a_in) {
+  OptArgs a = a_in;
+  read_batch(a);
+  const int j = blockIdx.y;
+  if (j == (int)gridDim.y - 1) {
+    if (blockIdx.x == 0) scaler_update(a);
+    return;
+  }
+  const int k = a.ids[j];
+  const TileRange tr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  const int t0 = tr.t0, t1 = tr.t1;
+  const int r0 = a.offs[j], r1 = a.offs[j + 1];
+  const int t = a.t_next[j];
+  const int batch_ok = a.scaler->batch_ok;
+  const bool in_range = k >= 0 && k < a.max_objects;
+  const int kc = in_range ? k : 0;
+  const ObjDesc& d = a.desc[kc];
+  const int registered = d.registered, n_params = d.n_params, hidden = d.hidden;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  float loss = 0.f;
+  if (lead && a.loss_out) loss = tile_sum(a.tile_loss, 1, t0, t1, 0);
+  __shared__ float sh[2];
+  if (threadIdx.x == 0) adam_coef_store(a, t, sh);
+  const bool valid = in_range && registered != 0 && batch_ok;
+  if (lead && a.loss_out) a.loss_out[j] = valid ? loss : 0.f;
+  if (!valid || r1 <= r0) return;
+  if (object_bad(a, j, k)) {
+    if (a.tile_bad && lead) a.flags[k] = 1;
+    return;
+  }
+  const AdamCoef c = adam_coef_load(a, sh);
+  const size_t base = (size_t)k * a.p_stride;
+  // p_stride is a multiple of 4, so p + 3 < p_stride for every p taken
+  for (int p = (blockIdx.x * blockDim.x + threadIdx.x) * 4; p < n_params; p += gridDim.x * blockDim.x * 4) {
+    const size_t i = base + p;
+    const float4 x = *reinterpret_cast<const float4*>(a.theta + i);
+    const float4 y = *reinterpret_cast<const float4*>(a.m + i);
+    const float4 z = *reinterpret_cast<const float4*>(a.v + i);
+    float th[4] = {x.x, x.y, x.z, x.w}, m[4] = {y.x, y.y, y.z, y.w}, v[4] = {z.x, z.y, z.z, z.w};
+    float g[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int tt = t0; tt < t1; tt += 8) {
+      float4 q[8];
 #pragma unroll
-  for (int e = 0; e < V; ++e) {
-    if (p + e < n_params) {
-      a.grad[i + e] = g[e];
-      if (isfinite(g[e])) {
-        adam_elem(c, g[e], th[e], m[e], v[e]);
-        a.theta[i + e] = th[e];
-        a.m[i + e] = m[e];
-        a.v[i + e] = v[e];
-      } else {
-        atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
+      for (int u = 0; u < 8; ++u)
+        q[u] = (tt + u < t1) ? *reinterpret_cast<const float4*>(a.partial + (size_t)(tt + u) * a.p_stride + p)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (tt + u < t1) {
+          g[0] += q[u].x;
+          g[1] += q[u].y;
+          g[2] += q[u].z;
+          g[3] += q[u].w;
+        }
+    }
+    if (p + 3 < n_params && isfinite(g[0]) && isfinite(g[1]) && isfinite(g[2]) && isfinite(g[3])) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) adam_elem(c, g[e], th[e], m[e], v[e]);
+      *reinterpret_cast<float4*>(a.grad + i) = make_float4(g[0], g[1], g[2], g[3]);
+      *reinterpret_cast<float4*>(a.theta + i) = make_float4(th[0], th[1], th[2], th[3]);
+      *reinterpret_cast<float4*>(a.m + i) = make_float4(m[0], m[1], m[2], m[3]);
+      *reinterpret_cast<float4*>(a.v + i) = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) update_image(a, k, hidden, p + e, th[e]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (p + e >= n_params) continue;
+        a.grad[i + e] = g[e];
+        if (isfinite(g[e])) {
+          adam_elem(c, g[e], th[e], m[e], v[e]);
+          a.theta[i + e] = th[e];
+          a.m[i + e] = m[e];
+          a.v[i + e] = v[e];
+        } else {
+          atomicOr(&a.flags[k], 2);
+        }
+        update_image(a, k, hidden, p + e, th[e]);
       }
-      update_image(a, k, hidden, p + e, th[e]);
     }
   }
   if (lead) a.desc[k].step = t;
@@ -2744,10 +2802,11 @@ hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
   return hipGetLastError();
 }
 
-// Parameter slots per object from which k_reduce_adam takes four parameters per thread (objects of
-// hidden 128 and up: their update streams whole vectors of theta, m, v and the partials; measured
-// 5 % faster on a step with a hidden-128 object). Below, one per thread keeps more workgroups in
-// flight for the few-thousand-parameter objects (four per thread measured 2 % slower at hidden 32).
+// Parameter slots per object from which the optimiser is k_reduce_adam_wide (objects of hidden 128
+// and up: whole vectors of theta, m, v and the partials; four parameters per thread measured 5 %
+// faster on a step with a hidden-128 object). Below, k_reduce_adam's one parameter per thread keeps
+// more workgroups in flight for the few-thousand-parameter objects (four per thread measured 2 %
+// slower at hidden 32).
 constexpr int kReduceWide = 32768;
 
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
@@ -2756,9 +2815,13 @@ hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
   if (kind == OPT_REDUCE) hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, a, 1);
   else if (kind == OPT_LOSS) hipLaunchKernelGGL(k_reduce, dim3(1, a.n_objects), dim3(256), 0, s, a, 0);
   else if (kind == OPT_ADAM) hipLaunchKernelGGL(k_adam, grid, dim3(256), 0, s, a);
-  else if (a.p_stride >= kReduceWide && a.p_stride % 4 == 0)  // four parameters per thread
-    hipLaunchKernelGGL(k_reduce_adam<4>, dim3((a.p_stride / 4 + 255) / 256, a.n_objects + 1), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_reduce_adam<1>, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
+  else if (a.p_stride >= kReduceWide && a.p_stride % 4 == 0) {
+    // four parameters per thread, about 4096 workgroups over the batch
+    const int per_object = std::max(1, std::min((a.p_stride / 4 + 255) / 256, (4096 + a.n_objects - 1) / a.n_objects));
+    hipLaunchKernelGGL(k_reduce_adam_wide, dim3(per_object, a.n_objects + 1), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_reduce_adam, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
