@@ -391,15 +391,15 @@ enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
 // every kGenBlockRows rows regardless of ray boundaries (rows are independent in those products).
 constexpr int kGenBlockRows = 128;
 // LDS of the product kernels: k_gen_gemm and k_gen_dw stage two BF16 operand tiles of up to
-// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small four waves' pairs of
-// 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16 accumulators and 8 bias
-// parts per lane).
+// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small up to sixteen waves'
+// pairs of 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16 accumulators
+// and 8 bias parts per lane).
 constexpr int kGenKChunk = 64;
 constexpr int kGenPitch = 36;
 constexpr int kGenTileLds = 2 * 128 * (kGenKChunk + 8) * 2;
-constexpr int kGenSmallLds = (4 * 2 * 32 * kGenPitch * 2 > 4 * (4 * 16 * 64 + 4 * 64 * 8))
-                                 ? 4 * 2 * 32 * kGenPitch * 2
-                                 : 4 * (4 * 16 * 64 + 4 * 64 * 8);
+constexpr int kGenSmallLds = (16 * 2 * 32 * kGenPitch * 2 > 4 * (16 * 16 * 64 + 16 * 64 * 8))
+                                 ? 16 * 2 * 32 * kGenPitch * 2
+                                 : 4 * (16 * 16 * 64 + 16 * 64 * 8);
 constexpr int kGenLdsBytes = kGenTileLds > kGenSmallLds ? kGenTileLds : kGenSmallLds;
 
 struct QueryArgs {

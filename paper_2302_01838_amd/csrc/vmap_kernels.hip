@@ -3387,20 +3387,22 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
 
 // Weight gradient of a layer with at most 32 outputs (every layer at hidden 16; the output layer
 // at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) of one object, and
-// its four waves take the object's rows in 32-row chunks in turn (chunk c to wave c mod 4), each
+// its NW waves take the object's rows in 32-row chunks in turn (chunk c to wave c mod NW), each
 // in its own LDS tiles, staged as the rows lie in memory (16-byte loads, the wave's next chunk in
 // flight during the current chunk's products) and read transposed. The waves' sums are added in
 // wave order, so the result does not depend on the grid. Bias gradient: the deltas as the products
 // see them (BF16), or the output layer's FP32 seed unrounded, summed per lane over its staged rows
-// and then over lanes and waves in a fixed order.
-__global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l) {
+// and then over lanes and waves in a fixed order. NW = 16 when the launch has few workgroups (a
+// wave's chain of dependent chunks is then a sixteenth of the object's rows), else 4.
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, int l) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
   constexpr int P = kGenPitch;                   // 32 columns + 4 (elements)
   constexpr int kWaveTile = 2 * 32 * P;          // one wave's A and B tiles (uint16 elements)
-  constexpr int kRed = 4 * 16 * 64 + 4 * 64 * 8;  // floats of the final sums: accumulators, bias parts
-  __shared__ __attribute__((aligned(16))) uint16_t lds[(4 * kWaveTile > 2 * kRed) ? 4 * kWaveTile : 2 * kRed];
+  constexpr int kRed = NW * 16 * 64 + NW * 64 * 8;  // floats of the final sums: accumulators, bias parts
+  __shared__ __attribute__((aligned(16))) uint16_t lds[(NW * kWaveTile > 2 * kRed) ? NW * kWaveTile : 2 * kRed];
   const int H = g.H;
   const bool head = (l == kLayers);
   const int K = (l == 0) ? kEnc : H;
@@ -3453,7 +3455,7 @@ __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l)
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   float dbv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this lane's columns' bias parts
   if (wave * 32 < nrows) fetch(wave);
-  for (int c = wave; c * 32 < nrows; c += 4) {
+  for (int c = wave; c * 32 < nrows; c += NW) {
     wave_lds_sync();  // this wave's previous chunk has been read
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -3484,7 +3486,7 @@ __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l)
         }
       }
     }
-    if ((c + 4) * 32 < nrows) fetch(c + 4);
+    if ((c + NW) * 32 < nrows) fetch(c + NW);
     wave_lds_sync();
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) {
@@ -3493,44 +3495,47 @@ __global__ void __launch_bounds__(256) k_gen_dw_small(const GenArgs g_in, int l)
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
   }
-  // the four waves' sums, added in wave order
-  __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);  // [4 waves][16][64], then [4 waves][64 lanes][8]
-  float* redb = red + 4 * 16 * 64;
+  // Bias parts: a butterfly over the lanes that hold the same columns (lane bits at and above
+  // log2(per); the output layer's seeds sit on lanes 0..31, the others hold zeros), leaving each
+  // wave's sums on lanes 0 .. per - 1, in a fixed order.
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    if (off < per) break;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dbv[e] += __shfl_xor(dbv[e], off);
+  }
+  __syncthreads();  // every wave is done with its tiles
+  float* red = reinterpret_cast<float*>(lds);  // [NW waves][16][64], then [NW waves][32] bias sums
+  float* redb = red + NW * 16 * 64;
 #pragma unroll
   for (int i = 0; i < 16; ++i) red[(wave * 16 + i) * 64 + lane] = acc[i];
+  if (lane < per) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) redb[(wave * 64 + lane) * 8 + e] = dbv[e];
+    for (int e = 0; e < 8; ++e) redb[wave * 32 + 8 * lane + e] = dbv[e];
+  }
   __syncthreads();
+  // element i of the accumulators (output 8 (i / 4) + 4 (lane / 32) + i mod 4, input n0 + lane mod
+  // 32) is summed over the waves in wave order by wave i mod NW
   int bad = 0;
-  if (wave == 0) {
-    const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
-    float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
-    const int m32 = lane & 31, kh = lane >> 5;
-    const int col = n0 + m32;
-    if (col < K) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int o = 8 * (i >> 2) + 4 * kh + (i & 3);
-        if (o >= O) continue;
-        float v = red[i * 64 + lane];
-        for (int w = 1; w < 4; ++w) v += red[(w * 16 + i) * 64 + lane];
-        v *= inv;
-        bad |= partial_bad(v);
-        dst[(size_t)o * K + col] = v;
-      }
-    }
-    if (bias && lane < O) {
-      // output o: lanes whose pieces hold its column (head: lanes 0..31, element o), in order
-      const int o = lane;
-      const int chunk = head ? 0 : (o >> 3), e = head ? o : (o & 7), nl = head ? 32 : 64;
-      float v = 0.f;
-      for (int w = 0; w < 4; ++w)
-        for (int L = chunk; L < nl; L += per) v += redb[(w * 64 + L) * 8 + e];
-      v *= inv;
-      bad |= partial_bad(v);
-      dst[(size_t)O * K + o] = v;
-    }
+  const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
+  float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
+  const int m32 = lane & 31, kh = lane >> 5;
+  const int col = n0 + m32;
+  for (int i = wave; i < 16; i += NW) {
+    const int o = 8 * (i >> 2) + 4 * kh + (i & 3);
+    if (o >= O || col >= K) continue;
+    float v = red[i * 64 + lane];
+    for (int w = 1; w < NW; ++w) v += red[(w * 16 + i) * 64 + lane];
+    v *= inv;
+    bad |= partial_bad(v);
+    dst[(size_t)o * K + col] = v;
+  }
+  if (bias && wave == 0 && lane < O) {
+    float v = 0.f;
+    for (int w = 0; w < NW; ++w) v += redb[w * 32 + lane];  // output o = lane: column 8 (o / 8) + o mod 8
+    v *= inv;
+    bad |= partial_bad(v);
+    dst[(size_t)O * K + lane] = v;
   }
   if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
 }
@@ -3617,8 +3622,11 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   if (train) {
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
-      if (O <= 32)
-        hipLaunchKernelGGL(k_gen_dw_small, dim3(g.a.n_objects, blocks(K, 32)), dim3(256), 0, s, g, l);
+      if (O <= 32) {
+        const dim3 grid(g.a.n_objects, blocks(K, 32));
+        if (grid.x * grid.y <= 256) hipLaunchKernelGGL(k_gen_dw_small<16>, grid, dim3(1024), 0, s, g, l);
+        else hipLaunchKernelGGL(k_gen_dw_small<4>, grid, dim3(256), 0, s, g, l);
+      }
       else if (O >= 128 && K >= 128)
         hipLaunchKernelGGL(k_gen_dw<128>, dim3(g.a.n_objects, blocks(O, 128) * blocks(K, 128)), dim3(256), 0, s, g, l);
       else
