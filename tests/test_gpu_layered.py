@@ -5,8 +5,9 @@ device memory (encoding, one product launch per layer forward, rendering, one la
 and direction backward). Same acceptance as the BF16 tile kernels: renders, losses and
 parameters after one step within 2e-2 of FP64; gradients and Adam moments within 2e-3 of the
 oracle's BF16 mode (same rounding points) and within 2e-2 of FP64 arithmetic whose decisions are
-taken in BF16, on the rays away from a kink. Also: ragged rays and samples per ray, a stack that
-mixes a fused width with a layered one, the autograd split, and the bitwise invariants.
+taken in BF16, on the rays away from a kink. Also: ragged rays and samples per ray, objects whose
+rows end around the 128-row blocks of the wide products, a stack that mixes a fused width with a
+layered one, the autograd split, and the bitwise invariants.
 """
 import dataclasses
 
@@ -75,6 +76,21 @@ def test_layered_ragged_rays(H, S):
     batch = scenes.make_batch(sc, 0, n_rays={0: 1, 1: 7, 2: 64, 3: 33})
     errs, errs16, _, _ = step_errors(objs, states, batch, "bf16", sc.B)
     report(f"layered ragged H={H} S={S}", **errs)
+    check_step(errs, errs16, "bf16")
+
+
+@pytest.mark.parametrize("H,S,rays", [(256, 1, {0: 127, 1: 128, 2: 129, 3: 255}),
+                                      (512, 2, {0: 63, 1: 64, 2: 65, 3: 128})])
+def test_layered_row_block_edges(H, S, rays):
+    """Objects whose rows end just before, at and just after a multiple of 128: the wide products
+    cut an object's rows into 128-row blocks regardless of ray boundaries, so the last block of
+    an object holds 127, 128, 129 (and 126, 130) or 255 rows' remainders."""
+    print(f"[layered] row blocks H={H} S={S} rays={rays}", flush=True)
+    sc = _scene(H, S=S)
+    objs, states = make_pair(sc, "bf16", max_rays=sum(rays.values()) + 64)
+    batch = scenes.make_batch(sc, 0, n_rays=rays)
+    errs, errs16, _, _ = step_errors(objs, states, batch, "bf16", sc.B)
+    report(f"layered row blocks H={H} S={S}", **errs)
     check_step(errs, errs16, "bf16")
 
 
