@@ -149,7 +149,8 @@ WorkLayout work_layout(const vmap_config* c) {
     w.gbs = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
     w.gen_loss = off; off = align256(off + (size_t)w.max_gen_tiles * 4);
     w.gact = off; off = align256(off + (size_t)(kLayers + 1) * layer);
-    w.gdelta = off; off = align256(off + 2 * layer);
+    // deltas: two buffers taken alternately, four at hidden 16 (one per hidden layer)
+    w.gdelta = off; off = align256(off + (c->max_hidden == 16 ? 4 : 2) * layer);
     w.gz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
     w.gdz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
   }
@@ -422,6 +423,7 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       const size_t layer = (size_t)c->wl.gen_rows * (size_t)c->wl.gen_ld;
       g.delta[0] = reinterpret_cast<uint16_t*>(c->work + c->wl.gdelta);
       g.delta[1] = g.delta[0] + layer;
+      g.delta4 = (H == 16 && c->cfg.max_hidden == 16) ? g.delta[0] : nullptr;
       g.z = reinterpret_cast<float*>(c->work + c->wl.gz);
       g.dz = reinterpret_cast<float*>(c->work + c->wl.gdz);
       g.ld = c->wl.gen_ld;

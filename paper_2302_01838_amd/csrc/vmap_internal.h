@@ -384,6 +384,8 @@ struct GenArgs {
   int64_t layer_elems;   // elements per layer of act
   int max_gen_blocks;    // 128-row blocks the block table holds
   int32_t* gbs;          // [n_objects + 1] first 128-row block of each batch object
+  uint16_t* delta4;      // hidden 16: BF16 [4][rows][ld], the deltas at layers 0..3's outputs (all
+                         // kept, so that one launch takes every weight gradient); NULL otherwise
 };
 // Kinds of the layered path's row-block product kernel (the weight gradients have their own).
 enum GenKind { GEN_FWD = 0, GEN_DX = 1 };

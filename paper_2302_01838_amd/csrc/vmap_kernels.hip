@@ -2885,10 +2885,12 @@ __device__ __forceinline__ int gen_object(const int32_t* __restrict__ gts, int n
   return lo;
 }
 
-// Delta buffer i mod 2 (a select: indexing the kernel argument's array by a run-time value would
-// put the whole argument block in per-lane scratch memory).
-__device__ __forceinline__ uint16_t* gen_delta(const GenArgs& g, int i) {
-  return (i & 1) ? g.delta[1] : g.delta[0];
+// Buffer of the deltas at layer m's outputs (m = 0..3): one per layer at hidden 16, else the two
+// buffers alternately (layer m in buffer (3 - m) mod 2). A select: indexing the kernel argument's
+// array by a run-time value would put the whole argument block in per-lane scratch memory.
+__device__ __forceinline__ uint16_t* gen_delta_out(const GenArgs& g, int m) {
+  if (g.delta4) return g.delta4 + (int64_t)m * g.layer_elems;
+  return ((3 - m) & 1) ? g.delta[1] : g.delta[0];
 }
 
 struct GenTile {
@@ -2957,21 +2959,14 @@ __global__ void __launch_bounds__(1024) k_gen_tiles(const GenArgs g_in) {
   }
 }
 
-// Encoding of every sample of a row tile (one wave per tile): normalised point in FP64 rounded
-// once, Gaussian Fourier features (and the integrated encoding's attenuation) as in forward_pass,
-// rounded to BF16 in pairs, into layer 0 of the activations.
-__global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
-  GenArgs g = g_in;
-  read_batch(g.a);
-  const StepArgs& a = g.a;
-  const int lane = threadIdx.x & 63, t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  GenTile tl;
-  if (!gen_tile(g, a, t, tl)) return;
-  const int S = a.S, nslots = (tl.hi - tl.lo) * S;
-  if (lane >= nslots) return;
+// Encoding of sample `slot` of row tile tl: normalised point in FP64 rounded once, Gaussian Fourier
+// features (and the integrated encoding's attenuation) as in forward_pass, rounded to BF16 in
+// pairs: w[0..7] the sines of features (0, 1) .. (14, 15), w[8..15] the cosines.
+__device__ __forceinline__ void gen_encode_row(const StepArgs& a, const GenTile& tl, int slot, unsigned int w[16]) {
   const ObjDesc& d = a.desc[tl.k];
-  const int64_t row = (int64_t)tl.lo * S + lane;
-  const int ray = tl.lo + lane / S;
+  const int S = a.S;
+  const int64_t row = (int64_t)tl.lo * S + slot;
+  const int ray = tl.lo + slot / S;
   const double tt = (double)a.t[row];
   const float* o3 = a.rays_o + 3 * (size_t)ray;
   const float* d3 = a.rays_d + 3 * (size_t)ray;
@@ -2982,7 +2977,6 @@ __global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
   xt[2] = (float)(((double)o3[2] + tt * (double)d3[2] - d.centre[2]) * inv_s);
   xt[3] = a.var ? (float)((double)a.var[row] * inv_s * inv_s) : 0.f;
   const float* Bm = a.B;
-  unsigned int* out = reinterpret_cast<unsigned int*>(g.act + row * g.ld);
 #pragma unroll
   for (int f = 0; f < kFeatures; f += 2) {
     float sv[2], cv[2];
@@ -2999,9 +2993,26 @@ __global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
         cv[u] *= att;
       }
     }
-    out[f / 2] = pack2(sv[0], sv[1]);
-    out[(kFeatures + f) / 2] = pack2(cv[0], cv[1]);
+    w[f / 2] = pack2(sv[0], sv[1]);
+    w[(kFeatures + f) / 2] = pack2(cv[0], cv[1]);
   }
+}
+
+// Encoding of every sample of a row tile (one wave per tile) into layer 0 of the activations.
+__global__ void __launch_bounds__(256) k_gen_encode(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  const int lane = threadIdx.x & 63, t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  GenTile tl;
+  if (!gen_tile(g, a, t, tl)) return;
+  const int S = a.S, nslots = (tl.hi - tl.lo) * S;
+  if (lane >= nslots) return;
+  unsigned int w[16];
+  gen_encode_row(a, tl, lane, w);
+  unsigned int* out = reinterpret_cast<unsigned int*>(g.act + ((int64_t)tl.lo * S + lane) * g.ld);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] = w[i];
 }
 
 // Lane `lane`'s MFMA operand from a row-major BF16 tile T (pitch P elements, a multiple of 4): the
@@ -3088,7 +3099,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
-  const uint16_t* dout = head ? nullptr : gen_delta(g, 3 - l);  // delta at layer l's outputs
+  const uint16_t* dout = head ? nullptr : gen_delta_out(g, l);  // delta at layer l's outputs
   // logical block: column blocks fastest, so that an XCD's consecutive blocks share rows of A
   // and an object's W
   const int lb = xcd_grouped_index();
@@ -3220,7 +3231,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
       }
   }
   __syncthreads();
-  uint16_t* dst = (KIND == GEN_FWD) ? g.act + (int64_t)(l + 1) * g.layer_elems : gen_delta(g, 4 - l);
+  uint16_t* dst = (KIND == GEN_FWD) ? g.act + (int64_t)(l + 1) * g.layer_elems : gen_delta_out(g, l - 1);
   constexpr int CPR = T / 8;  // 16-byte pieces per row
 #pragma unroll
   for (int q = 0; q < T * CPR / 256; ++q) {
@@ -3293,7 +3304,7 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
   // this thread's pieces of a chunk: p = tid + 256 q, row p / CPR, columns 8 (p mod CPR) .. + 7,
   // the same columns in every chunk
   const int c8 = (tid % CPR) * 8;
-  const uint16_t* dsrc = gen_delta(g, 3 - l) + ob.r0 * ld + m0 + c8;
+  const uint16_t* dsrc = gen_delta_out(g, l) + ob.r0 * ld + m0 + c8;
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0 + c8;
   const bool aok = m0 + c8 < O, bok = n0 + c8 < K;  // O and K are multiples of 8
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -3395,9 +3406,10 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
 // and then over lanes and waves in a fixed order. NW = 16 when the launch has few workgroups (a
 // wave's chain of dependent chunks is then a sixteenth of the object's rows), else 4.
 template <int NW>
-__global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, int l) {
+__global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, int l_arg) {
   GenArgs g = g_in;
   read_batch(g.a);
+  const int l = l_arg >= 0 ? l_arg : (int)blockIdx.z;  // l_arg < 0: every layer, one per grid z
   const StepArgs& a = g.a;
   constexpr int P = kGenPitch;                   // 32 columns + 4 (elements)
   constexpr int kWaveTile = 2 * 32 * P;          // one wave's A and B tiles (uint16 elements)
@@ -3426,7 +3438,7 @@ __global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, in
   // row lane. A lane's columns are the same in every chunk.
   const int lp = head ? 0 : (O >= 32 ? 2 : (O >= 16 ? 1 : 0)), per = 1 << lp;  // per = O / 8
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0;
-  const uint16_t* dsrc = head ? nullptr : gen_delta(g, 3 - l) + ob.r0 * ld;
+  const uint16_t* dsrc = head ? nullptr : gen_delta_out(g, l) + ob.r0 * ld;
   const float* zsrc = g.dz + ob.r0 * kOut;
   u4 va[2], vb[2];
   float4 vz;
@@ -3540,6 +3552,188 @@ __global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, in
   if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
 }
 
+// Hidden 16: the forward of one row tile per wave in one launch, the tile's activations kept in
+// LDS between layers: the encoding (gen_encode_row), then the five layers as k_gen_gemm computes
+// them (BF16 operands, W rounded as read, FP32 accumulation in the same K steps, bias, ReLU with
+// NaN kept, BF16 rounding; the output layer's z in FP32). Writes every layer's activations, which
+// the backward reads, and z.
+__global__ void __launch_bounds__(256) k_gen_fwd16(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  constexpr int H = 16, P = kEnc + 8;  // LDS row pitch: 32 features + 8 (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t tiles[4 * 64 * P];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = blockIdx.x * 4 + wave;
+  const int m32 = lane & 31, kh = lane >> 5;
+  GenTile tl;
+  if (!gen_tile(g, a, t, tl)) return;  // uniform over the wave; no workgroup barrier below
+  const int nrows = (tl.hi - tl.lo) * a.S;
+  if (nrows <= 0) return;
+  const int64_t r0 = (int64_t)tl.lo * a.S;
+  const int64_t ld = g.ld;
+  uint16_t* T = tiles + wave * 64 * P;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  {
+    unsigned int w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = 0u;
+    if (lane < nrows) gen_encode_row(a, tl, lane, w);  // rows past the tile: zeros
+    u4* lrow = reinterpret_cast<u4*>(T + lane * P);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lrow[q] = u4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+    if (lane < nrows) {
+      u4* grow = reinterpret_cast<u4*>(g.act + (r0 + lane) * ld);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) grow[q] = u4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+    }
+  }
+  wave_lds_sync();
+  const float* th = a.theta + (size_t)tl.k * a.p_stride;
+#pragma unroll
+  for (int l = 0; l <= kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
+    const float* W = th + layer_param_off(H, l);  // [O][K], then b [O]
+    f32x16 acc[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[rb][i] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < K / 16; ++ks) {
+      // B: output m32 (below O), inputs 16 ks + 8 kh .. + 7 of its row of W
+      u4 wb = {0u, 0u, 0u, 0u};
+      if (m32 < O) {
+        const float4 x0 = *reinterpret_cast<const float4*>(W + m32 * K + 16 * ks + 8 * kh);
+        const float4 x1 = *reinterpret_cast<const float4*>(W + m32 * K + 16 * ks + 8 * kh + 4);
+        wb = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+      }
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, wb);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(T + (32 * rb + m32) * P + 16 * ks + 8 * kh);
+        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[rb], 0, 0, 0);
+      }
+    }
+    wave_lds_sync();  // the layer's inputs have been read
+    const float b = (m32 < O) ? W[O * K + m32] : 0.f;
+    // element 4 jj + i of acc[rb]: row 32 rb + 8 jj + 4 kh + i, output m32
+    if (l < kLayers) {
+      if (m32 < O) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
+            float y = acc[rb][i] + b;
+            y = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
+            T[r * P + m32] = (uint16_t)(pack2(y, 0.f) & 0xffffu);
+          }
+      }
+      wave_lds_sync();
+      if (lane < nrows) {  // h_{l+1}: the row's 16 BF16 (32 bytes)
+        const u4* lrow = reinterpret_cast<const u4*>(T + lane * P);
+        u4* grow = reinterpret_cast<u4*>(g.act + (int64_t)(l + 1) * g.layer_elems + (r0 + lane) * ld);
+        grow[0] = lrow[0];
+        grow[1] = lrow[1];
+      }
+    } else if (m32 < O) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
+          if (r < nrows) g.z[(r0 + r) * kOut + m32] = acc[rb][i] + b;
+        }
+    }
+  }
+}
+
+// Hidden 16: the input-gradient chain of one row tile per wave in one launch, from the output
+// layer's seeds dz down to the deltas at layer 0's outputs, as k_gen_gemm<GEN_DX> computes each
+// (BF16 operands: the deltas, or dz rounded; W rounded as read; FP32 accumulation; BF16 rounding),
+// each masked by ReLU' of the layer below (its BF16 output +0 exactly where the unit is inactive),
+// written to its own delta buffer and kept in LDS as the next product's operand.
+__global__ void __launch_bounds__(256) k_gen_dx16(const GenArgs g_in) {
+  GenArgs g = g_in;
+  read_batch(g.a);
+  const StepArgs& a = g.a;
+  constexpr int H = 16, P = H + 8;  // LDS row pitch (elements)
+  __shared__ __attribute__((aligned(16))) uint16_t tiles[4 * 64 * P];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = blockIdx.x * 4 + wave;
+  const int m32 = lane & 31, kh = lane >> 5;
+  GenTile tl;
+  if (!gen_tile(g, a, t, tl)) return;  // uniform over the wave; no workgroup barrier below
+  const int nrows = (tl.hi - tl.lo) * a.S;
+  if (nrows <= 0) return;
+  const int64_t r0 = (int64_t)tl.lo * a.S;
+  const int64_t ld = g.ld;
+  uint16_t* T = tiles + wave * 64 * P;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const float* th = a.theta + (size_t)tl.k * a.p_stride;
+#pragma unroll
+  for (int l = kLayers; l >= 1; --l) {
+    const int O = (l == kLayers) ? kOut : H;      // outputs of layer l: the K index here
+    const float* W = th + layer_param_off(H, l);  // [O][16]
+    // B: input m32 (below 16), outputs 8 kh .. + 7 (below O): W[o][m32]
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int o = 8 * kh + e;
+      x[e] = (m32 < H && o < O) ? W[o * H + m32] : 0.f;
+    }
+    const bf16x8 bv = __builtin_bit_cast(
+        bf16x8, u4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])});
+    f32x16 acc[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      bf16x8 av;
+      if (l == kLayers) {  // the seeds, FP32 [rows][4], rounded: K index 0..3 on the first half
+        u4 v = {0u, 0u, 0u, 0u};
+        const int r = 32 * rb + m32;
+        if (kh == 0 && r < nrows) {
+          const float4 d4 = *reinterpret_cast<const float4*>(g.dz + (r0 + r) * kOut);
+          v = u4{pack2(d4.x, d4.y), pack2(d4.z, d4.w), 0u, 0u};
+        }
+        av = __builtin_bit_cast(bf16x8, v);
+      } else {
+        av = *reinterpret_cast<const bf16x8*>(T + (32 * rb + m32) * P + 8 * kh);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[rb][i] = 0.f;
+      acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[rb], 0, 0, 0);
+    }
+    wave_lds_sync();  // the previous deltas have been read
+    if (m32 < H) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
+          T[r * P + m32] = (uint16_t)(pack2(acc[rb][i], 0.f) & 0xffffu);
+        }
+    }
+    wave_lds_sync();
+    if (lane < nrows) {  // mask the row, write the deltas at layer l - 1's outputs, keep them
+      u4* lrow = reinterpret_cast<u4*>(T + lane * P);
+      const u4* hrow = reinterpret_cast<const u4*>(g.act + (int64_t)l * g.layer_elems + (r0 + lane) * ld);
+      u4* drow = reinterpret_cast<u4*>(gen_delta_out(g, l - 1) + (r0 + lane) * ld);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        u4 v = lrow[q];
+        const u4 h = hrow[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned int lo = (h[e] & 0xffffu) ? 0xffffu : 0u, hi = (h[e] >> 16) ? 0xffff0000u : 0u;
+          v[e] &= lo | hi;
+        }
+        lrow[q] = v;
+        drow[q] = v;
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
 // Rendering, loss and (training) the adjoint of one row tile per wave, by the fused kernels'
 // render_subtile; the tile's loss (a fixed-order wave sum) goes to gen_loss, dL/dz to dz.
 template <bool TRAIN>
@@ -3614,6 +3808,20 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
     }
   };
   hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
+  if (H == 16) {  // one launch per direction through all layers, then every weight gradient at once
+    if (!g.delta4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gen_fwd16, dim3(wave_blocks), dim3(256), 0, s, g);
+    if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
+    if (train) {
+      hipLaunchKernelGGL(k_gen_dx16, dim3(wave_blocks), dim3(256), 0, s, g);
+      const dim3 grid(g.a.n_objects, 1, kLayers + 1);  // inputs 32 or 16: one 32-column block
+      if (grid.x * grid.z <= 256) hipLaunchKernelGGL(k_gen_dw_small<16>, grid, dim3(1024), 0, s, g, -1);
+      else hipLaunchKernelGGL(k_gen_dw_small<4>, grid, dim3(256), 0, s, g, -1);
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_gen_encode, dim3(wave_blocks), dim3(256), 0, s, g);
   for (int l = 0; l <= kLayers; ++l) fwd_dx(GEN_FWD, (l == kLayers) ? kOut : H, l);
   if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
