@@ -31,7 +31,7 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t tile_start, flags, t_next, mark, batch, tile_bad, tile_loss, partial, wimage, img32, total;
+  size_t tile_start, flags, t_next, mark, batch, tile_bad, tile_loss, partial, wimage, img32, gimg, total;
   size_t wimage_stride;
   int max_tiles;
   // layered path (generic widths): row tiles, their losses, activations, deltas, z and dz
@@ -136,6 +136,9 @@ WorkLayout work_layout(const vmap_config* c) {
   w.wimage = off; off = align256(off + (size_t)c->max_objects * w.wimage_stride);
   // weight images of width-32 objects (staged by a plain copy)
   w.img32 = off; off = align256(off + (size_t)c->max_objects * img32_bytes(bf));
+  // BF16 parameter copies of layered-path objects of hidden 128 and up (the wide products' W)
+  w.gimg = off;
+  if (bf && keeps_gimg(c->max_hidden)) off = align256(off + (size_t)c->max_objects * ps * 2);
   // layered path: when max_hidden is one of its widths, activations and deltas of every sample
   // (rows = max_rays * max_samples_per_ray, ld = max(32, max_hidden) BF16 per row)
   if (bf && generic_width(c->max_hidden)) {
@@ -224,6 +227,10 @@ struct vmap_ctx {
   BatchDev* batch_dev() { return reinterpret_cast<BatchDev*>(work + wl.batch); }
   int32_t* tile_bad() { return reinterpret_cast<int32_t*>(work + wl.tile_bad); }
   unsigned char* img32() { return work + wl.img32; }
+  // BF16 parameter copies (layered path, hidden >= 128), or NULL when the stack keeps none
+  uint16_t* gimg() {
+    return (cfg.precision == VMAP_BF16 && keeps_gimg(cfg.max_hidden)) ? reinterpret_cast<uint16_t*>(work + wl.gimg) : nullptr;
+  }
   float* tile_loss() { return reinterpret_cast<float*>(work + wl.tile_loss); }
   float* partial() { return reinterpret_cast<float*>(work + wl.partial); }
   unsigned char* wimage() { return wl.wimage_stride ? work + wl.wimage : nullptr; }
@@ -302,6 +309,7 @@ StepArgs make_step_args(vmap_ctx* c, const vmap_batch* b) {
   a.wimage = c->wimage();
   a.wimage_stride = (int64_t)c->wl.wimage_stride;
   a.img32 = c->img32();
+  a.gimg = c->gimg();
   return a;
 }
 
@@ -362,6 +370,7 @@ OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* 
   a.growth = c->cfg.scale_growth_interval;
   a.max_tiles = c->wl.max_tiles;
   a.img32 = c->img32();
+  a.gimg = c->gimg();
   return a;
 }
 
@@ -627,8 +636,13 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   return VMAP_OK;
 }
 
-// The weight image of object k (width 32) from its current parameters.
+// The weight image of object k (width 32), or its BF16 parameter copy (layered path, hidden 128
+// and up), from its current parameters.
 hipError_t restage_image(vmap_ctx* c, int k, hipStream_t s) {
+  if (keeps_gimg(c->objs[k].hidden)) {
+    uint16_t* gimg = c->gimg();
+    return gimg ? launch_stage_gimg(c->theta(), gimg, k, c->p_stride, s) : hipSuccess;
+  }
   if (c->objs[k].hidden != 32) return hipSuccess;
   StepArgs a{};
   a.max_objects = c->cfg.max_objects;
@@ -636,6 +650,7 @@ hipError_t restage_image(vmap_ctx* c, int k, hipStream_t s) {
   a.p_stride = c->p_stride;
   a.desc = c->desc();
   a.img32 = c->img32();
+  a.gimg = c->gimg();
   return launch_stage_image32(c->cfg.precision == VMAP_BF16, a, k, s);
 }
 

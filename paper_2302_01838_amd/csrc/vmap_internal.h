@@ -298,6 +298,8 @@ struct OptArgs {
   const int32_t* t_next;      // per batch object, from k_worklist
   const int32_t* tile_bad;    // [tiles] non-finite partial per tile (MODE_STEP), or NULL: flags
   unsigned char* img32;       // weight images of width-32 objects [max_objects][img32_bytes]
+  uint16_t* gimg;             // BF16 copies of the parameters of layered-path objects of hidden
+                              // 128 or more [max_objects][p_stride], or NULL
   int p_stride;
   int max_objects;
   ObjDesc* desc;
@@ -357,6 +359,7 @@ struct StepArgs {
   unsigned char* wimage;      // weight images of wide objects, [max_objects][wimage_stride]
   int64_t wimage_stride;
   unsigned char* img32;       // weight images of width-32 objects [max_objects][img32_bytes]
+  const uint16_t* gimg;       // BF16 copies of layered-path parameters (hidden >= 128), or NULL
   // MODE_STEP only: the tile table (in LDS at byte offset lds_table) is also written to
   // tile_start_out, with the next Adam step counts (t_next) and cleared flags, for the optimiser;
   // tiles report a non-finite partial in tile_bad [tiles].
@@ -469,6 +472,10 @@ hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s);
 // unscaled gradient into its one tile partial and its loss into that tile's loss. tiles_bound:
 // host bound on the row tiles (ceil(n_rays / rpw) + n_objects).
 hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s);
+// The BF16 parameter copy of layered-path object k (hidden >= 128) from its parameters.
+hipError_t launch_stage_gimg(const float* theta, uint16_t* gimg, int k, int p_stride, hipStream_t s);
+// Whether objects of width H keep a BF16 parameter copy (layered path, wide products).
+__host__ __device__ constexpr bool keeps_gimg(int H) { return generic_width(H) && H >= 128; }
 enum OptKind { OPT_LOSS = 0, OPT_REDUCE = 1, OPT_ADAM = 2, OPT_REDUCE_ADAM = 3 };
 hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s);
 hipError_t launch_init_object(int k, int H, uint64_t seed, const double* bounds,

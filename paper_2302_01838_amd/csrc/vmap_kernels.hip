@@ -845,8 +845,13 @@ __device__ AdamCoef adam_coef(const OptArgs& a, int t) {
   return adam_coef_load(a, sh);
 }
 
-// Parameter p of object k changed to th: its entry in the object's weight image (width 32).
+// Parameter p of object k changed to th: its entry in the object's weight image (width 32), or
+// in its BF16 parameter copy (layered path, hidden 128 and up).
 __device__ __forceinline__ void update_image(const OptArgs& a, int k, int hidden, int p, float th) {
+  if (a.gimg && keeps_gimg(hidden)) {
+    a.gimg[(size_t)k * a.p_stride + p] = (uint16_t)(pack2(th, 0.f) & 0xffffu);
+    return;
+  }
   if (!a.img32 || hidden != 32) return;
   if (a.bf16) place_param<32, true>(a.img32 + (size_t)k * img32_bytes(true), p, th);
   else place_param<32, false>(a.img32 + (size_t)k * img32_bytes(false), p, th);
@@ -2318,8 +2323,13 @@ __global__ void __launch_bounds__(256) k_reduce_adam_wide(const OptArgs a_in) {
       *reinterpret_cast<float4*>(a.theta + i) = make_float4(th[0], th[1], th[2], th[3]);
       *reinterpret_cast<float4*>(a.m + i) = make_float4(m[0], m[1], m[2], m[3]);
       *reinterpret_cast<float4*>(a.v + i) = make_float4(v[0], v[1], v[2], v[3]);
+      if (a.gimg && keeps_gimg(hidden)) {  // the four BF16 copies in one store (i is a multiple of 4)
+        typedef unsigned int u2w __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<u2w*>(a.gimg + i) = u2w{pack2(th[0], th[1]), pack2(th[2], th[3])};
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) update_image(a, k, hidden, p + e, th[e]);
+        for (int e = 0; e < 4; ++e) update_image(a, k, hidden, p + e, th[e]);
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -2869,7 +2879,8 @@ hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
 //   forward  (GEN_FWD): rows = samples, n = outputs, k = inputs;   A = h_l,   B = W_l^T
 //   input gradient (GEN_DX): rows = samples, n = inputs, k = outputs;  A = delta, B = W_l
 // A is staged as its rows lie (k contiguous) and read as one 16-byte LDS read per lane; B is the
-// rows of W, staged as they lie, read directly (forward) or transposed (input gradient).
+// rows of W from the BF16 parameter copy, staged as they lie, read directly (forward) or
+// transposed (input gradient).
 // Weight gradients (k_gen_dw, k_gen_dw_small): rows = outputs, n = inputs, k = samples;
 // A = delta^T, B = h_l^T, both staged as the sample rows lie and read transposed.
 
@@ -3070,7 +3081,8 @@ __device__ __forceinline__ bool gen_rows(const GenArgs& g, const StepArgs& a, in
 // Forward and input-gradient products of one row block: a workgroup (four waves, 2 x 2) computes
 // a T x T block of D = A B (T = 64 or 128), each wave a T/2 x T/2 quarter as (T/64)^2 32 x 32
 // MFMA tiles, over K in chunks of 64. A (h_l, or the deltas at layer l's outputs) is staged as its
-// rows lie; B is rows of W (FP32, rounded to BF16 as staged), read directly (forward: W rows are
+// rows lie; B is rows of W from the object's BF16 parameter copy (the optimiser keeps it equal to
+// the parameters rounded to nearest even), read directly (forward: W rows are
 // the output columns, k contiguous) or transposed (input gradient: W rows are the k index). The
 // next chunk's loads are in flight while the current chunk's products run.
 template <int KIND, int T>
@@ -3084,7 +3096,7 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   constexpr int PT = T + T / 8;                // pitch of the transposed W tile (rows = k)
   constexpr int WT = T / 2, NS = WT / 32;      // wave tile, 32 x 32 MFMA tiles per dimension
   constexpr int NA = T * KC / 8 / 256;         // A pieces (8 BF16) per thread and chunk
-  constexpr int NB = T * KC / 4 / 256;         // W pieces (4 FP32) per thread and chunk
+  constexpr int NB = T * KC / 8 / 256;         // W pieces (8 BF16) per thread and chunk
   constexpr int PC = T + 8;                    // pitch of the staged result block
   constexpr int kA = T * PA, kB = (KIND == GEN_FWD) ? T * PA : KC * PT;
   static_assert(T * PC <= kA + kB, "the result block fits the operand tiles");
@@ -3109,13 +3121,12 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   if (!gen_rows<T>(g, a, bx, k, r0, nrows)) return;
   const int n0 = by * T;
   const float* W = a.theta + (size_t)k * a.p_stride + layer_param_off(H, l);  // [O][K], then b [O]
+  const uint16_t* Wb = a.gimg + (size_t)k * a.p_stride + layer_param_off(H, l);  // W in BF16
   const int ktot = (KIND == GEN_FWD) ? K : O;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  typedef unsigned int u2w __attribute__((ext_vector_type(2)));
   // A piece p = tid + 256 q: row p / 8, k columns 8 (p mod 8); ktot is a multiple of 8, or the
   // output layer's 4 seeds (FP32 [rows][4], rounded here)
-  u4 va[NA];
-  float4 vw[NB];
+  u4 va[NA], vw[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
@@ -3134,13 +3145,13 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int p = tid + 256 * q;
-      vw[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (KIND == GEN_FWD) {  // W rows n0 + n, k0 + c .. + 3
-        const int n = p >> 4, c = (p & 15) * 4;
-        if (n0 + n < O && k0 + c < K) vw[q] = *reinterpret_cast<const float4*>(W + (size_t)(n0 + n) * K + k0 + c);
-      } else {  // W rows k0 + o, columns n0 + c .. + 3
-        const int o = p / (T / 4), c = (p % (T / 4)) * 4;
-        if (k0 + o < O && n0 + c < K) vw[q] = *reinterpret_cast<const float4*>(W + (size_t)(k0 + o) * K + n0 + c);
+      vw[q] = u4{0u, 0u, 0u, 0u};
+      if constexpr (KIND == GEN_FWD) {  // W rows n0 + n, k0 + c .. + 7 (K is a multiple of 8)
+        const int n = p >> 3, c = (p & 7) * 8;
+        if (n0 + n < O && k0 + c < K) vw[q] = *reinterpret_cast<const u4*>(Wb + (size_t)(n0 + n) * K + k0 + c);
+      } else {  // W rows k0 + o, columns n0 + c .. + 7
+        const int o = p / (T / 8), c = (p % (T / 8)) * 8;
+        if (k0 + o < O && n0 + c < K) vw[q] = *reinterpret_cast<const u4*>(Wb + (size_t)(k0 + o) * K + n0 + c);
       }
     }
   };
@@ -3162,9 +3173,8 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int p = tid + 256 * q;
-      const u2w w = u2w{pack2(vw[q].x, vw[q].y), pack2(vw[q].z, vw[q].w)};
-      if constexpr (KIND == GEN_FWD) *reinterpret_cast<u2w*>(Bs + (p >> 4) * PA + (p & 15) * 4) = w;
-      else *reinterpret_cast<u2w*>(Bs + (p / (T / 4)) * PT + (p % (T / 4)) * 4) = w;
+      if constexpr (KIND == GEN_FWD) *reinterpret_cast<u4*>(Bs + (p >> 3) * PA + (p & 7) * 8) = vw[q];
+      else *reinterpret_cast<u4*>(Bs + (p / (T / 8)) * PT + (p % (T / 8)) * 8) = vw[q];
     }
     if (k0 + KC < ktot) fetch(k0 + KC);
     __syncthreads();
@@ -3785,6 +3795,24 @@ __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
   float s = 0.f;
   for (int t = tr.t0; t < tr.t1; ++t) s += g.gen_loss[t];
   a.tile_loss[ts] = s;
+}
+
+// BF16 copy of object k's parameter slots (round to nearest even), eight per thread.
+__global__ void __launch_bounds__(256) k_gen_stage_gimg(const float* __restrict__ theta, uint16_t* __restrict__ gimg,
+                                                       int k, int p_stride) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const int p = (blockIdx.x * blockDim.x + threadIdx.x) * 8;  // p_stride is a multiple of 8
+  if (p >= p_stride) return;
+  const size_t i = (size_t)k * p_stride + p;
+  const float4 x0 = *reinterpret_cast<const float4*>(theta + i);
+  const float4 x1 = *reinterpret_cast<const float4*>(theta + i + 4);
+  *reinterpret_cast<u4*>(gimg + i) = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
+}
+
+hipError_t launch_stage_gimg(const float* theta, uint16_t* gimg, int k, int p_stride, hipStream_t s) {
+  if (!theta || !gimg || k < 0 || p_stride <= 0 || p_stride % 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gen_stage_gimg, dim3((p_stride / 8 + 255) / 256), dim3(256), 0, s, theta, gimg, k, p_stride);
+  return hipGetLastError();
 }
 
 hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s) {
