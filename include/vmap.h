@@ -70,9 +70,10 @@ typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed
  * model's width, Sec. 4, Implementation Details), 1 <= max_samples_per_ray <= 64. Objects of
  * different widths may share a stack and a batch (max_hidden bounds them). In VMAP_BF16 the
  * widths 16, 256, 512 and 1024 (the hidden-size range of Sec. 4.3's vectorised-vs-sequential
- * study) are trained by a layered path (one launch per layer and direction, activations in the
- * workspace) with the same rounding points; they need max_hidden in {16, 256, 512, 1024}, a stack
- * holds objects of at most one of them, and vmap_query_occupancy does not take them.
+ * study) are trained by a layered path (launches per layer and direction, or at width 16 one per
+ * direction, activations in the workspace) with the same rounding points; they need max_hidden in
+ * {16, 256, 512, 1024}, a stack holds objects of at most one of them, and vmap_query_occupancy
+ * does not take them.
  */
 typedef struct {
   int32_t max_objects;          /* capacity of the model stack, 1..65536 */
@@ -141,9 +142,11 @@ typedef struct {
 size_t vmap_state_bytes(const vmap_config* cfg);
 
 /* Bytes of the caller-owned device workspace for batches of up to config.max_rays rays and
- * config.max_objects objects: tile partial gradients, work lists and, when max_hidden = 128,
- * one BF16 weight image per object slot (the training kernel reads wide weights from device
- * memory). Returns 0 for an invalid config. Host only. */
+ * config.max_objects objects: tile partial gradients, work lists and, in VMAP_BF16, weight images
+ * (hidden 32 and 128: one per object slot, the training kernels read them) and, when max_hidden
+ * is a layered-path width, every sample's activations and deltas for max_rays rays of
+ * max_samples_per_ray samples (at 256 and up also a BF16 copy of each object slot's parameters).
+ * Returns 0 for an invalid config. Host only. */
 size_t vmap_workspace_bytes(const vmap_config* cfg);
 
 /* Number of parameters of one object of width `hidden` under cfg (no padding). Host only. */
