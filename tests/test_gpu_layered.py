@@ -94,6 +94,24 @@ def test_layered_row_block_edges(H, S, rays):
     check_step(errs, errs16, "bf16")
 
 
+@pytest.mark.parametrize("H", [256, 1024])
+def test_layered_set_params_then_step(H):
+    """Parameters set from the host (seeded perturbations well beyond one step's update) reach the
+    wide products: their BF16 parameter copy is restaged on set_state, so the step matches the
+    oracle run from the same parameters (a stale copy would run the initial weights)."""
+    print(f"[layered] set params H={H}", flush=True)
+    sc = _scene(H)
+    objs, states = make_pair(sc, "bf16")
+    rng = np.random.default_rng(23)
+    for k, st in states.items():
+        th = (st.theta + 0.3 * np.abs(st.theta).mean() * rng.standard_normal(st.theta.shape)).astype(np.float32)
+        objs.set_state(k, vm.STATE_PARAMS, th)
+        st.theta = th.astype(np.float64)
+    errs, errs16, _, _ = step_errors(objs, states, scenes.make_batch(sc, 0), "bf16", sc.B)
+    report(f"layered set params H={H}", **errs)
+    check_step(errs, errs16, "bf16")
+
+
 def test_layered_with_fused_width_in_one_step():
     """Hidden-32 objects (fused tile kernel) and hidden-256 objects (layered path) in one batch."""
     sc = _scene(0, widths=[32, 256, 32, 256])
