@@ -3820,6 +3820,8 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots || blocks_bound <= 0) return hipErrorInvalidValue;
   // k_gen_dw_small stages a narrow hidden layer's deltas in 8-column runs, 1, 2 or 4 per row
   if (g.H <= 32 && g.H != 8 && g.H != 16 && g.H != 32) return hipErrorInvalidValue;
+  // hidden 16 keeps every layer's deltas (four buffers); the wide products read W in BF16
+  if ((g.H == 16 && !g.delta4) || (keeps_gimg(g.H) && !g.a.gimg)) return hipErrorInvalidValue;
   const bool train = (mode == MODE_TRAIN);
   const int H = g.H;
   const int wave_blocks = (tiles_bound + 3) / 4;
@@ -3837,7 +3839,6 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   };
   hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
   if (H == 16) {  // one launch per direction through all layers, then every weight gradient at once
-    if (!g.delta4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gen_fwd16, dim3(wave_blocks), dim3(256), 0, s, g);
     if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
     else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
