@@ -1,4 +1,5 @@
-"""Weight images of width-32 objects, through the C ABI.
+"""Weight images of width-32 objects and the BF16 parameter copies of wide layered-path objects,
+through the C ABI.
 
 The tile kernel stages a width-32 object's weights by copying its weight image: the object's
 parameters already in the byte layout of the LDS staging (BF16 with transposed copies and bias
@@ -97,3 +98,39 @@ def test_set_state_restages_the_image():
     lb = b.step(db).cpu().numpy()
     assert np.array_equal(la, lb)
     _same(a, b, range(4))
+
+
+def _layered_scene(H):
+    import dataclasses
+    base = scenes.make_scene("tiny_k4")
+    return dataclasses.replace(base, objects=[dataclasses.replace(o, hidden=H) for o in base.objects])
+
+
+@pytest.mark.parametrize("H", [256, 1024])
+def test_layered_bf16_copy_after_steps_matches_whole_staging(H):
+    """The layered path's wide products read W from a BF16 copy of each object's parameters,
+    which the optimiser writes with every update (four at a time in the wide optimiser): after
+    each training step, and after an autograd-split Adam step, a twin whose copies are rebuilt
+    whole from its parameters trains, renders and stores bit for bit alike."""
+    sc = _layered_scene(H)
+    ids = range(4)
+    inc, _ = make_pair(sc, "bf16")
+    whole, _ = make_pair(sc, "bf16")
+    for s in range(3):
+        db = vm.DeviceBatch(scenes.make_batch(sc, s))
+        l1 = inc.step(db).cpu().numpy()
+        l2 = whole.step(db).cpu().numpy()
+        torch.cuda.synchronize()
+        print(f"[image] layered H={H} step {s}: loss sum {l1.sum():.6g}", flush=True)
+        assert np.array_equal(l1, l2), s
+        _restage(whole, ids)
+    db = vm.DeviceBatch(scenes.make_batch(sc, 3))
+    for o in (inc, whole):
+        o.backward(db, torch.ones(db.n_objects, device="cuda"))
+        o.adam_step(db)
+    torch.cuda.synchronize()
+    _restage(whole, ids)
+    _same(inc, whole, ids)
+    db = vm.DeviceBatch(scenes.make_batch(sc, 4))
+    for a, b in zip(inc.forward(db), whole.forward(db)):
+        assert torch.equal(a, b)
