@@ -448,7 +448,11 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
     }
     hipError_t e = launch_stage_images(H, bf, a, -1, si);
     if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
-    e = launch_tiles(H, bf, mode, a, c->waves, grid, si);
+    // this width's tiles are at most ceil(rays / its rays per tile) + objects: wider tiles need
+    // fewer workgroups than the stack's smallest tile size gives (the kernels stride over tiles)
+    const int rpt_h = tile_rays(H, c->rays_per_tile, c->rays_per_tile_wide);
+    const int grid_h = std::min(grid, (b->n_rays_total + rpt_h - 1) / rpt_h + b->n_objects);
+    e = launch_tiles(H, bf, mode, a, c->waves, grid_h, si);
     if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
   }
   if (fork) {
