@@ -35,7 +35,7 @@ struct WorkLayout {
   size_t wimage_stride;
   int max_tiles;
   // layered path (generic widths): row tiles, their losses, activations, deltas, z and dz
-  size_t gts, gbs, gen_loss, gact, gdelta, gz, gdz;
+  size_t gts, gbs, gws, gen_loss, gact, gdelta, gz, gdz;
   int max_gen_tiles, max_gen_blocks;
   int64_t gen_ld, gen_rows;
 };
@@ -150,6 +150,7 @@ WorkLayout work_layout(const vmap_config* c) {
     w.max_gen_blocks = (int)((w.gen_rows + kGenBlockRows - 1) / kGenBlockRows) + c->max_objects;
     w.gts = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
     w.gbs = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
+    w.gws = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
     w.gen_loss = off; off = align256(off + (size_t)w.max_gen_tiles * 4);
     w.gact = off; off = align256(off + (size_t)(kLayers + 1) * layer);
     // deltas: two buffers taken alternately, four at hidden 16 (one per hidden layer)
@@ -333,11 +334,18 @@ hipEvent_t pooled_event(vmap_ctx* c) {
   return e;
 }
 
+// Rays per work tile of a layered-path object in a batch of S samples per ray: about
+// kGenWorkRows rows, never fewer rays than the narrow tiles the workspace's tile count allows for.
+int gen_work_rays(const vmap_ctx* c, int S) {
+  return std::max(c->min_rays_per_tile, (kGenWorkRows + S - 1) / std::max(S, 1));
+}
+
 hipError_t enqueue_worklist(vmap_ctx* c, const vmap_batch* b, hipStream_t s,
                             const BatchDev* bd = nullptr) {
   return launch_worklist(b->n_objects, b->n_rays_total, b->object_ids, b->ray_offsets,
-                         c->rays_per_tile, c->rays_per_tile_wide, c->cfg.max_objects, c->desc(),
-                         c->scaler(), c->tile_start(), c->flags(), c->t_next(), bd, s);
+                         c->rays_per_tile, c->rays_per_tile_wide, gen_work_rays(c, b->samples_per_ray),
+                         c->cfg.max_objects, c->desc(), c->scaler(), c->tile_start(), c->flags(),
+                         c->t_next(), bd, s);
 }
 
 OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* grad_out,
@@ -426,6 +434,7 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       g.max_gen_tiles = c->wl.max_gen_tiles;
       g.gts = reinterpret_cast<int32_t*>(c->work + c->wl.gts);
       g.gbs = reinterpret_cast<int32_t*>(c->work + c->wl.gbs);
+      g.gws = reinterpret_cast<int32_t*>(c->work + c->wl.gws);
       g.max_gen_blocks = c->wl.max_gen_blocks;
       g.gen_loss = reinterpret_cast<float*>(c->work + c->wl.gen_loss);
       g.act = reinterpret_cast<uint16_t*>(c->work + c->wl.gact);
@@ -442,7 +451,9 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       const long long rows = (long long)b->n_rays_total * b->samples_per_ray;
       const long long blocks_bound = (rows + kGenBlockRows - 1) / kGenBlockRows + b->n_objects;
       if (blocks_bound > g.max_gen_blocks) return c->fail(VMAP_ECAPACITY, "batch needs more row blocks than the workspace holds");
-      hipError_t e = launch_generic(mode, g, tiles_bound, (int)blocks_bound, si);
+      g.work_rays = gen_work_rays(c, b->samples_per_ray);
+      const int work_bound = (b->n_rays_total + g.work_rays - 1) / g.work_rays + b->n_objects;
+      hipError_t e = launch_generic(mode, g, tiles_bound, (int)blocks_bound, work_bound, si);
       if (e != hipSuccess) return c->hip_fail(e, "layered-path launch");
       continue;
     }

@@ -224,12 +224,13 @@ __host__ __device__ constexpr int img32_bytes(bool bf16) { return round_up(lds_l
 
 // Widths without a fused tile kernel, trained (BF16) by the layered path: a chain of launches
 // over activations kept in device memory (encoding, one product launch per layer forward and per
-// layer and direction backward, rendering). The whole object is one work tile there: its
-// gradient is summed over all its rows by one product launch per layer.
+// layer and direction backward, rendering). Its work tiles (one weight-gradient partial each) are
+// runs of about kGenWorkRows rows of an object: an object of fewer rows is one work tile.
 __host__ __device__ constexpr bool generic_width(int H) {
   return H == 16 || H == 256 || H == 512 || H == 1024;
 }
 constexpr int kWholeObject = 1 << 26;  // rays per tile of a layered-path object (max_rays bound)
+constexpr int kGenWorkRows = 4096;     // rows (samples) per work tile of a layered-path object
 
 // Rays per work tile of an object of width H.
 __host__ __device__ constexpr int tile_rays(int H, int rpt, int rpt_wide) {
@@ -389,6 +390,9 @@ struct GenArgs {
   int32_t* gbs;          // [n_objects + 1] first 128-row block of each batch object
   uint16_t* delta4;      // hidden 16: BF16 [4][rows][ld], the deltas at layers 0..3's outputs (all
                          // kept, so that one launch takes every weight gradient); NULL otherwise
+  int work_rays;         // rays per work tile of this chain's objects (the work list's)
+  int32_t* gws;          // [n_objects + 1] first work tile of each batch object among this chain's
+                         // work tiles (the chain's objects' tiles, counted alone)
 };
 // Kinds of the layered path's row-block product kernel (the weight gradients have their own).
 enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
@@ -396,15 +400,16 @@ enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
 // every kGenBlockRows rows regardless of ray boundaries (rows are independent in those products).
 constexpr int kGenBlockRows = 128;
 // LDS of the product kernels: k_gen_gemm and k_gen_dw stage two BF16 operand tiles of up to
-// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small up to sixteen waves'
-// pairs of 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16 accumulators
-// and 8 bias parts per lane).
+// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small its kGenDwWaves
+// waves' pairs of 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16
+// accumulators per lane and 32 bias sums per wave).
 constexpr int kGenKChunk = 64;
 constexpr int kGenPitch = 36;
+constexpr int kGenDwWaves = 8;
 constexpr int kGenTileLds = 2 * 128 * (kGenKChunk + 8) * 2;
-constexpr int kGenSmallLds = (16 * 2 * 32 * kGenPitch * 2 > 4 * (16 * 16 * 64 + 16 * 64 * 8))
-                                 ? 16 * 2 * 32 * kGenPitch * 2
-                                 : 4 * (16 * 16 * 64 + 16 * 64 * 8);
+constexpr int kGenSmallLds = (kGenDwWaves * 2 * 32 * kGenPitch * 2 > 4 * kGenDwWaves * (16 * 64 + 32))
+                                 ? kGenDwWaves * 2 * 32 * kGenPitch * 2
+                                 : 4 * kGenDwWaves * (16 * 64 + 32);
 constexpr int kGenLdsBytes = kGenTileLds > kGenSmallLds ? kGenTileLds : kGenSmallLds;
 
 struct QueryArgs {
@@ -460,6 +465,7 @@ struct SceneArgs {
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
                            const int32_t* ray_offsets, int rays_per_tile, int rays_per_tile_wide,
+                           int rays_per_tile_gen,
                            int max_objects, const ObjDesc* desc, ScalerState* scaler,
                            int32_t* tile_start, int32_t* flags, int32_t* t_next,
                            const BatchDev* bd, hipStream_t s);
@@ -471,7 +477,8 @@ hipError_t launch_debug_batch(const StepArgs& a, int32_t* mark, hipStream_t s);
 // products, rendering (and loss), then in training the backward products, writing each object's
 // unscaled gradient into its one tile partial and its loss into that tile's loss. tiles_bound:
 // host bound on the row tiles (ceil(n_rays / rpw) + n_objects).
-hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s);
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, int work_bound,
+                          hipStream_t s);
 // The BF16 parameter copy of layered-path object k (hidden >= 128) from its parameters.
 hipError_t launch_stage_gimg(const float* theta, uint16_t* gimg, int k, int p_stride, hipStream_t s);
 // Whether objects of width H keep a BF16 parameter copy (layered path, wide products).

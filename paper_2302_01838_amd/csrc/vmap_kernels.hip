@@ -111,18 +111,15 @@ __device__ __forceinline__ int first_tile_of_block(int n_tiles) {
   return start + b / kXcds;
 }
 
-// Logical index of this workgroup in a two-dimensional grid, x fastest in the result, such that
-// each XCD (workgroups are dealt to the eight XCDs in turn by linear index) takes one contiguous
-// range of logical indices: blocks that share operands (the same rows or the same object) then
-// share one L2.
-__device__ __forceinline__ int xcd_grouped_index() {
-  constexpr int kXcds = 8;
-  const int n = (int)(gridDim.x * gridDim.y);
-  const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
-  const int x = b % kXcds;
-  int start = 0;
-  for (int y = 0; y < x; ++y) start += (n - y + kXcds - 1) / kXcds;  // workgroups of XCD y
-  return start + b / kXcds;
+// Unit and block of this workgroup in a one-dimensional grid of 8 ceil(units / 8) nblk
+// workgroups (workgroups are dealt to the eight XCDs in turn by index): unit u goes to XCD u mod 8,
+// and each XCD takes its units' nblk blocks one unit after another, so that the blocks of a unit
+// (which share its rows and its object's weights) share one L2, and the units that exist (the
+// first ones of a bound with slack) are spread evenly over the XCDs.
+__device__ __forceinline__ void xcd_unit_block(int nblk, int& unit, int& blk) {
+  const int b = (int)blockIdx.x, x = b & 7, s = b >> 3;
+  unit = x + 8 * (s / nblk);
+  blk = s % nblk;
 }
 
 // Logistic sigmoid from the hardware exponential and reciprocal (about 1 ulp each; an IEEE
@@ -2087,7 +2084,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
 // kernels leave every object unchanged (ScalerState::batch_ok).
 
 __global__ void __launch_bounds__(1024) k_worklist(int n_objects, int n_rays, const int32_t* ids,
-                                                   const int32_t* offs, int rpt, int rpt_wide,
+                                                   const int32_t* offs, int rpt, int rpt_wide, int rpt_gen,
                                                    int max_objects, const ObjDesc* __restrict__ desc,
                                                    ScalerState* __restrict__ scaler,
                                                    int32_t* __restrict__ tile_start,
@@ -2108,7 +2105,9 @@ __global__ void __launch_bounds__(1024) k_worklist(int n_objects, int n_rays, co
   // rays per tile of batch object j (by its width; invalid ids take the narrow size)
   auto rpt_of = [&](int j) {
     const int k = ids[j];
-    return (k >= 0 && k < max_objects && desc[k].registered) ? tile_rays(desc[k].hidden, rpt, rpt_wide) : rpt;
+    if (k < 0 || k >= max_objects || !desc[k].registered) return rpt;
+    const int h = desc[k].hidden;
+    return generic_width(h) ? rpt_gen : tile_rays(h, rpt, rpt_wide);
   };
   auto seg_ok = [&](int j, int o0, int o1) { return batch_segment_ok(j, n_objects, o0, o1, n_rays); };
   for (int j = j0; j < j1; ++j) {
@@ -2803,12 +2802,14 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s) {
 
 hipError_t launch_worklist(int n_objects, int n_rays, const int32_t* object_ids,
                            const int32_t* ray_offsets, int rays_per_tile, int rays_per_tile_wide,
+                           int rays_per_tile_gen,
                            int max_objects, const ObjDesc* desc, ScalerState* scaler,
                            int32_t* tile_start, int32_t* flags, int32_t* t_next,
                            const BatchDev* bd, hipStream_t s) {
+  if (rays_per_tile_gen < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, n_objects, n_rays, object_ids,
-                     ray_offsets, rays_per_tile, rays_per_tile_wide, max_objects, desc, scaler,
-                     tile_start, flags, t_next, bd);
+                     ray_offsets, rays_per_tile, rays_per_tile_wide, rays_per_tile_gen, max_objects,
+                     desc, scaler, tile_start, flags, t_next, bd);
   return hipGetLastError();
 }
 
@@ -2884,14 +2885,22 @@ hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
 // Weight gradients (k_gen_dw, k_gen_dw_small): rows = outputs, n = inputs, k = samples;
 // A = delta^T, B = h_l^T, both staged as the sample rows lie and read transposed.
 
-// Batch object of row tile t: the largest j with gts[j] <= t (objects without tiles have an empty
-// range and are passed over), by bisection.
-__device__ __forceinline__ int gen_object(const int32_t* __restrict__ gts, int n_objects, int t) {
-  int lo = 0, hi = n_objects;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (gts[mid] <= t) lo = mid;
-    else hi = mid;
+// Batch object of element t (a row tile, row block or work tile) of a chain given by its exclusive
+// scan: the largest j below n_objects with scan[j] <= t (objects without elements have an empty
+// range and are passed over; scan[0] = 0 <= t). Searched by the whole wave, 64 ways at a time: the
+// lanes read 64 evenly spaced entries of the remaining range together and a ballot keeps the last
+// one at or below t, so a lookup waits on ceil(log64 n) loads rather than log2 n dependent ones.
+// Every lane of the wave must be active and pass the same t.
+__device__ __forceinline__ int gen_object(const int32_t* __restrict__ scan, int n_objects, int t) {
+  const int lane = (int)(threadIdx.x & 63);
+  int lo = 0, len = n_objects;  // the answer lies in [lo, lo + len), scan[lo] <= t
+  while (len > 1) {
+    const int step = (len + 63) >> 6;
+    const int i = lane * step;
+    const bool le = i < len && scan[lo + i] <= t;  // a prefix of the lanes (scan is nondecreasing)
+    const int c = __popcll(__ballot(le)) - 1;      // lane 0 always counts
+    lo += c * step;
+    len = min(step, len - c * step);
   }
   return lo;
 }
@@ -2919,14 +2928,15 @@ __device__ __forceinline__ bool gen_tile(const GenArgs& g, const StepArgs& a, in
   return true;
 }
 
-// Row tiles per batch object, ceil(rays / rpw), and 128-row product blocks, ceil(rays S / 128), for
-// the objects of width H; none for the others or for a batch that failed the offsets check
-// (ScalerState::batch_ok, from the work-list launch). gts and gbs: their exclusive scans.
+// Row tiles per batch object, ceil(rays / rpw), 128-row product blocks, ceil(rays S / 128), and
+// work tiles, ceil(rays / work_rays) (as the work list counts them), for the objects of width H;
+// none for the others or for a batch that failed the offsets check (ScalerState::batch_ok, from
+// the work-list launch). gts, gbs and gws: their exclusive scans.
 __global__ void __launch_bounds__(1024) k_gen_tiles(const GenArgs g_in) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  __shared__ int part[2][1024];
+  __shared__ int part[3][1024];
   const bool ok = a.scaler->batch_ok != 0;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (a.n_objects + nt - 1) / nt;
@@ -2939,34 +2949,41 @@ __global__ void __launch_bounds__(1024) k_gen_tiles(const GenArgs g_in) {
     return nr > 0 ? nr : 0;
   };
   auto nblk = [&](int nr) { return (int)(((long long)nr * a.S + kGenBlockRows - 1) / kGenBlockRows); };
-  int lt = 0, lb = 0;
+  int lt = 0, lb = 0, lw = 0;
   for (int j = j0; j < j1; ++j) {
     const int nr = rays(j);
     lt += tiles_of(nr, g.rpw);
     lb += nblk(nr);
+    lw += tiles_of(nr, g.work_rays);
   }
   part[0][tid] = lt;
   part[1][tid] = lb;
+  part[2][tid] = lw;
   __syncthreads();
   for (int off = 1; off < nt; off <<= 1) {
     const int vt = (tid >= off) ? part[0][tid - off] : 0;
     const int vb = (tid >= off) ? part[1][tid - off] : 0;
+    const int vw = (tid >= off) ? part[2][tid - off] : 0;
     __syncthreads();
     part[0][tid] += vt;
     part[1][tid] += vb;
+    part[2][tid] += vw;
     __syncthreads();
   }
-  int rt = part[0][tid] - lt, rb = part[1][tid] - lb;
+  int rt = part[0][tid] - lt, rb = part[1][tid] - lb, rw = part[2][tid] - lw;
   for (int j = j0; j < j1; ++j) {
     const int nr = rays(j);
     g.gts[j] = rt;
     g.gbs[j] = rb;
+    g.gws[j] = rw;
     rt += tiles_of(nr, g.rpw);
     rb += nblk(nr);
+    rw += tiles_of(nr, g.work_rays);
   }
   if (tid == nt - 1) {
     g.gts[a.n_objects] = part[0][nt - 1];
     g.gbs[a.n_objects] = part[1][nt - 1];
+    g.gws[a.n_objects] = part[2][nt - 1];
   }
 }
 
@@ -3086,7 +3103,7 @@ __device__ __forceinline__ bool gen_rows(const GenArgs& g, const StepArgs& a, in
 // the output columns, k contiguous) or transposed (input gradient: W rows are the k index). The
 // next chunk's loads are in flight while the current chunk's products run.
 template <int KIND, int T>
-__global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
+__global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l, int ncol_blocks) {
   static_assert(KIND == GEN_FWD || KIND == GEN_DX, "products over one row block");
   static_assert(T == 64 || T == 128, "block sizes");
   GenArgs g = g_in;
@@ -3112,10 +3129,9 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   const int64_t ld = g.ld;
   const uint16_t* act_l = g.act + (int64_t)l * g.layer_elems;  // h_l (l = 0: the encoding)
   const uint16_t* dout = head ? nullptr : gen_delta_out(g, l);  // delta at layer l's outputs
-  // logical block: column blocks fastest, so that an XCD's consecutive blocks share rows of A
-  // and an object's W
-  const int lb = xcd_grouped_index();
-  const int bx = lb / (int)gridDim.y, by = lb % (int)gridDim.y;
+  // row block bx, column block by (of ncol_blocks), the row blocks dealt to the XCDs in turn
+  int bx, by;
+  xcd_unit_block(ncol_blocks, bx, by);
   int k, nrows;
   int64_t r0;
   if (!gen_rows<T>(g, a, bx, k, r0, nrows)) return;
@@ -3261,22 +3277,28 @@ __global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l) {
   }
 }
 
-// Object j of the batch whose weight gradient a workgroup of the layered path computes: its id,
-// work tile and rows, if it is one of the chain's objects with rows (else false).
+// Work tile w of the layered chain (counted over the chain's objects alone, gws), whose
+// weight-gradient partial a workgroup computes: its object's id, its index in the batch's work
+// list (tile_start, shared with the other widths) and its rows (g.work_rays rays of one object),
+// if w is a work tile of one of the chain's objects with rows (else false).
 struct GenObj {
   int k, ts;
   int64_t r0;  // first row
   int nrows;
 };
-__device__ __forceinline__ bool gen_object_rows(const GenArgs& g, const StepArgs& a, int j, GenObj& o) {
-  if (j >= a.n_objects || !a.scaler->batch_ok) return false;
+__device__ __forceinline__ bool gen_work_rows(const GenArgs& g, const StepArgs& a, int w, GenObj& o) {
+  if (!a.scaler->batch_ok) return false;
+  const int total = clamp_tiles(g.gws[a.n_objects], a.max_tiles);
+  if (w >= total) return false;
+  const int j = gen_object(g.gws, a.n_objects, w);
   const int k = a.object_ids[j];
   if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != g.H) return false;
-  const int ts = a.tile_start[j];
-  if (ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return false;  // no rays: no tile
-  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], 0, kWholeObject, a.n_rays);
-  o = GenObj{k, ts, (int64_t)rr.lo * a.S, (rr.hi - rr.lo) * a.S};
-  return true;
+  const int i = w - g.gws[j];  // work tile i of object j
+  const TileRange tr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  if (i < 0 || tr.t0 + i >= tr.t1) return false;
+  const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], i, g.work_rays, a.n_rays);
+  o = GenObj{k, tr.t0 + i, (int64_t)rr.lo * a.S, (rr.hi - rr.lo) * a.S};
+  return o.nrows > 0;
 }
 
 // Weight gradient of a hidden layer of more than 32 outputs: dW_l[o][i] = sum over the object's
@@ -3287,7 +3309,7 @@ __device__ __forceinline__ bool gen_object_rows(const GenArgs& g, const StepArgs
 // chunk's loads are in flight while the current chunk's products run) and the operands are read
 // transposed; rows past the object's end are staged as zeros.
 template <int T>
-__global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
+__global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l, int nblk) {
   static_assert(T == 64 || T == 128, "block sizes");
   GenArgs g = g_in;
   read_batch(g.a);
@@ -3302,11 +3324,11 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
   const int K = (l == 0) ? kEnc : H, O = H;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, m32 = lane & 31, kh = lane >> 5;
-  // logical block: an object's blocks consecutive, so that an XCD works on few objects' rows
-  const int lb = xcd_grouped_index();
-  const int bj = lb / (int)gridDim.y, by = lb % (int)gridDim.y;
+  // work tile bj, weight block by (of nblk), the work tiles dealt to the XCDs in turn
+  int bj, by;
+  xcd_unit_block(nblk, bj, by);
   GenObj ob;
-  if (l >= kLayers || O <= 32 || !gen_object_rows(g, a, bj, ob)) return;
+  if (l >= kLayers || O <= 32 || !gen_work_rows(g, a, bj, ob)) return;
   const int64_t ld = g.ld;
   const int nrows = ob.nrows;
   const int nbi = (K + T - 1) / T;
@@ -3407,23 +3429,25 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l) {
 }
 
 // Weight gradient of a layer with at most 32 outputs (every layer at hidden 16; the output layer
-// at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) of one object, and
-// its NW waves take the object's rows in 32-row chunks in turn (chunk c to wave c mod NW), each
+// at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) over one work tile
+// of an object, and its NW waves take the tile's rows in 32-row chunks in turn (chunk c to wave
+// c mod NW), each
 // in its own LDS tiles, staged as the rows lie in memory (16-byte loads, the wave's next chunk in
 // flight during the current chunk's products) and read transposed. The waves' sums are added in
 // wave order, so the result does not depend on the grid. Bias gradient: the deltas as the products
 // see them (BF16), or the output layer's FP32 seed unrounded, summed per lane over its staged rows
-// and then over lanes and waves in a fixed order. NW = 16 when the launch has few workgroups (a
-// wave's chain of dependent chunks is then a sixteenth of the object's rows), else 4.
-template <int NW>
-__global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, int l_arg) {
+// and then over lanes and waves in a fixed order. The wave count is fixed (kGenDwWaves, not chosen
+// by the size of the launch), so an object's sums do not depend on the rest of the batch; eight
+// waves leave a wave an eighth of the work tile's rows and fit two workgroups on a CU (registers).
+__global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs g_in, int l_arg) {
+  constexpr int NW = kGenDwWaves;
   GenArgs g = g_in;
   read_batch(g.a);
   const int l = l_arg >= 0 ? l_arg : (int)blockIdx.z;  // l_arg < 0: every layer, one per grid z
   const StepArgs& a = g.a;
   constexpr int P = kGenPitch;                   // 32 columns + 4 (elements)
   constexpr int kWaveTile = 2 * 32 * P;          // one wave's A and B tiles (uint16 elements)
-  constexpr int kRed = NW * 16 * 64 + NW * 64 * 8;  // floats of the final sums: accumulators, bias parts
+  constexpr int kRed = NW * 16 * 64 + NW * 32;  // floats of the final sums: accumulators, bias sums
   __shared__ __attribute__((aligned(16))) uint16_t lds[(NW * kWaveTile > 2 * kRed) ? NW * kWaveTile : 2 * kRed];
   const int H = g.H;
   const bool head = (l == kLayers);
@@ -3431,7 +3455,7 @@ __global__ void __launch_bounds__(NW * 64) k_gen_dw_small(const GenArgs g_in, in
   const int O = head ? kOut : H;  // 4, or a hidden width of 8, 16 or 32 (the launch checks)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   GenObj ob;
-  if (!gen_object_rows(g, a, blockIdx.x, ob)) return;
+  if (!gen_work_rows(g, a, blockIdx.x, ob)) return;
   const int64_t ld = g.ld;
   const int nrows = ob.nrows;
   const int n0 = blockIdx.y * 32;
@@ -3781,7 +3805,8 @@ __global__ void __launch_bounds__(256) k_gen_render(const GenArgs g_in) {
   if (lane == 0) g.gen_loss[t] = loss;
 }
 
-// Loss of each object of the chain: its row tiles' losses in order, into its one work tile.
+// Loss of each object of the chain: its row tiles' losses in order, into its first work tile (its
+// other work tiles hold zero, so the optimiser's sum over them is the object's loss).
 __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
   GenArgs g = g_in;
   read_batch(g.a);
@@ -3790,11 +3815,12 @@ __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
   if (j >= a.n_objects) return;
   const int total = clamp_tiles(g.gts[a.n_objects], g.max_gen_tiles);
   const TileRange tr = clamp_tile_range(g.gts[j], g.gts[j + 1], total);
-  const int ts = a.tile_start[j];
-  if (tr.t1 <= tr.t0 || ts < 0 || ts >= a.max_tiles || a.tile_start[j + 1] <= ts) return;
+  const TileRange wr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
+  if (tr.t1 <= tr.t0 || wr.t1 <= wr.t0) return;
   float s = 0.f;
   for (int t = tr.t0; t < tr.t1; ++t) s += g.gen_loss[t];
-  a.tile_loss[ts] = s;
+  a.tile_loss[wr.t0] = s;
+  for (int t = wr.t0 + 1; t < wr.t1; ++t) a.tile_loss[t] = 0.f;
 }
 
 // BF16 copy of object k's parameter slots (round to nearest even), eight per thread.
@@ -3815,9 +3841,12 @@ hipError_t launch_stage_gimg(const float* theta, uint16_t* gimg, int k, int p_st
   return hipGetLastError();
 }
 
-hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, hipStream_t s) {
+hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int blocks_bound, int work_bound,
+                          hipStream_t s) {
   if (tiles_bound <= 0 || g.a.n_objects <= 0) return hipSuccess;
-  if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots || blocks_bound <= 0) return hipErrorInvalidValue;
+  if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots || blocks_bound <= 0 || work_bound <= 0 ||
+      g.work_rays < 1)
+    return hipErrorInvalidValue;
   // k_gen_dw_small stages a narrow hidden layer's deltas in 8-column runs, 1, 2 or 4 per row
   if (g.H <= 32 && g.H != 8 && g.H != 16 && g.H != 32) return hipErrorInvalidValue;
   // hidden 16 keeps every layer's deltas (four buffers); the wide products read W in BF16
@@ -3828,13 +3857,17 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   auto blocks = [](int n, int t) { return (n + t - 1) / t; };
   // a product whose output columns number at least 128 takes 128 x 128 blocks over 128-row blocks;
   // narrower ones 64 x 64 blocks over the row tiles
+  // one-dimensional grids of 8 ceil(units / 8) x blocks-per-unit workgroups (xcd_unit_block)
+  auto grid1 = [&](int units, int nblk) { return dim3((unsigned)(8 * blocks(units, 8) * nblk)); };
   auto fwd_dx = [&](int kind, int ncols, int l) {
     if (ncols >= 128) {
-      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 128>), dim3(blocks_bound, blocks(ncols, 128)), dim3(256), 0, s, g, l);
-      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 128>), dim3(blocks_bound, blocks(ncols, 128)), dim3(256), 0, s, g, l);
+      const int nb = blocks(ncols, 128);
+      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 128>), grid1(blocks_bound, nb), dim3(256), 0, s, g, l, nb);
+      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 128>), grid1(blocks_bound, nb), dim3(256), 0, s, g, l, nb);
     } else {
-      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 64>), dim3(tiles_bound, blocks(ncols, 64)), dim3(256), 0, s, g, l);
-      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 64>), dim3(tiles_bound, blocks(ncols, 64)), dim3(256), 0, s, g, l);
+      const int nb = blocks(ncols, 64);
+      if (kind == GEN_FWD) hipLaunchKernelGGL((k_gen_gemm<GEN_FWD, 64>), grid1(tiles_bound, nb), dim3(256), 0, s, g, l, nb);
+      else hipLaunchKernelGGL((k_gen_gemm<GEN_DX, 64>), grid1(tiles_bound, nb), dim3(256), 0, s, g, l, nb);
     }
   };
   hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
@@ -3845,9 +3878,8 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
     hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
     if (train) {
       hipLaunchKernelGGL(k_gen_dx16, dim3(wave_blocks), dim3(256), 0, s, g);
-      const dim3 grid(g.a.n_objects, 1, kLayers + 1);  // inputs 32 or 16: one 32-column block
-      if (grid.x * grid.z <= 256) hipLaunchKernelGGL(k_gen_dw_small<16>, grid, dim3(1024), 0, s, g, -1);
-      else hipLaunchKernelGGL(k_gen_dw_small<4>, grid, dim3(256), 0, s, g, -1);
+      const dim3 grid(work_bound, 1, kLayers + 1);  // inputs 32 or 16: one 32-column block
+      hipLaunchKernelGGL(k_gen_dw_small, grid, dim3(kGenDwWaves * 64), 0, s, g, -1);
     }
     return hipGetLastError();
   }
@@ -3860,14 +3892,15 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
       if (O <= 32) {
-        const dim3 grid(g.a.n_objects, blocks(K, 32));
-        if (grid.x * grid.y <= 256) hipLaunchKernelGGL(k_gen_dw_small<16>, grid, dim3(1024), 0, s, g, l);
-        else hipLaunchKernelGGL(k_gen_dw_small<4>, grid, dim3(256), 0, s, g, l);
+        hipLaunchKernelGGL(k_gen_dw_small, dim3(work_bound, blocks(K, 32)), dim3(kGenDwWaves * 64), 0, s, g, l);
       }
-      else if (O >= 128 && K >= 128)
-        hipLaunchKernelGGL(k_gen_dw<128>, dim3(g.a.n_objects, blocks(O, 128) * blocks(K, 128)), dim3(256), 0, s, g, l);
-      else
-        hipLaunchKernelGGL(k_gen_dw<64>, dim3(g.a.n_objects, blocks(O, 64) * blocks(K, 64)), dim3(256), 0, s, g, l);
+      else if (O >= 128 && K >= 128) {
+        const int nb = blocks(O, 128) * blocks(K, 128);
+        hipLaunchKernelGGL(k_gen_dw<128>, grid1(work_bound, nb), dim3(256), 0, s, g, l, nb);
+      } else {
+        const int nb = blocks(O, 64) * blocks(K, 64);
+        hipLaunchKernelGGL(k_gen_dw<64>, grid1(work_bound, nb), dim3(256), 0, s, g, l, nb);
+      }
       if (l > 0) fwd_dx(GEN_DX, K, l);
     }
   }

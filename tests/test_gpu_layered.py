@@ -94,6 +94,39 @@ def test_layered_row_block_edges(H, S, rays):
     check_step(errs, errs16, "bf16")
 
 
+@pytest.mark.parametrize("H", [16, 256])
+def test_layered_object_over_several_work_tiles(H):
+    """An object of 10,000 rows (1,000 rays of 10 samples) has its weight gradient summed over
+    three work tiles of about 4,096 rows (partials added in order by the optimiser), next to small
+    objects of one work tile each."""
+    print(f"[layered] work tiles H={H}", flush=True)
+    sc = _scene(H)
+    rays = {0: 1000, 1: 7, 2: 120, 3: 1}
+    objs, states = make_pair(sc, "bf16", max_rays=sum(rays.values()) + 64)
+    errs, errs16, _, _ = step_errors(objs, states, scenes.make_batch(sc, 0, n_rays=rays), "bf16", sc.B)
+    report(f"layered work tiles H={H}", **errs)
+    check_step(errs, errs16, "bf16")
+
+
+@pytest.mark.parametrize("H", [16, 256])
+def test_layered_results_independent_of_batch(H):
+    """Four objects stepped alone and inside the whole 50-object uneven batch (several times the
+    work tiles, so every launch grid differs) end with the same losses and states bit for bit:
+    no launch shape chosen from the batch's size changes an object's sums."""
+    print(f"[layered] batch independence H={H}", flush=True)
+    base = scenes.make_scene("k50_uneven")
+    sc = dataclasses.replace(base, objects=[dataclasses.replace(o, hidden=H) for o in base.objects])
+    ids = [0, 1, 2, 3]
+    objs, _ = make_pair(sc, "bf16")
+    small = objs.step(vm.DeviceBatch(scenes.make_batch(sc, 0, object_ids=ids))).cpu().numpy()
+    snap_small = snapshot(objs, ids)
+    objs, _ = make_pair(sc, "bf16")
+    full = objs.step(vm.DeviceBatch(scenes.make_batch(sc, 0))).cpu().numpy()
+    snap_full = snapshot(objs, ids)
+    assert np.array_equal(small.view(np.uint32), full[: len(ids)].view(np.uint32))
+    assert all(same_state(snap_small[k], snap_full[k]) for k in ids)
+
+
 @pytest.mark.parametrize("H", [256, 1024])
 def test_layered_set_params_then_step(H):
     """Parameters set from the host (seeded perturbations well beyond one step's update) reach the
