@@ -422,6 +422,9 @@ def main():
                     help="tile size of objects wider than 32 (0: the library default)")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
                     help="k50_uneven is the headline workload; the others are reported in the docs")
+    ap.add_argument("--hidden", type=int, default=0,
+                    help="give every object of the workload this width (the layered widths 16, "
+                         "256, 512, 1024 train in BF16 only); not the headline configuration")
     ap.add_argument("--sweep-objects", type=int, nargs="*", default=None,
                     help="only run the vectorised-vs-sequential sweep over these object counts")
     ap.add_argument("--sweep-hidden", type=int, nargs="*", default=None,
@@ -441,7 +444,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 5}), flush=True)
         return
     if args.forms is None:
-        args.forms = "bf16" if args.workload != WORKLOAD else "fp32,bf16"
+        args.forms = "bf16" if (args.workload != WORKLOAD or args.hidden) else "fp32,bf16"
     if args.sweep_hidden is not None:
         widths = args.sweep_hidden or [16, 32, 64, 128, 256, 512, 1024]
         res = sweep_hidden(widths, max(1, min(args.steps, 20)), graph=bool(args.graph))
@@ -466,6 +469,11 @@ def main():
     import scenes
 
     scene = scenes.make_scene(args.workload)
+    if args.hidden:
+        import dataclasses
+        scene = dataclasses.replace(scene, objects=[dataclasses.replace(o, hidden=args.hidden)
+                                                    for o in scene.objects])
+    headline = args.workload == WORKLOAD and not args.hidden
     n_batches = args.distinct_batches or (args.warmup + args.steps)
     log(f"generating {n_batches} batches of {args.workload}")
     batches = gen_batches(scene, n_batches)
@@ -505,8 +513,8 @@ def main():
     shape = head.get("launch", {})
     traffic = (measured_traffic(prec, shape.get("rays_per_tile", 0), shape.get("waves", 0),
                                 shape.get("split_step", False))
-               if args.workload == WORKLOAD else None)
-    if args.workload != WORKLOAD:
+               if headline else None)
+    if not headline:
         kname = ("tile kernels of the step (cooperative kernel of the wide models, with the "
                  "hidden-32 tile kernel where present), events around all of a step's tile launches")
     elif shape.get("split_step"):
@@ -530,7 +538,8 @@ def main():
         "vs_baseline": None,
         "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
+        "config": {"workload": WORKLOAD_TEXT[args.workload]
+                   + (f", every object at hidden {args.hidden}" if args.hidden else ""),
                    "objects": scene.n_objects, "samples_per_step": dev_batches[0].n_samples,
                    "graph": bool(args.graph), "parallelism": "single GPU",
                    "launch": {k: v for k, v in head.get("launch", {}).items()}},

@@ -3811,16 +3811,23 @@ __global__ void __launch_bounds__(256) k_gen_loss(const GenArgs g_in) {
   GenArgs g = g_in;
   read_batch(g.a);
   const StepArgs& a = g.a;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);  // a wave per batch object
   if (j >= a.n_objects) return;
   const int total = clamp_tiles(g.gts[a.n_objects], g.max_gen_tiles);
   const TileRange tr = clamp_tile_range(g.gts[j], g.gts[j + 1], total);
   const TileRange wr = clamp_tile_range(a.tile_start[j], a.tile_start[j + 1], a.max_tiles);
   if (tr.t1 <= tr.t0 || wr.t1 <= wr.t0) return;
+  // the row tiles' losses are read 64 at a time (one per lane) and added one after another in
+  // tile order from lane registers: the same sum as a serial loop, without a load per addition
   float s = 0.f;
-  for (int t = tr.t0; t < tr.t1; ++t) s += g.gen_loss[t];
-  a.tile_loss[wr.t0] = s;
-  for (int t = wr.t0 + 1; t < wr.t1; ++t) a.tile_loss[t] = 0.f;
+  for (int t0 = tr.t0; t0 < tr.t1; t0 += 64) {
+    const float v = (t0 + lane < tr.t1) ? g.gen_loss[t0 + lane] : 0.f;
+    const int n = min(64, tr.t1 - t0);
+    for (int i = 0; i < n; ++i) s += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+  }
+  if (lane == 0) a.tile_loss[wr.t0] = s;
+  for (int t = wr.t0 + 1 + lane; t < wr.t1; t += 64) a.tile_loss[t] = 0.f;
 }
 
 // BF16 copy of object k's parameter slots (round to nearest even), eight per thread.
@@ -3875,7 +3882,7 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
     hipLaunchKernelGGL(k_gen_fwd16, dim3(wave_blocks), dim3(256), 0, s, g);
     if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
     else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 3) / 4), dim3(256), 0, s, g);
     if (train) {
       hipLaunchKernelGGL(k_gen_dx16, dim3(wave_blocks), dim3(256), 0, s, g);
       const dim3 grid(work_bound, 1, kLayers + 1);  // inputs 32 or 16: one 32-column block
@@ -3887,7 +3894,7 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   for (int l = 0; l <= kLayers; ++l) fwd_dx(GEN_FWD, (l == kLayers) ? kOut : H, l);
   if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
   else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
-  hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 255) / 256), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 3) / 4), dim3(256), 0, s, g);
   if (train) {
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
