@@ -191,7 +191,8 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
 def sweep_hidden(widths, steps, n_objects=50, graph=False):
     """Vectorised vs sequential training step over hidden widths (Sec. 4.3, Fig. "ablative
     vectorised", right): n_objects objects of one width, 120 rays x 10 samples each, BF16. Widths
-    32, 64 and 128 run the fused tile kernels, the others the layered path. Returns ms per step."""
+    32, 64 and 128 run the fused tile kernels, 16 the width-32 one zero-padded, 256 and up the
+    layered path. Returns ms per step."""
     import dataclasses
     import torch
     import scenes
@@ -220,7 +221,8 @@ def sweep_hidden(widths, steps, n_objects=50, graph=False):
                 sub["S"] = b["S"]
                 row.append(vm.DeviceBatch(sub))
             per_obj.append(row)
-        res = {"hidden": H, "path": "fused tile kernel" if H in (32, 64, 128) else "layered"}
+        res = {"hidden": H, "path": ("fused tile kernel" if H in (32, 64, 128) else
+                                     "fused tile kernel, zero-padded to 32" if H == 16 else "layered")}
         for mode in ("vectorised", "sequential"):
             objs = vm.ObjectSet(max_objects=n_objects, B=sc.B, hidden=H, precision="bf16",
                                 max_rays=full[0].n_rays, max_samples_per_ray=sc.S)

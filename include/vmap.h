@@ -66,14 +66,15 @@ typedef struct vmap_ctx vmap_ctx; /* opaque; created by vmap_init_objects, freed
  * "Surface and Volume Rendering"). Parameters of one object are stored, in this order,
  * W_1 [H x E], b_1 [H], W_2 [H x H], b_2, ..., W_L, b_L, W_out [4 x H], b_out [4], every W
  * row-major as [out][in]; E = 2 * n_features. Supported: n_features = 16, n_hidden_layers = 4,
- * hidden in {32, 64} in both precisions and 128 in VMAP_BF16 (the background
+ * hidden in {16, 32, 64} in both precisions and 128 in VMAP_BF16 (the background
  * model's width, Sec. 4, Implementation Details), 1 <= max_samples_per_ray <= 64. Objects of
- * different widths may share a stack and a batch (max_hidden bounds them). In VMAP_BF16 the
- * widths 16, 256, 512 and 1024 (the hidden-size range of Sec. 4.3's vectorised-vs-sequential
- * study) are trained by a layered path (launches per layer and direction, or at width 16 one per
- * direction, activations in the workspace) with the same rounding points; they need max_hidden in
- * {16, 256, 512, 1024}, a stack holds objects of at most one of them, and vmap_query_occupancy
- * does not take them.
+ * different widths may share a stack and a batch (max_hidden bounds them). Width 16 runs in the
+ * width-32 kernels with its weights zero-padded to 32 units (exact: the extra units never
+ * activate), so its objects share the width-32 objects' launches, and a stack whose max_hidden
+ * is 16 is sized as for 32. In VMAP_BF16 the widths 256, 512 and 1024 (with 16, the hidden-size
+ * range of Sec. 4.3's vectorised-vs-sequential study) are trained by a layered path (launches
+ * per layer and direction, activations in the workspace) with the same rounding points; a stack
+ * holds objects of at most one of them, and vmap_query_occupancy does not take them.
  */
 typedef struct {
   int32_t max_objects;          /* capacity of the model stack, 1..65536 */
@@ -142,10 +143,10 @@ typedef struct {
 size_t vmap_state_bytes(const vmap_config* cfg);
 
 /* Bytes of the caller-owned device workspace for batches of up to config.max_rays rays and
- * config.max_objects objects: tile partial gradients, work lists and, in VMAP_BF16, weight images
- * (hidden 32 and 128: one per object slot, the training kernels read them) and, when max_hidden
- * is a layered-path width, every sample's activations and deltas for max_rays rays of
- * max_samples_per_ray samples (at 256 and up also a BF16 copy of each object slot's parameters).
+ * config.max_objects objects: tile partial gradients, work lists, weight images (hidden 16 and
+ * 32, one per object slot in either precision; hidden 128 in VMAP_BF16: the training kernels read
+ * them) and, when max_hidden is a layered-path width, every sample's activations and deltas for
+ * max_rays rays of max_samples_per_ray samples, and a BF16 copy of each object slot's parameters.
  * Returns 0 for an invalid config. Host only. */
 size_t vmap_workspace_bytes(const vmap_config* cfg);
 

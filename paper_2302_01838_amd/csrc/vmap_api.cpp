@@ -49,11 +49,9 @@ const char* check_config(const vmap_config* c) {
   if (c->n_hidden_layers != kLayers) return "n_hidden_layers must be 4";
   if (c->precision != VMAP_FP32 && c->precision != VMAP_BF16) return "precision must be VMAP_FP32 or VMAP_BF16";
   if (!hidden_ok(c->hidden, c->precision))
-    return "hidden width not supported (32 or 64; 128, and 16, 256, 512, 1024 by the layered path, in BF16)";
+    return "hidden width not supported (16, 32 or 64; 128, and 256, 512, 1024 by the layered path, in BF16)";
   if (c->max_hidden < c->hidden || !hidden_ok(c->max_hidden, c->precision))
     return "max_hidden must be a supported width >= hidden";
-  if (generic_width(c->hidden) && !generic_width(c->max_hidden))
-    return "a hidden width of the layered path (16, 256, 512, 1024) needs max_hidden of the same set";
   if (c->max_samples_per_ray < 1 || c->max_samples_per_ray > kSlots) return "max_samples_per_ray must be in [1, 64]";
   if (c->max_rays < 0 || c->max_rays > (1 << 26)) return "max_rays must be in [0, 2^26]";
   if (c->rays_per_tile < 0 || c->rays_per_tile > (1 << 16)) return "rays_per_tile must be in [0, 65536]";
@@ -100,10 +98,15 @@ int min_rays_per_tile(const vmap_config* c) {
   return c->max_hidden > 32 ? std::min(rpt, default_rays_per_tile_wide(c)) : rpt;
 }
 
+// Floats per object in the parameter, moment and gradient arrays and per tile partial: the
+// parameters of the widest kernel width the stack may run (hidden 16 runs at width 32, and its
+// tiles write width-32 partials).
+int param_stride(const vmap_config* c) { return pad_params(n_params_of(kernel_width(c->max_hidden))); }
+
 StateLayout state_layout(const vmap_config* c) {
   StateLayout s{};
   const size_t K = (size_t)c->max_objects;
-  const size_t ps = (size_t)pad_params(n_params_of(c->max_hidden));
+  const size_t ps = (size_t)param_stride(c);
   size_t off = 0;
   s.desc = off; off = align256(off + K * sizeof(ObjDesc));
   s.scaler = off; off = align256(off + sizeof(ScalerState));
@@ -119,7 +122,7 @@ StateLayout state_layout(const vmap_config* c) {
 WorkLayout work_layout(const vmap_config* c) {
   WorkLayout w{};
   const int rpt = min_rays_per_tile(c);
-  const size_t ps = (size_t)pad_params(n_params_of(c->max_hidden));
+  const size_t ps = (size_t)param_stride(c);
   w.max_tiles = (c->max_rays + rpt - 1) / rpt + c->max_objects;
   size_t off = 0;
   w.tile_start = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
@@ -153,8 +156,8 @@ WorkLayout work_layout(const vmap_config* c) {
     w.gws = off; off = align256(off + ((size_t)c->max_objects + 1) * 4);
     w.gen_loss = off; off = align256(off + (size_t)w.max_gen_tiles * 4);
     w.gact = off; off = align256(off + (size_t)(kLayers + 1) * layer);
-    // deltas: two buffers taken alternately, four at hidden 16 (one per hidden layer)
-    w.gdelta = off; off = align256(off + (c->max_hidden == 16 ? 4 : 2) * layer);
+    // deltas: two buffers taken alternately
+    w.gdelta = off; off = align256(off + 2 * layer);
     w.gz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
     w.gdz = off; off = align256(off + (size_t)w.gen_rows * kOut * 4);
   }
@@ -270,10 +273,14 @@ int validate_batch(vmap_ctx* c, const vmap_batch* b, bool need_targets) {
   return VMAP_OK;
 }
 
+// Kernel widths of the registered objects (hidden 16 shares the width-32 kernels), ascending:
+// one width group, and one tile launch or layered chain, per entry.
 std::vector<int> widths_present(vmap_ctx* c) {
   std::vector<int> w;
-  for (const auto& o : c->objs)
-    if (o.registered && std::find(w.begin(), w.end(), o.hidden) == w.end()) w.push_back(o.hidden);
+  for (const auto& o : c->objs) {
+    const int kw = kernel_width(o.hidden);
+    if (o.registered && std::find(w.begin(), w.end(), kw) == w.end()) w.push_back(kw);
+  }
   std::sort(w.begin(), w.end());
   return w;
 }
@@ -441,7 +448,6 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       const size_t layer = (size_t)c->wl.gen_rows * (size_t)c->wl.gen_ld;
       g.delta[0] = reinterpret_cast<uint16_t*>(c->work + c->wl.gdelta);
       g.delta[1] = g.delta[0] + layer;
-      g.delta4 = (H == 16 && c->cfg.max_hidden == 16) ? g.delta[0] : nullptr;
       g.z = reinterpret_cast<float*>(c->work + c->wl.gz);
       g.dz = reinterpret_cast<float*>(c->work + c->wl.gdz);
       g.ld = c->wl.gen_ld;
@@ -609,7 +615,7 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
     }
   }
   const bool bf = cfg->precision == VMAP_BF16;
-  for (int H = 32; H <= cfg->max_hidden; H *= 2) {
+  for (int H = 32; H <= kernel_width(cfg->max_hidden); H *= 2) {
     if (tiles_supported(H, bf) && tile_lds_bytes(H, bf, 4) > 160 * 1024) {
       g_init_error = "model too large for the 160 KB LDS of a workgroup";
       return VMAP_ENOTSUP;
@@ -621,7 +627,7 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   c->wl = wl;
   c->state = reinterpret_cast<unsigned char*>(state_dev);
   c->work = reinterpret_cast<unsigned char*>(workspace_dev);
-  c->p_stride = pad_params(n_params_of(cfg->max_hidden));
+  c->p_stride = param_stride(cfg);
   c->rays_per_tile = default_rays_per_tile(cfg);
   c->rays_per_tile_wide = default_rays_per_tile_wide(cfg);
   c->min_rays_per_tile = min_rays_per_tile(cfg);
@@ -658,7 +664,7 @@ hipError_t restage_image(vmap_ctx* c, int k, hipStream_t s) {
     uint16_t* gimg = c->gimg();
     return gimg ? launch_stage_gimg(c->theta(), gimg, k, c->p_stride, s) : hipSuccess;
   }
-  if (c->objs[k].hidden != 32) return hipSuccess;
+  if (kernel_width(c->objs[k].hidden) != 32) return hipSuccess;
   StepArgs a{};
   a.max_objects = c->cfg.max_objects;
   a.theta = c->theta();
@@ -676,8 +682,6 @@ int vmap_add_object(vmap_ctx* c, const vmap_object_desc* d, const float* init_pa
   const int H = d->hidden ? d->hidden : c->cfg.hidden;
   if (!hidden_ok(H, c->cfg.precision) || H > c->cfg.max_hidden)
     return c->fail(VMAP_ENOTSUP, "object hidden width not supported or above max_hidden");
-  if (generic_width(H) && !generic_width(c->cfg.max_hidden))
-    return c->fail(VMAP_ENOTSUP, "widths 16, 256, 512 and 1024 (layered path) need max_hidden of that set");
   if (generic_width(H) && c->gen_width != 0 && c->gen_width != H)
     return c->fail(VMAP_ENOTSUP, "a stack holds objects of at most one layered-path width");
   if (!(d->scale > 0.f) || !std::isfinite(d->scale)) return c->fail(VMAP_EINVAL, "desc.scale must be > 0");
@@ -979,7 +983,7 @@ int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, fl
   q.occ = occ_out;
   q.rgb = rgb_out;
   const bool bf = c->cfg.precision == VMAP_BF16;
-  const int H = c->objs[k].hidden;
+  const int H = kernel_width(c->objs[k].hidden);  // hidden 16: the width-32 kernel, zero-padded
   if (generic_width(H)) return c->fail(VMAP_ENOTSUP, "point queries of layered-path widths are not built");
   q.wimage = c->wimage();
   q.wimage_stride = (int64_t)c->wl.wimage_stride;

@@ -227,7 +227,56 @@ __host__ __device__ constexpr int img32_bytes(bool bf16) { return round_up(lds_l
 // layer and direction backward, rendering). Its work tiles (one weight-gradient partial each) are
 // runs of about kGenWorkRows rows of an object: an object of fewer rows is one work tile.
 __host__ __device__ constexpr bool generic_width(int H) {
-  return H == 16 || H == 256 || H == 512 || H == 1024;
+  return H == 256 || H == 512 || H == 1024;
+}
+
+// Width of the fused kernels that run an object of width H: hidden 16 runs in the width-32
+// kernels with its weights zero-padded to 32 units (the padded units' pre-activations are exactly
+// zero, so they stay inactive, add exact zeros to every sum and get zero gradients), sharing their
+// tiles, weight images and partials with the width-32 objects of the stack.
+__host__ __device__ constexpr int kernel_width(int H) { return H == 16 ? 32 : H; }
+
+// Slot of parameter p of a width-H object in the parameter layout of its kernel width (the
+// layout of the weight images and the tile partials): p itself, except at hidden 16, where
+// layer l's weight (o, i) and bias o keep their indices in the width-32 layout.
+__host__ __device__ constexpr int padded_index(int H, int p) {
+  if (H != 16) return p;
+  constexpr int H2 = 32;
+  int off = 0, off2 = 0;
+  for (int l = 0; l <= kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : 16, O = (l == kLayers) ? kOut : 16;
+    const int K2 = (l == 0) ? kEnc : H2, O2 = (l == kLayers) ? kOut : H2;
+    if (p < off + O * K) {
+      const int e = p - off, o = e / K, i = e - o * K;
+      return off2 + o * K2 + i;
+    }
+    if (p < off + O * K + O) return off2 + O2 * K2 + (p - off - O * K);
+    off += O * K + O;
+    off2 += O2 * K2 + O2;
+  }
+  return -1;  // p beyond the object's parameters
+}
+
+// Inverse of padded_index at hidden 16: the parameter of a width-16 object held in slot q of the
+// width-32 layout, or -1 for a padding slot (zero weight or bias).
+__host__ __device__ constexpr int unpadded_index16(int q) {
+  constexpr int H2 = 32;
+  int off = 0, off2 = 0;
+  for (int l = 0; l <= kLayers; ++l) {
+    const int K = (l == 0) ? kEnc : 16, O = (l == kLayers) ? kOut : 16;
+    const int K2 = (l == 0) ? kEnc : H2, O2 = (l == kLayers) ? kOut : H2;
+    if (q < off2 + O2 * K2) {
+      const int e = q - off2, o = e / K2, i = e - o * K2;
+      return (o < O && i < K) ? off + o * K + i : -1;
+    }
+    if (q < off2 + O2 * K2 + O2) {
+      const int o = q - off2 - O2 * K2;
+      return o < O ? off + O * K + o : -1;
+    }
+    off += O * K + O;
+    off2 += O2 * K2 + O2;
+  }
+  return -1;
 }
 constexpr int kWholeObject = 1 << 26;  // rays per tile of a layered-path object (max_rays bound)
 constexpr int kGenWorkRows = 4096;     // rows (samples) per work tile of a layered-path object
@@ -388,8 +437,6 @@ struct GenArgs {
   int64_t layer_elems;   // elements per layer of act
   int max_gen_blocks;    // 128-row blocks the block table holds
   int32_t* gbs;          // [n_objects + 1] first 128-row block of each batch object
-  uint16_t* delta4;      // hidden 16: BF16 [4][rows][ld], the deltas at layers 0..3's outputs (all
-                         // kept, so that one launch takes every weight gradient); NULL otherwise
   int work_rays;         // rays per work tile of this chain's objects (the work list's)
   int32_t* gws;          // [n_objects + 1] first work tile of each batch object among this chain's
                          // work tiles (the chain's objects' tiles, counted alone)
@@ -400,8 +447,8 @@ enum GenKind { GEN_FWD = 0, GEN_DX = 1 };
 // every kGenBlockRows rows regardless of ray boundaries (rows are independent in those products).
 constexpr int kGenBlockRows = 128;
 // LDS of the product kernels: k_gen_gemm and k_gen_dw stage two BF16 operand tiles of up to
-// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small its kGenDwWaves
-// waves' pairs of 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16
+// 128 x (kGenKChunk + 8) or kGenKChunk x (128 + 16) elements; k_gen_dw_small (the output layer)
+// its kGenDwWaves waves' pairs of 32-row tiles (rows of kGenPitch elements), then the waves' FP32 sums (16
 // accumulators per lane and 32 bias sums per wave).
 constexpr int kGenKChunk = 64;
 constexpr int kGenPitch = 36;

@@ -276,10 +276,21 @@ __device__ __forceinline__ void fetch_image_lds(const unsigned char* src, unsign
   }
 }
 
+// src_hidden: the object's own width; an object of hidden 16 staged at H = 32 reads each slot of
+// the width-32 layout from its own parameters (padded_index), zero for the padding.
 template <int H, bool BF>
-__device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsigned char* smem, int tid, int nt) {
+__device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsigned char* smem, int tid, int nt,
+                                              int src_hidden = H) {
   constexpr LdsLayout L = lds_layout(H, BF, 1);
   using WT = typename std::conditional<BF, __bf16, float>::type;
+  const bool padded = (H == 32 && src_hidden == 16);
+  auto param = [&](int q) -> float {
+    if (padded) {
+      const int p = unpadded_index16(q);
+      return p >= 0 ? th[p] : 0.f;
+    }
+    return th[q];
+  };
   int off = 0;
   float* bias = reinterpret_cast<float*>(smem + L.b_off);
 #pragma unroll
@@ -289,7 +300,7 @@ __device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsi
     const int ws = L.w_stride[l];
     for (int e = tid; e < H * K; e += nt) {
       const int row = e / K, col = e - row * K;
-      const WT w = (WT)th[off + e];
+      const WT w = (WT)param(off + e);
       W[row * ws + (col & ~31) + colpos(col & 31)] = w;
       if constexpr (BF) {
         if (l > 0) {  // W^T[col][row], rows of the transpose permuted like the forward's K axis
@@ -299,22 +310,22 @@ __device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsi
       }
     }
     off += H * K;
-    for (int e = tid; e < H; e += nt) bias[l * H + e] = th[off + e];
+    for (int e = tid; e < H; e += nt) bias[l * H + e] = param(off + e);
     off += H;
   }
   for (int e = tid; e < kOut * H; e += nt) {
     const int c = e / H, col = e - c * H;
     if constexpr (BF) {
-      const __bf16 w = (__bf16)th[off + e];
+      const __bf16 w = (__bf16)param(off + e);
       reinterpret_cast<__bf16*>(smem + L.whb_off)[c * (H + 8) + (col & ~31) + colpos(col & 31)] = w;
       reinterpret_cast<__bf16*>(smem + L.whtb_off)[col * kOut + c] = w;
     } else {
-      reinterpret_cast<float*>(smem + L.wh_off)[c * (H + 4) + (col & ~31) + colpos(col & 31)] = th[off + e];
+      reinterpret_cast<float*>(smem + L.wh_off)[c * (H + 4) + (col & ~31) + colpos(col & 31)] = param(off + e);
     }
   }
   off += kOut * H;
   float* bh = reinterpret_cast<float*>(smem + L.bh_off);
-  for (int e = tid; e < kOut; e += nt) bh[e] = th[off + e];
+  for (int e = tid; e < kOut; e += nt) bh[e] = param(off + e);
   if constexpr (BF) {
     // bias as an MFMA operand: b = hi + mid + lo exactly (three BF16 pieces of 8 bits each)
     __bf16* bA = reinterpret_cast<__bf16*>(smem + L.bA_off);
@@ -328,7 +339,7 @@ __device__ __forceinline__ void stage_weights(const float* __restrict__ th, unsi
     }
     for (int e = tid; e < kLayers * H; e += nt) {
       const int l = e / H, row = e - l * H;
-      const float b = th[boff[l] + row];
+      const float b = param(boff[l] + row);
       const __bf16 hi = (__bf16)b;
       const __bf16 mid = (__bf16)(b - (float)hi);
       const __bf16 lo = (__bf16)((b - (float)hi) - (float)mid);
@@ -842,16 +853,18 @@ __device__ AdamCoef adam_coef(const OptArgs& a, int t) {
   return adam_coef_load(a, sh);
 }
 
-// Parameter p of object k changed to th: its entry in the object's weight image (width 32), or
-// in its BF16 parameter copy (layered path, hidden 128 and up).
+// Parameter p of object k changed to th: its entry in the object's weight image (width 32, also
+// for hidden 16, whose image is the zero-padded width-32 one), or in its BF16 parameter copy
+// (layered path, hidden 128 and up).
 __device__ __forceinline__ void update_image(const OptArgs& a, int k, int hidden, int p, float th) {
   if (a.gimg && keeps_gimg(hidden)) {
     a.gimg[(size_t)k * a.p_stride + p] = (uint16_t)(pack2(th, 0.f) & 0xffffu);
     return;
   }
-  if (!a.img32 || hidden != 32) return;
-  if (a.bf16) place_param<32, true>(a.img32 + (size_t)k * img32_bytes(true), p, th);
-  else place_param<32, false>(a.img32 + (size_t)k * img32_bytes(false), p, th);
+  if (!a.img32 || kernel_width(hidden) != 32) return;
+  const int q = padded_index(hidden, p);
+  if (a.bf16) place_param<32, true>(a.img32 + (size_t)k * img32_bytes(true), q, th);
+  else place_param<32, false>(a.img32 + (size_t)k * img32_bytes(false), q, th);
 }
 
 // One Adam update; the contractions are spelled out so that the rounding does not depend on how
@@ -1021,7 +1034,7 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
       if (tid == 0) atomicOr(&a.scaler->device_error, 1);
       continue;
     }
-    if (hidden != H) continue;  // handled by the launch for that width
+    if (kernel_width(hidden) != H) continue;  // handled by the launch for that width
     if (restage) {
       __builtin_amdgcn_s_waitcnt(0);  // this thread's part of the image is in LDS
       staged = k;
@@ -1562,7 +1575,7 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
       if (tid == 0) atomicOr(&a.scaler->device_error, 1);
       continue;
     }
-    if (a.desc[k].hidden != H) continue;
+    if (kernel_width(a.desc[k].hidden) != H) continue;
     const int rpt = tile_rays(H, a.rays_per_tile, a.rays_per_tile_wide);
     const RayRange rr = tile_ray_range(a.ray_offsets[j], a.ray_offsets[j + 1], tile - a.tile_start[j],
                                        rpt, a.n_rays);
@@ -2029,11 +2042,11 @@ __global__ void __launch_bounds__(256) k_stage_image(const StepArgs a_in, int si
     if ((int)blockIdx.y >= a.n_objects) return;
     k = a.object_ids[blockIdx.y];
   }
-  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || a.desc[k].hidden != H) return;
+  if (k < 0 || k >= a.max_objects || !a.desc[k].registered || kernel_width(a.desc[k].hidden) != H) return;
   unsigned char* dst = (H == 32) ? a.img32 + (size_t)k * img32_bytes(BF)
                                  : a.wimage + (size_t)k * a.wimage_stride;
   stage_weights<H, BF>(a.theta + (size_t)k * a.p_stride, dst, blockIdx.x * blockDim.x + threadIdx.x,
-                       gridDim.x * blockDim.x);
+                       gridDim.x * blockDim.x, a.desc[k].hidden);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2050,7 +2063,7 @@ __global__ void __launch_bounds__(256) k_query(const QueryArgs qa) {
   if (tid < 3 * kFeatures) Bl[tid] = qa.B[tid];
   const unsigned char* wb = smem;
   if constexpr (GW) wb = qa.wimage + (size_t)qa.k * qa.wimage_stride;
-  else stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem, tid, blockDim.x);
+  else stage_weights<H, BF>(qa.theta + (size_t)qa.k * qa.p_stride, smem, tid, blockDim.x, qa.desc[qa.k].hidden);
   __syncthreads();
   const ObjDesc d = qa.desc[qa.k];
   for (int64_t chunk = (int64_t)blockIdx.x * nw + wave; chunk * kSlots < qa.n; chunk += (int64_t)gridDim.x * nw) {
@@ -2161,7 +2174,7 @@ __global__ void __launch_bounds__(256) k_reduce(const OptArgs a_in, int want_gra
   bool bad = false;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < a.p_stride) {
-    const float g = (p < P) ? tile_sum(a.partial, a.p_stride, t0, t1, p) : 0.f;
+    const float g = (p < P) ? tile_sum(a.partial, a.p_stride, t0, t1, padded_index(a.desc[k].hidden, p)) : 0.f;
     bad = !isfinite(g);
     a.grad[(size_t)k * a.p_stride + p] = g;
     if (a.grad_out) a.grad_out[(size_t)j * a.p_stride + p] = g;
@@ -2224,7 +2237,8 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     th = a.theta[i];
     m = a.m[i];
     v = a.v[i];
-    g = tile_sum(a.partial, a.p_stride, t0, t1, p);
+    // the partials hold the kernel width's layout (hidden 16: padded to 32)
+    g = tile_sum(a.partial, a.p_stride, t0, t1, (hidden == 16 && p < n_params) ? padded_index(16, p) : p);
   }
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   float loss = 0.f;
@@ -2300,11 +2314,14 @@ __global__ void __launch_bounds__(256) k_reduce_adam_wide(const OptArgs a_in) {
     const float4 z = *reinterpret_cast<const float4*>(a.v + i);
     float th[4] = {x.x, x.y, x.z, x.w}, m[4] = {y.x, y.y, y.z, y.w}, v[4] = {z.x, z.y, z.z, z.w};
     float g[4] = {0.f, 0.f, 0.f, 0.f};
+    // slot of p in the partials (hidden 16: the width-32 layout, where four parameters p..p+3
+    // with p a multiple of 4 stay four consecutive slots)
+    const int pq = padded_index(hidden, p);
     for (int tt = t0; tt < t1; tt += 8) {
       float4 q[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        q[u] = (tt + u < t1) ? *reinterpret_cast<const float4*>(a.partial + (size_t)(tt + u) * a.p_stride + p)
+        q[u] = (tt + u < t1) ? *reinterpret_cast<const float4*>(a.partial + (size_t)(tt + u) * a.p_stride + pq)
                              : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int u = 0; u < 8; ++u)
@@ -2719,7 +2736,7 @@ static hipError_t launch_tiles_t(const StepArgs& a_in, int nwaves, int grid, hip
 }
 
 int tiles_supported(int H, bool bf16) {
-  return H == 32 || H == 64 || (H == 128 && bf16) || (generic_width(H) && bf16);
+  return H == 16 || H == 32 || H == 64 || (H == 128 && bf16) || (generic_width(H) && bf16);
 }
 
 int tile_waves(int H, int requested) { return H == 32 ? requested : 4; }
@@ -2905,11 +2922,10 @@ __device__ __forceinline__ int gen_object(const int32_t* __restrict__ scan, int 
   return lo;
 }
 
-// Buffer of the deltas at layer m's outputs (m = 0..3): one per layer at hidden 16, else the two
-// buffers alternately (layer m in buffer (3 - m) mod 2). A select: indexing the kernel argument's
-// array by a run-time value would put the whole argument block in per-lane scratch memory.
+// Buffer of the deltas at layer m's outputs (m = 0..3): the two buffers alternately (layer m in
+// buffer (3 - m) mod 2). A select: indexing the kernel argument's array by a run-time value would
+// put the whole argument block in per-lane scratch memory.
 __device__ __forceinline__ uint16_t* gen_delta_out(const GenArgs& g, int m) {
-  if (g.delta4) return g.delta4 + (int64_t)m * g.layer_elems;
   return ((3 - m) & 1) ? g.delta[1] : g.delta[0];
 }
 
@@ -3428,31 +3444,29 @@ __global__ void __launch_bounds__(256) k_gen_dw(const GenArgs g_in, int l, int n
   if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
 }
 
-// Weight gradient of a layer with at most 32 outputs (every layer at hidden 16; the output layer
-// at every width): a workgroup computes outputs [0, O) x inputs [n0, n0 + 32) over one work tile
-// of an object, and its NW waves take the tile's rows in 32-row chunks in turn (chunk c to wave
-// c mod NW), each
-// in its own LDS tiles, staged as the rows lie in memory (16-byte loads, the wave's next chunk in
-// flight during the current chunk's products) and read transposed. The waves' sums are added in
-// wave order, so the result does not depend on the grid. Bias gradient: the deltas as the products
-// see them (BF16), or the output layer's FP32 seed unrounded, summed per lane over its staged rows
-// and then over lanes and waves in a fixed order. The wave count is fixed (kGenDwWaves, not chosen
-// by the size of the launch), so an object's sums do not depend on the rest of the batch; eight
-// waves leave a wave an eighth of the work tile's rows and fit two workgroups on a CU (registers).
-__global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs g_in, int l_arg) {
+// Weight gradient of the output layer (4 outputs) of the layered path: a workgroup computes
+// outputs [0, 4) x inputs [n0, n0 + 32) over one work tile of an object, and its NW waves take the
+// tile's rows in 32-row chunks in turn (chunk c to wave c mod NW), each in its own LDS tiles,
+// staged as the rows lie in memory (16-byte loads, the wave's next chunk in flight during the
+// current chunk's products) and read transposed: A = the FP32 seeds dz rounded to BF16 (the MFMA
+// operand; rows 4..31 of the tile stay zero), B = h_4. The waves' sums are added in wave order,
+// so the result does not depend on the grid. Bias gradient: the FP32 seeds unrounded, summed per
+// lane over its staged rows and then over lanes and waves in a fixed order. The wave count is
+// fixed (kGenDwWaves, not chosen by the size of the launch), so an object's sums do not depend on
+// the rest of the batch; eight waves leave a wave an eighth of the work tile's rows and fit two
+// workgroups on a CU (registers).
+__global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs g_in) {
   constexpr int NW = kGenDwWaves;
   GenArgs g = g_in;
   read_batch(g.a);
-  const int l = l_arg >= 0 ? l_arg : (int)blockIdx.z;  // l_arg < 0: every layer, one per grid z
+  constexpr int l = kLayers;
   const StepArgs& a = g.a;
   constexpr int P = kGenPitch;                   // 32 columns + 4 (elements)
   constexpr int kWaveTile = 2 * 32 * P;          // one wave's A and B tiles (uint16 elements)
   constexpr int kRed = NW * 16 * 64 + NW * 32;  // floats of the final sums: accumulators, bias sums
   __shared__ __attribute__((aligned(16))) uint16_t lds[(NW * kWaveTile > 2 * kRed) ? NW * kWaveTile : 2 * kRed];
   const int H = g.H;
-  const bool head = (l == kLayers);
-  const int K = (l == 0) ? kEnc : H;
-  const int O = head ? kOut : H;  // 4, or a hidden width of 8, 16 or 32 (the launch checks)
+  const int K = H;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   GenObj ob;
   if (!gen_work_rows(g, a, blockIdx.x, ob)) return;
@@ -3464,17 +3478,14 @@ __global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs
   uint16_t* Bs = As + 32 * P;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   typedef unsigned int u2w __attribute__((ext_vector_type(2)));
-  // columns that no piece covers (A's past O) stay zero
+  // columns that no piece covers (A's past the 4 outputs) stay zero
   for (int i = lane; i < kWaveTile / 8; i += 64) *reinterpret_cast<u4*>(As + 8 * i) = u4{0u, 0u, 0u, 0u};
-  // pieces of a 32-row chunk: B (h_l, columns n0..n0+31): p = lane + 64 q, row p / 4, columns
-  // 8 (p mod 4); A hidden (delta, columns 0..O-1): p = lane + 64 q below 32 per, row p / per,
-  // columns 8 (p mod per), per = O / 8; A of the output layer (the FP32 seed [rows][4]): lane < 32,
-  // row lane. A lane's columns are the same in every chunk.
-  const int lp = head ? 0 : (O >= 32 ? 2 : (O >= 16 ? 1 : 0)), per = 1 << lp;  // per = O / 8
+  // pieces of a 32-row chunk: B (h_4, columns n0..n0+31): p = lane + 64 q, row p / 4, columns
+  // 8 (p mod 4); A (the FP32 seed [rows][4]): lane < 32, row lane. A lane's columns are the same
+  // in every chunk.
   const uint16_t* hsrc = g.act + (int64_t)l * g.layer_elems + ob.r0 * ld + n0;
-  const uint16_t* dsrc = head ? nullptr : gen_delta_out(g, l) + ob.r0 * ld;
   const float* zsrc = g.dz + ob.r0 * kOut;
-  u4 va[2], vb[2];
+  u4 vb[2];
   float4 vz;
   auto fetch = [&](int c) {
     const int rb = c * 32;
@@ -3484,22 +3495,13 @@ __global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs
       vb[q] = u4{0u, 0u, 0u, 0u};
       if (r < nrows && n0 + cc < K) vb[q] = *reinterpret_cast<const u4*>(hsrc + (int64_t)r * ld + cc);
     }
-    if (head) {
-      vz = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (lane < 32 && rb + lane < nrows) vz = *reinterpret_cast<const float4*>(zsrc + (int64_t)(rb + lane) * kOut);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int p = lane + 64 * q, r = rb + (p >> lp);
-        va[q] = u4{0u, 0u, 0u, 0u};
-        if (p < 32 * per && r < nrows) va[q] = *reinterpret_cast<const u4*>(dsrc + (int64_t)r * ld + 8 * (p & (per - 1)));
-      }
-    }
+    vz = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < 32 && rb + lane < nrows) vz = *reinterpret_cast<const float4*>(zsrc + (int64_t)(rb + lane) * kOut);
   };
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  float dbv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this lane's columns' bias parts
+  float dbv[kOut] = {0.f, 0.f, 0.f, 0.f};  // this lane's bias parts
   if (wave * 32 < nrows) fetch(wave);
   for (int c = wave; c * 32 < nrows; c += NW) {
     wave_lds_sync();  // this wave's previous chunk has been read
@@ -3508,28 +3510,13 @@ __global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs
       const int p = lane + 64 * q;
       *reinterpret_cast<u4*>(Bs + (p >> 2) * P + 8 * (p & 3)) = vb[q];
     }
-    if (head) {
-      if (lane < 32) {
-        *reinterpret_cast<u2w*>(As + lane * P) = u2w{pack2(vz.x, vz.y), pack2(vz.z, vz.w)};
-        if (bias) {
-          dbv[0] += vz.x;
-          dbv[1] += vz.y;
-          dbv[2] += vz.z;
-          dbv[3] += vz.w;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int p = lane + 64 * q;
-        if (p < 32 * per) {
-          *reinterpret_cast<u4*>(As + (p >> lp) * P + 8 * (p & (per - 1))) = va[q];
-          if (bias) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              dbv[e] += __builtin_bit_cast(float, ((va[q][e >> 1] >> (16 * (e & 1))) & 0xffffu) << 16);
-          }
-        }
+    if (lane < 32) {
+      *reinterpret_cast<u2w*>(As + lane * P) = u2w{pack2(vz.x, vz.y), pack2(vz.z, vz.w)};
+      if (bias) {
+        dbv[0] += vz.x;
+        dbv[1] += vz.y;
+        dbv[2] += vz.z;
+        dbv[3] += vz.w;
       }
     }
     if ((c + NW) * 32 < nrows) fetch(c + NW);
@@ -3541,231 +3528,46 @@ __global__ void __launch_bounds__(kGenDwWaves * 64) k_gen_dw_small(const GenArgs
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
   }
-  // Bias parts: a butterfly over the lanes that hold the same columns (lane bits at and above
-  // log2(per); the output layer's seeds sit on lanes 0..31, the others hold zeros), leaving each
-  // wave's sums on lanes 0 .. per - 1, in a fixed order.
+  // bias parts: a butterfly over the wave's lanes (the seeds sit on lanes 0..31, the others hold
+  // zeros), leaving the wave's sums on every lane, in a fixed order
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    if (off < per) break;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dbv[e] += __shfl_xor(dbv[e], off);
+    for (int e = 0; e < kOut; ++e) dbv[e] += __shfl_xor(dbv[e], off);
   }
   __syncthreads();  // every wave is done with its tiles
   float* red = reinterpret_cast<float*>(lds);  // [NW waves][16][64], then [NW waves][32] bias sums
   float* redb = red + NW * 16 * 64;
 #pragma unroll
   for (int i = 0; i < 16; ++i) red[(wave * 16 + i) * 64 + lane] = acc[i];
-  if (lane < per) {
+  if (lane == 0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) redb[wave * 32 + 8 * lane + e] = dbv[e];
+    for (int e = 0; e < kOut; ++e) redb[wave * 32 + e] = dbv[e];
   }
   __syncthreads();
   // element i of the accumulators (output 8 (i / 4) + 4 (lane / 32) + i mod 4, input n0 + lane mod
-  // 32) is summed over the waves in wave order by wave i mod NW
+  // 32) is summed over the waves in wave order by wave i mod NW; outputs 0..3 are elements 0..3
+  // of lanes 0..31
   int bad = 0;
   const float inv = a.use_scale ? 1.0f / a.scaler->scale : 1.0f;
   float* dst = a.partial + (size_t)ob.ts * a.p_stride + layer_param_off(H, l);
-  const int m32 = lane & 31, kh = lane >> 5;
-  const int col = n0 + m32;
-  for (int i = wave; i < 16; i += NW) {
-    const int o = 8 * (i >> 2) + 4 * kh + (i & 3);
-    if (o >= O || col >= K) continue;
+  const int col = n0 + (lane & 31);
+  for (int i = wave; i < kOut; i += NW) {
+    if (lane >= 32 || col >= K) continue;
     float v = red[i * 64 + lane];
     for (int w = 1; w < NW; ++w) v += red[(w * 16 + i) * 64 + lane];
     v *= inv;
     bad |= partial_bad(v);
-    dst[(size_t)o * K + col] = v;
+    dst[(size_t)i * K + col] = v;
   }
-  if (bias && wave == 0 && lane < O) {
+  if (bias && wave == 0 && lane < kOut) {
     float v = 0.f;
-    for (int w = 0; w < NW; ++w) v += redb[w * 32 + lane];  // output o = lane: column 8 (o / 8) + o mod 8
+    for (int w = 0; w < NW; ++w) v += redb[w * 32 + lane];
     v *= inv;
     bad |= partial_bad(v);
-    dst[(size_t)O * K + lane] = v;
+    dst[(size_t)kOut * K + lane] = v;
   }
   if (__syncthreads_or(bad) && tid == 0) atomicOr(&a.flags[ob.k], 1);
-}
-
-// Hidden 16: the forward of one row tile per wave in one launch, the tile's activations kept in
-// LDS between layers: the encoding (gen_encode_row), then the five layers as k_gen_gemm computes
-// them (BF16 operands, W rounded as read, FP32 accumulation in the same K steps, bias, ReLU with
-// NaN kept, BF16 rounding; the output layer's z in FP32). Writes every layer's activations, which
-// the backward reads, and z.
-__global__ void __launch_bounds__(256) k_gen_fwd16(const GenArgs g_in) {
-  GenArgs g = g_in;
-  read_batch(g.a);
-  const StepArgs& a = g.a;
-  constexpr int H = 16, P = kEnc + 8;  // LDS row pitch: 32 features + 8 (elements)
-  __shared__ __attribute__((aligned(16))) uint16_t tiles[4 * 64 * P];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = blockIdx.x * 4 + wave;
-  const int m32 = lane & 31, kh = lane >> 5;
-  GenTile tl;
-  if (!gen_tile(g, a, t, tl)) return;  // uniform over the wave; no workgroup barrier below
-  const int nrows = (tl.hi - tl.lo) * a.S;
-  if (nrows <= 0) return;
-  const int64_t r0 = (int64_t)tl.lo * a.S;
-  const int64_t ld = g.ld;
-  uint16_t* T = tiles + wave * 64 * P;
-  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  {
-    unsigned int w[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) w[i] = 0u;
-    if (lane < nrows) gen_encode_row(a, tl, lane, w);  // rows past the tile: zeros
-    u4* lrow = reinterpret_cast<u4*>(T + lane * P);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) lrow[q] = u4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-    if (lane < nrows) {
-      u4* grow = reinterpret_cast<u4*>(g.act + (r0 + lane) * ld);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) grow[q] = u4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-    }
-  }
-  wave_lds_sync();
-  const float* th = a.theta + (size_t)tl.k * a.p_stride;
-#pragma unroll
-  for (int l = 0; l <= kLayers; ++l) {
-    const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
-    const float* W = th + layer_param_off(H, l);  // [O][K], then b [O]
-    f32x16 acc[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[rb][i] = 0.f;
-#pragma unroll
-    for (int ks = 0; ks < K / 16; ++ks) {
-      // B: output m32 (below O), inputs 16 ks + 8 kh .. + 7 of its row of W
-      u4 wb = {0u, 0u, 0u, 0u};
-      if (m32 < O) {
-        const float4 x0 = *reinterpret_cast<const float4*>(W + m32 * K + 16 * ks + 8 * kh);
-        const float4 x1 = *reinterpret_cast<const float4*>(W + m32 * K + 16 * ks + 8 * kh + 4);
-        wb = u4{pack2(x0.x, x0.y), pack2(x0.z, x0.w), pack2(x1.x, x1.y), pack2(x1.z, x1.w)};
-      }
-      const bf16x8 bv = __builtin_bit_cast(bf16x8, wb);
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(T + (32 * rb + m32) * P + 16 * ks + 8 * kh);
-        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[rb], 0, 0, 0);
-      }
-    }
-    wave_lds_sync();  // the layer's inputs have been read
-    const float b = (m32 < O) ? W[O * K + m32] : 0.f;
-    // element 4 jj + i of acc[rb]: row 32 rb + 8 jj + 4 kh + i, output m32
-    if (l < kLayers) {
-      if (m32 < O) {
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
-            float y = acc[rb][i] + b;
-            y = (y <= 0.f) ? 0.f : y;  // ReLU (a NaN stays NaN)
-            T[r * P + m32] = (uint16_t)(pack2(y, 0.f) & 0xffffu);
-          }
-      }
-      wave_lds_sync();
-      if (lane < nrows) {  // h_{l+1}: the row's 16 BF16 (32 bytes)
-        const u4* lrow = reinterpret_cast<const u4*>(T + lane * P);
-        u4* grow = reinterpret_cast<u4*>(g.act + (int64_t)(l + 1) * g.layer_elems + (r0 + lane) * ld);
-        grow[0] = lrow[0];
-        grow[1] = lrow[1];
-      }
-    } else if (m32 < O) {
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
-          if (r < nrows) g.z[(r0 + r) * kOut + m32] = acc[rb][i] + b;
-        }
-    }
-  }
-}
-
-// Hidden 16: the input-gradient chain of one row tile per wave in one launch, from the output
-// layer's seeds dz down to the deltas at layer 0's outputs, as k_gen_gemm<GEN_DX> computes each
-// (BF16 operands: the deltas, or dz rounded; W rounded as read; FP32 accumulation; BF16 rounding),
-// each masked by ReLU' of the layer below (its BF16 output +0 exactly where the unit is inactive),
-// written to its own delta buffer and kept in LDS as the next product's operand.
-__global__ void __launch_bounds__(256) k_gen_dx16(const GenArgs g_in) {
-  GenArgs g = g_in;
-  read_batch(g.a);
-  const StepArgs& a = g.a;
-  constexpr int H = 16, P = H + 8;  // LDS row pitch (elements)
-  __shared__ __attribute__((aligned(16))) uint16_t tiles[4 * 64 * P];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = blockIdx.x * 4 + wave;
-  const int m32 = lane & 31, kh = lane >> 5;
-  GenTile tl;
-  if (!gen_tile(g, a, t, tl)) return;  // uniform over the wave; no workgroup barrier below
-  const int nrows = (tl.hi - tl.lo) * a.S;
-  if (nrows <= 0) return;
-  const int64_t r0 = (int64_t)tl.lo * a.S;
-  const int64_t ld = g.ld;
-  uint16_t* T = tiles + wave * 64 * P;
-  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  const float* th = a.theta + (size_t)tl.k * a.p_stride;
-#pragma unroll
-  for (int l = kLayers; l >= 1; --l) {
-    const int O = (l == kLayers) ? kOut : H;      // outputs of layer l: the K index here
-    const float* W = th + layer_param_off(H, l);  // [O][16]
-    // B: input m32 (below 16), outputs 8 kh .. + 7 (below O): W[o][m32]
-    float x[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int o = 8 * kh + e;
-      x[e] = (m32 < H && o < O) ? W[o * H + m32] : 0.f;
-    }
-    const bf16x8 bv = __builtin_bit_cast(
-        bf16x8, u4{pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]), pack2(x[6], x[7])});
-    f32x16 acc[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      bf16x8 av;
-      if (l == kLayers) {  // the seeds, FP32 [rows][4], rounded: K index 0..3 on the first half
-        u4 v = {0u, 0u, 0u, 0u};
-        const int r = 32 * rb + m32;
-        if (kh == 0 && r < nrows) {
-          const float4 d4 = *reinterpret_cast<const float4*>(g.dz + (r0 + r) * kOut);
-          v = u4{pack2(d4.x, d4.y), pack2(d4.z, d4.w), 0u, 0u};
-        }
-        av = __builtin_bit_cast(bf16x8, v);
-      } else {
-        av = *reinterpret_cast<const bf16x8*>(T + (32 * rb + m32) * P + 8 * kh);
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[rb][i] = 0.f;
-      acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[rb], 0, 0, 0);
-    }
-    wave_lds_sync();  // the previous deltas have been read
-    if (m32 < H) {
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = 32 * rb + 8 * (i >> 2) + 4 * kh + (i & 3);
-          T[r * P + m32] = (uint16_t)(pack2(acc[rb][i], 0.f) & 0xffffu);
-        }
-    }
-    wave_lds_sync();
-    if (lane < nrows) {  // mask the row, write the deltas at layer l - 1's outputs, keep them
-      u4* lrow = reinterpret_cast<u4*>(T + lane * P);
-      const u4* hrow = reinterpret_cast<const u4*>(g.act + (int64_t)l * g.layer_elems + (r0 + lane) * ld);
-      u4* drow = reinterpret_cast<u4*>(gen_delta_out(g, l - 1) + (r0 + lane) * ld);
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        u4 v = lrow[q];
-        const u4 h = hrow[q];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const unsigned int lo = (h[e] & 0xffffu) ? 0xffffu : 0u, hi = (h[e] >> 16) ? 0xffff0000u : 0u;
-          v[e] &= lo | hi;
-        }
-        lrow[q] = v;
-        drow[q] = v;
-      }
-    }
-    wave_lds_sync();
-  }
 }
 
 // Rendering, loss and (training) the adjoint of one row tile per wave, by the fused kernels'
@@ -3854,10 +3656,8 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   if (!generic_width(g.H) || g.a.S < 1 || g.a.S > kSlots || blocks_bound <= 0 || work_bound <= 0 ||
       g.work_rays < 1)
     return hipErrorInvalidValue;
-  // k_gen_dw_small stages a narrow hidden layer's deltas in 8-column runs, 1, 2 or 4 per row
-  if (g.H <= 32 && g.H != 8 && g.H != 16 && g.H != 32) return hipErrorInvalidValue;
-  // hidden 16 keeps every layer's deltas (four buffers); the wide products read W in BF16
-  if ((g.H == 16 && !g.delta4) || (keeps_gimg(g.H) && !g.a.gimg)) return hipErrorInvalidValue;
+  // the wide products read W from the BF16 parameter copy
+  if (keeps_gimg(g.H) && !g.a.gimg) return hipErrorInvalidValue;
   const bool train = (mode == MODE_TRAIN);
   const int H = g.H;
   const int wave_blocks = (tiles_bound + 3) / 4;
@@ -3878,18 +3678,6 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
     }
   };
   hipLaunchKernelGGL(k_gen_tiles, dim3(1), dim3(1024), 0, s, g);
-  if (H == 16) {  // one launch per direction through all layers, then every weight gradient at once
-    hipLaunchKernelGGL(k_gen_fwd16, dim3(wave_blocks), dim3(256), 0, s, g);
-    if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_gen_render<false>, dim3(wave_blocks), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(k_gen_loss, dim3((g.a.n_objects + 3) / 4), dim3(256), 0, s, g);
-    if (train) {
-      hipLaunchKernelGGL(k_gen_dx16, dim3(wave_blocks), dim3(256), 0, s, g);
-      const dim3 grid(work_bound, 1, kLayers + 1);  // inputs 32 or 16: one 32-column block
-      hipLaunchKernelGGL(k_gen_dw_small, grid, dim3(kGenDwWaves * 64), 0, s, g, -1);
-    }
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL(k_gen_encode, dim3(wave_blocks), dim3(256), 0, s, g);
   for (int l = 0; l <= kLayers; ++l) fwd_dx(GEN_FWD, (l == kLayers) ? kOut : H, l);
   if (train) hipLaunchKernelGGL(k_gen_render<true>, dim3(wave_blocks), dim3(256), 0, s, g);
@@ -3898,9 +3686,8 @@ hipError_t launch_generic(int mode, const GenArgs& g, int tiles_bound, int block
   if (train) {
     for (int l = kLayers; l >= 0; --l) {
       const int K = (l == 0) ? kEnc : H, O = (l == kLayers) ? kOut : H;
-      if (O <= 32) {
-        hipLaunchKernelGGL(k_gen_dw_small, dim3(work_bound, blocks(K, 32)), dim3(kGenDwWaves * 64), 0, s, g, l);
-      }
+      if (l == kLayers)
+        hipLaunchKernelGGL(k_gen_dw_small, dim3(work_bound, blocks(K, 32)), dim3(kGenDwWaves * 64), 0, s, g);
       else if (O >= 128 && K >= 128) {
         const int nb = blocks(O, 128) * blocks(K, 128);
         hipLaunchKernelGGL(k_gen_dw<128>, grid1(work_bound, nb), dim3(256), 0, s, g, l, nb);

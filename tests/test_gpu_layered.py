@@ -1,4 +1,4 @@
-"""GPU parity of the layered path (hidden 16, 256, 512, 1024 in BF16) against the FP64 oracle.
+"""GPU parity of the layered path (hidden 256, 512, 1024 in BF16) against the FP64 oracle.
 
 These widths have no fused tile kernel: the step runs as a chain of launches over activations in
 device memory (encoding, one product launch per layer forward, rendering, one launch per layer
@@ -27,7 +27,7 @@ if not torch.cuda.is_available():  # collected on CPU hosts, never run there
 
 import paper_2302_01838_amd as vm  # noqa: E402
 
-WIDTHS = [16, 256, 512, 1024]
+WIDTHS = [256, 512, 1024]
 
 
 def _scene(H, S=None, widths=None):
@@ -51,7 +51,7 @@ def test_layered_train_step_parity(H):
     check_step(errs, errs16, "bf16")
 
 
-@pytest.mark.parametrize("H", [16, 256])
+@pytest.mark.parametrize("H", [256, 512])
 def test_layered_forward_parity(H):
     sc = _scene(H)
     objs, states = make_pair(sc, "bf16")
@@ -66,7 +66,7 @@ def test_layered_forward_parity(H):
         assert v <= 2e-2
 
 
-@pytest.mark.parametrize("H,S", [(16, 17), (256, 17), (16, 1), (256, 64)])
+@pytest.mark.parametrize("H,S", [(256, 17), (512, 1), (256, 64)])
 def test_layered_ragged_rays(H, S):
     """Objects of 1, 7, 64 and 33 rays; S = 17 leaves 13 of 64 rows of each row tile empty, S = 1
     gives 64 one-sample rays per tile, S = 64 one ray per tile."""
@@ -94,7 +94,7 @@ def test_layered_row_block_edges(H, S, rays):
     check_step(errs, errs16, "bf16")
 
 
-@pytest.mark.parametrize("H", [16, 256])
+@pytest.mark.parametrize("H", [256, 512])
 def test_layered_object_over_several_work_tiles(H):
     """An object of 10,000 rows (1,000 rays of 10 samples) has its weight gradient summed over
     three work tiles of about 4,096 rows (partials added in order by the optimiser), next to small
@@ -108,7 +108,7 @@ def test_layered_object_over_several_work_tiles(H):
     check_step(errs, errs16, "bf16")
 
 
-@pytest.mark.parametrize("H", [16, 256])
+@pytest.mark.parametrize("H", [256, 512])
 def test_layered_results_independent_of_batch(H):
     """Four objects stepped alone and inside the whole 50-object uneven batch (several times the
     work tiles, so every launch grid differs) end with the same losses and states bit for bit:
@@ -210,7 +210,8 @@ def test_layered_bitwise_invariants():
 
 
 def test_layered_width_rules():
-    """One layered width per stack; layered widths need a layered max_hidden; no point queries."""
+    """One layered width per stack; layered widths need a layered max_hidden; BF16 only; no point
+    queries."""
     sc = _scene(256)
     objs = vm.ObjectSet(max_objects=4, B=sc.B, hidden=256, precision="bf16", max_rays=512,
                         max_samples_per_ray=sc.S, max_hidden=512)
@@ -221,5 +222,5 @@ def test_layered_width_rules():
     with pytest.raises(vm.VmapError):
         objs.query(0, np.zeros((4, 3), np.float32))
     with pytest.raises(vm.VmapError):
-        vm.ObjectSet(max_objects=4, B=sc.B, hidden=16, precision="fp32", max_rays=512,
+        vm.ObjectSet(max_objects=4, B=sc.B, hidden=256, precision="fp32", max_rays=512,
                      max_samples_per_ray=sc.S)

@@ -1,5 +1,5 @@
-"""Weight images of width-32 objects and the BF16 parameter copies of wide layered-path objects,
-through the C ABI.
+"""Weight images of width-32 (and zero-padded width-16) objects and the BF16 parameter copies of
+wide layered-path objects, through the C ABI.
 
 The tile kernel stages a width-32 object's weights by copying its weight image: the object's
 parameters already in the byte layout of the LDS staging (BF16 with transposed copies and bias
@@ -9,6 +9,8 @@ object set normally and a twin whose images are rewritten whole from its paramet
 update (a set_state of each object's own parameters); every loss, render and state must agree
 bitwise, so the incremental image writes put every parameter where the whole staging does.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -38,9 +40,13 @@ def _same(a, b, ids):
         assert a.get_state(k, vm.STATE_STEP) == b.get_state(k, vm.STATE_STEP)
 
 
+@pytest.mark.parametrize("H", [32, 16])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_images_after_training_steps_match_whole_staging(precision):
+def test_images_after_training_steps_match_whole_staging(precision, H):
+    """Hidden 16 keeps the zero-padded width-32 image: the optimiser writes its parameters into
+    their padded slots and leaves the padding zero."""
     sc = scaled(scenes.make_scene("k50_uneven"), 10)
+    sc = dataclasses.replace(sc, objects=[dataclasses.replace(o, hidden=H) for o in sc.objects])
     ids = range(sc.n_objects)
     inc, _ = make_pair(sc, precision)
     whole, _ = make_pair(sc, precision)
@@ -49,7 +55,7 @@ def test_images_after_training_steps_match_whole_staging(precision):
         l1 = inc.step(db).cpu().numpy()
         l2 = whole.step(db).cpu().numpy()
         torch.cuda.synchronize()
-        print(f"[image] {precision} step {s}: loss sum {l1.sum():.6g}", flush=True)
+        print(f"[image] {precision} H={H} step {s}: loss sum {l1.sum():.6g}", flush=True)
         assert np.array_equal(l1, l2), s
         _restage(whole, ids)
     _same(inc, whole, ids)

@@ -60,7 +60,23 @@ def test_wide_models_bf16_only(lib):
     assert lib.vmap_object_params(ctypes.byref(vm.default_config(hidden=32)), 128) == 0
 
 
-@pytest.mark.parametrize("H", [16, 256, 512, 1024])
+def test_hidden16_runs_in_width32_kernels(lib):
+    """Hidden 16 trains in both precisions, zero-padded into the width-32 kernels: its own
+    parameter count (the pinned layout), and the state and workspace of a width-32 stack (its
+    parameter slots and tile partials keep the width-32 stride)."""
+    for prec in (vm.VMAP_FP32, vm.VMAP_BF16):
+        kw = dict(max_objects=8, precision=prec, max_rays=4096, max_samples_per_ray=20)
+        c16 = vm.default_config(hidden=16, **kw)
+        c32 = vm.default_config(hidden=32, **kw)
+        assert lib.vmap_object_params(ctypes.byref(c16), 16) == 33 * 16 + 3 * (16 * 16 + 16) + 4 * 16 + 4
+        assert lib.vmap_state_bytes(ctypes.byref(c16)) == lib.vmap_state_bytes(ctypes.byref(c32)) > 0
+        assert lib.vmap_workspace_bytes(ctypes.byref(c16)) == lib.vmap_workspace_bytes(ctypes.byref(c32)) > 0
+    mixed = vm.default_config(hidden=16, max_hidden=256, precision=vm.VMAP_BF16)
+    assert lib.vmap_state_bytes(ctypes.byref(mixed)) > 0
+    assert lib.vmap_object_params(ctypes.byref(mixed), 16) == 1412
+
+
+@pytest.mark.parametrize("H", [256, 512, 1024])
 def test_layered_widths_bf16_only(lib, H):
     """Widths of the layered path: BF16 only, a layered max_hidden, parameter counts of the
     pinned layout (32H + H + 3(H^2 + H) + 4H + 4), and workspace for the activations of
@@ -72,9 +88,7 @@ def test_layered_widths_bf16_only(lib, H):
     assert wb >= 7 * 1000 * 10 * max(32, H) * 2
     assert lib.vmap_state_bytes(ctypes.byref(vm.default_config(hidden=H))) == 0  # FP32
     mixed = vm.default_config(hidden=32, max_hidden=H, precision=vm.VMAP_BF16)
-    assert (lib.vmap_state_bytes(ctypes.byref(mixed)) > 0) == (H > 32)
-    bad = vm.default_config(hidden=16, max_hidden=64, precision=vm.VMAP_BF16)
-    assert lib.vmap_state_bytes(ctypes.byref(bad)) == 0
+    assert lib.vmap_state_bytes(ctypes.byref(mixed)) > 0
 
 
 @pytest.mark.parametrize("field,value", [("max_objects", 0), ("n_features", 8),
