@@ -209,7 +209,8 @@ class ObjectSet:
         self.tuned = None
         if rays_per_tile == 0 and autotune:
             from .tune import lookup
-            self.tuned = lookup(hidden, max_samples_per_ray, precision)
+            # hidden 16 runs in the width-32 kernels (zero-padded) and takes their tuned shape
+            self.tuned = lookup(32 if hidden == 16 else hidden, max_samples_per_ray, precision)
             if self.tuned:
                 rays_per_tile = int(self.tuned["rays_per_tile"])
         if rays_per_tile_wide == 0 and autotune and (max_hidden or hidden) > 32:
