@@ -385,6 +385,8 @@ OptArgs make_opt_args(vmap_ctx* c, const vmap_batch* b, float* loss_out, float* 
   a.growth = c->cfg.scale_growth_interval;
   a.max_tiles = c->wl.max_tiles;
   a.img32 = c->img32();
+  a.wimage = c->wimage();
+  a.wimage_stride = (int64_t)c->wl.wimage_stride;
   a.gimg = c->gimg();
   return a;
 }
@@ -463,13 +465,12 @@ int enqueue_tiles(vmap_ctx* c, const vmap_batch* b, int mode, const float* dloss
       if (e != hipSuccess) return c->hip_fail(e, "layered-path launch");
       continue;
     }
-    hipError_t e = launch_stage_images(H, bf, a, -1, si);
-    if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
-    // this width's tiles are at most ceil(rays / its rays per tile) + objects: wider tiles need
-    // fewer workgroups than the stack's smallest tile size gives (the kernels stride over tiles)
+    // The weight images are current (staged when parameters are set, then kept by the optimiser).
+    // This width's tiles are at most ceil(rays / its rays per tile) + objects: wider tiles need
+    // fewer workgroups than the stack's smallest tile size gives (the kernels stride over tiles).
     const int rpt_h = tile_rays(H, c->rays_per_tile, c->rays_per_tile_wide);
     const int grid_h = std::min(grid, (b->n_rays_total + rpt_h - 1) / rpt_h + b->n_objects);
-    e = launch_tiles(H, bf, mode, a, c->waves, grid_h, si);
+    hipError_t e = launch_tiles(H, bf, mode, a, c->waves, grid_h, si);
     if (e != hipSuccess) return c->hip_fail(e, "tile kernel launch");
   }
   if (fork) {
@@ -657,21 +658,26 @@ int vmap_init_objects(const vmap_config* cfg, const float* B_host, void* state_d
   return VMAP_OK;
 }
 
-// The weight image of object k (width 32), or its BF16 parameter copy (layered path, hidden 128
-// and up), from its current parameters.
+// The weight image of object k (width 32, or the BF16 image of hidden 128), or its BF16 parameter
+// copy (layered path, hidden 256 and up), from its current parameters. The optimiser kernels keep
+// them current after each update.
 hipError_t restage_image(vmap_ctx* c, int k, hipStream_t s) {
   if (keeps_gimg(c->objs[k].hidden)) {
     uint16_t* gimg = c->gimg();
     return gimg ? launch_stage_gimg(c->theta(), gimg, k, c->p_stride, s) : hipSuccess;
   }
-  if (kernel_width(c->objs[k].hidden) != 32) return hipSuccess;
+  const int kw = kernel_width(c->objs[k].hidden);
+  if (kw != 32 && !weights_global(kw)) return hipSuccess;
   StepArgs a{};
   a.max_objects = c->cfg.max_objects;
   a.theta = c->theta();
   a.p_stride = c->p_stride;
   a.desc = c->desc();
   a.img32 = c->img32();
+  a.wimage = c->wimage();
+  a.wimage_stride = (int64_t)c->wl.wimage_stride;
   a.gimg = c->gimg();
+  if (weights_global(kw)) return launch_stage_images(kw, c->cfg.precision == VMAP_BF16, a, k, s);
   return launch_stage_image32(c->cfg.precision == VMAP_BF16, a, k, s);
 }
 
@@ -989,18 +995,7 @@ int vmap_query_occupancy(vmap_ctx* c, int32_t k, const float* pts, int64_t n, fl
   q.wimage_stride = (int64_t)c->wl.wimage_stride;
   q.max_objects = c->cfg.max_objects;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (weights_global(H)) {
-    StepArgs a{};
-    a.max_objects = c->cfg.max_objects;
-    a.theta = c->theta();
-    a.p_stride = c->p_stride;
-    a.desc = c->desc();
-    a.wimage = c->wimage();
-    a.wimage_stride = (int64_t)c->wl.wimage_stride;
-    hipError_t e = launch_stage_images(H, bf, a, k, s);
-    if (e != hipSuccess) return c->hip_fail(e, "weight image launch");
-  }
-  hipError_t e = launch_query(H, bf, q, s);
+  hipError_t e = launch_query(H, bf, q, s);  // a hidden-128 object's image is current
   if (e != hipSuccess) return c->hip_fail(e, "query launch");
   return VMAP_OK;
 }

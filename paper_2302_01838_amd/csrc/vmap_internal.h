@@ -348,6 +348,8 @@ struct OptArgs {
   const int32_t* t_next;      // per batch object, from k_worklist
   const int32_t* tile_bad;    // [tiles] non-finite partial per tile (MODE_STEP), or NULL: flags
   unsigned char* img32;       // weight images of width-32 objects [max_objects][img32_bytes]
+  unsigned char* wimage;      // BF16 weight images of hidden-128 objects [max_objects][stride], or NULL
+  int64_t wimage_stride;
   uint16_t* gimg;             // BF16 copies of the parameters of layered-path objects of hidden
                               // 128 or more [max_objects][p_stride], or NULL
   int p_stride;

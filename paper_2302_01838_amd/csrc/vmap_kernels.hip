@@ -854,11 +854,15 @@ __device__ AdamCoef adam_coef(const OptArgs& a, int t) {
 }
 
 // Parameter p of object k changed to th: its entry in the object's weight image (width 32, also
-// for hidden 16, whose image is the zero-padded width-32 one), or in its BF16 parameter copy
-// (layered path, hidden 128 and up).
+// for hidden 16, whose image is the zero-padded width-32 one; the BF16 image of hidden 128), or
+// in its BF16 parameter copy (layered path, hidden 256 and up).
 __device__ __forceinline__ void update_image(const OptArgs& a, int k, int hidden, int p, float th) {
   if (a.gimg && keeps_gimg(hidden)) {
     a.gimg[(size_t)k * a.p_stride + p] = (uint16_t)(pack2(th, 0.f) & 0xffffu);
+    return;
+  }
+  if (hidden == 128) {
+    if (a.wimage && a.bf16) place_param<128, true>(a.wimage + (size_t)k * a.wimage_stride, p, th);
     return;
   }
   if (!a.img32 || kernel_width(hidden) != 32) return;
@@ -1530,7 +1534,8 @@ __global__ void __launch_bounds__((BF && H == 32) ? 512 : 256, 1) k_step_tiles(c
 // the weight-gradient accumulators, and the tile needs no cross-wave reduction: the waves' slices
 // are disjoint. For H = 128 the weights and their BF16 transposes do not fit in LDS beside the
 // staging tiles: they are read from the object's weight image in device memory (the byte layout
-// of the LDS staging, written by k_stage_image for this step), and each wave accumulates its
+// of the LDS staging, staged when the parameters are set and kept current by the optimiser
+// kernels), and each wave accumulates its
 // gradient slice in the tile's partial in device memory, layer by layer, not in registers.
 
 template <int H, bool BF, int MODE>
@@ -2031,8 +2036,9 @@ __global__ void __launch_bounds__(256, 1) k_step_coop(const StepArgs a_in) {
   }
 }
 
-// Weight images of wide objects for one step: block (x, j) stages a share of batch object j's
-// parameters (or of object `single`).
+// Weight image of object `single` (width 32, or hidden 128 in BF16) from its parameters, when they
+// are set (added, or written through vmap_set_state); the optimiser kernels keep it current after
+// that. With single < 0, block (x, j) stages a share of batch object j's image.
 template <int H, bool BF>
 __global__ void __launch_bounds__(256) k_stage_image(const StepArgs a_in, int single) {
   StepArgs a = a_in;

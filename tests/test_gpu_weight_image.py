@@ -64,6 +64,29 @@ def test_images_after_training_steps_match_whole_staging(precision, H):
         assert torch.equal(a, b)
 
 
+def test_hidden128_image_after_training_steps_matches_whole_staging():
+    """The BF16 image of a hidden-128 object (the room's background width, read by the
+    cooperative kernel from device memory) is kept by the optimiser as well, not restaged per
+    step."""
+    sc = scenes.make_scene("tiny_k4")
+    sc = dataclasses.replace(sc, objects=[dataclasses.replace(o, hidden=(128 if k == 1 else 32))
+                                          for k, o in enumerate(sc.objects)])
+    inc, _ = make_pair(sc, "bf16")
+    whole, _ = make_pair(sc, "bf16")
+    for s in range(3):
+        db = vm.DeviceBatch(scenes.make_batch(sc, s))
+        l1 = inc.step(db).cpu().numpy()
+        l2 = whole.step(db).cpu().numpy()
+        torch.cuda.synchronize()
+        print(f"[image] hidden 128 step {s}: loss sum {l1.sum():.6g}", flush=True)
+        assert np.array_equal(l1, l2), s
+        _restage(whole, range(4))
+    _same(inc, whole, range(4))
+    pts = scenes.make_points(sc, 1, 500, seed=3)
+    for a, b in zip(inc.query(1, pts), whole.query(1, pts)):
+        assert torch.equal(a, b)
+
+
 def test_images_after_autograd_adam_step():
     """The autograd split's Adam kernel keeps the images current as well."""
     sc = scenes.make_scene("tiny_k4")
