@@ -112,7 +112,7 @@ def batch_flops(scene, db) -> float:
 
 
 def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
-             rays_per_tile_wide=0, split_step=False):
+             rays_per_tile_wide=0, split_step=False, device_sampling=False):
     import torch
     import paper_2302_01838_amd as vm
     nrays = max(db.n_rays for db in dev_batches)
@@ -123,17 +123,28 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     for ob in scene.objects:
         objs.add(ob.norm_centre, ob.norm_scale, hidden=ob.hidden, seed=ob.seed)
     objs.set_graph_mode(graph)
+    # with device sampling each step first draws its batch's sample depths on the GPU (Eqs. 1-2,
+    # into the batch's t) from the rays' bounds and guide depths, with a new seed per step
+    sigma = scene.near[1] if scene.near[0] == "normal" else scene.near[1] / 3.0 ** 0.5
+    draws = [0]
+
+    def step(db, losses=None):
+        if device_sampling:
+            tn, tf, tg = db.sampling
+            objs.sample_rays(tn, tf, tg, db.S, scene.n_strat, sigma, seed=draws[0], out=db["t"])
+            draws[0] += 1
+        objs.step(db, losses)
     n_obj = scene.n_objects
     loss_hist = torch.zeros(warmup + steps, n_obj, device="cuda")
     for i in range(warmup):
-        objs.step(dev_batches[i % len(dev_batches)], loss_hist[i])
+        step(dev_batches[i % len(dev_batches)], loss_hist[i])
     torch.cuda.synchronize()
     # two events only: an event between steps is a marker the GPU waits on (about 5 us each)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
     for i in range(steps):
-        objs.step(dev_batches[(warmup + i) % len(dev_batches)], loss_hist[warmup + i])
+        step(dev_batches[(warmup + i) % len(dev_batches)], loss_hist[warmup + i])
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -145,7 +156,7 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev + 1)]
     evs[0].record()
     for i in range(n_ev):
-        objs.step(dev_batches[(warmup + i) % len(dev_batches)])
+        step(dev_batches[(warmup + i) % len(dev_batches)])
         evs[i + 1].record()
     torch.cuda.synchronize()
     per_step = [evs[i].elapsed_time(evs[i + 1]) for i in range(10, n_ev)]
@@ -157,7 +168,7 @@ def run_form(precision, scene, dev_batches, steps, warmup, graph, timing_steps,
     objs.set_graph_mode(False)
     objs.kernel_timing(1)
     for i in range(timing_steps):
-        objs.step(dev_batches[i % len(dev_batches)])
+        step(dev_batches[i % len(dev_batches)])
     torch.cuda.synchronize()
     k_ms, k_n = objs.kernel_timing(0)
     k_samples = statistics.mean(dev_batches[i % len(dev_batches)].n_samples for i in range(timing_steps))
@@ -424,6 +435,9 @@ def main():
                     help="tile size of objects wider than 32 (0: the library default)")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOAD_TEXT),
                     help="k50_uneven is the headline workload; the others are reported in the docs")
+    ap.add_argument("--device-sampling", action="store_true",
+                    help="draw every step's sample depths on the GPU (vmap_sample_rays) before "
+                         "the step: the end-to-end rate; not the headline configuration")
     ap.add_argument("--hidden", type=int, default=0,
                     help="give every object of the workload this width (the layered widths 16, "
                          "256, 512, 1024 train in BF16 only); not the headline configuration")
@@ -475,7 +489,7 @@ def main():
         import dataclasses
         scene = dataclasses.replace(scene, objects=[dataclasses.replace(o, hidden=args.hidden)
                                                     for o in scene.objects])
-    headline = args.workload == WORKLOAD and not args.hidden
+    headline = args.workload == WORKLOAD and not args.hidden and not args.device_sampling
     n_batches = args.distinct_batches or (args.warmup + args.steps)
     log(f"generating {n_batches} batches of {args.workload}")
     batches = gen_batches(scene, n_batches)
@@ -491,6 +505,10 @@ def main():
 
     vm.load_library()
     dev_batches = [vm.DeviceBatch(b) for b in batches]
+    if args.device_sampling:  # each batch's ray bounds and guide depths, resident like the batch
+        for db, b in zip(dev_batches, batches):
+            db.sampling = tuple(torch.as_tensor(b[k]).to("cuda").contiguous()
+                                for k in ("t_near", "t_far", "t_guide"))
     torch.cuda.synchronize()
 
     forms = {}
@@ -499,7 +517,7 @@ def main():
         forms[prec] = run_form(prec, scene, dev_batches, args.steps, args.warmup,
                                bool(args.graph), timing_steps=min(args.steps, 50),
                                rays_per_tile_wide=args.rays_per_tile_wide,
-                               split_step=args.split_step)
+                               split_step=args.split_step, device_sampling=args.device_sampling)
         log(f"form {prec}: {forms[prec]['ms_per_step']:.4f} ms/step, "
             f"{forms[prec]['ray_samples_per_s']:.4g} samples/s, final loss "
             f"{forms[prec]['final_loss']:.6g}")
@@ -541,7 +559,8 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload]
-                   + (f", every object at hidden {args.hidden}" if args.hidden else ""),
+                   + (f", every object at hidden {args.hidden}" if args.hidden else "")
+                   + (", sample depths drawn on the GPU every step" if args.device_sampling else ""),
                    "objects": scene.n_objects, "samples_per_step": dev_batches[0].n_samples,
                    "graph": bool(args.graph), "parallelism": "single GPU",
                    "launch": {k: v for k, v in head.get("launch", {}).items()}},

@@ -397,13 +397,18 @@ class ObjectSet:
         return occ, rgb
 
     def sample_rays(self, t_near, t_far, depth, S: int, n_strat: int, sigma: float = 0.03,
-                    seed: int = 0):
-        """Depth-guided, sorted sample depths [R, S] on the device (Sec. 3.3, Eqs. 1-2)."""
+                    seed: int = 0, out=None):
+        """Depth-guided, sorted sample depths [R, S] on the device (Sec. 3.3, Eqs. 1-2), into
+        ``out`` (a contiguous FP32 device tensor of R x S values, e.g. a batch's ``t``) if given."""
         torch = _torch()
         f = lambda x: torch.as_tensor(x).to(device=self.device, dtype=torch.float32).contiguous()
         tn, tf, d = f(t_near), f(t_far), f(depth)
         R = tn.numel()
-        out = torch.empty(R, S, dtype=torch.float32, device=self.device)
+        if out is None:
+            out = torch.empty(R, S, dtype=torch.float32, device=self.device)
+        elif (out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != R * S
+              or out.device != self.device):
+            raise ValueError("out must be a contiguous float32 tensor of n_rays x S on the stack's device")
         ptr = lambda x: x.data_ptr() if R else None
         self._check(self.lib.vmap_sample_rays(self.ctx, R, S, n_strat, ptr(tn), ptr(tf), ptr(d),
                                               float(sigma), int(seed) & ((1 << 64) - 1),

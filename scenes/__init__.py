@@ -318,7 +318,9 @@ def make_batch(scene: Scene, step: int = 0, object_ids: Optional[List[int]] = No
     per-object ray counts (zero allowed). Keys: object_ids [n], ray_offsets [n+1], rays_o
     [R,3], rays_d [R,3], t [R,S], depth [R], rgb [R,3], mask [R], S; with ``pixel_radius``
     (radians) also var [R,S] = (pixel_radius t)^2, the variance of an isotropic Gaussian as wide
-    as the pixel's footprint at each sample.
+    as the pixel's footprint at each sample. Also t_near, t_far [R] (the sampling interval) and
+    t_guide [R] (the depth the samples of ``t`` were guided by: the noisy depth where the ray
+    hits, else the far bound or the occluder), for sampling on the device.
     """
     if object_ids is None:
         object_ids = [k for k, ob in enumerate(scene.objects) if ob.join_step <= step]
@@ -335,7 +337,7 @@ def make_batch(scene: Scene, step: int = 0, object_ids: Optional[List[int]] = No
             t_s = np.where(mask, depth, t_s)
         t = _samples(rng, scene, t_n, t_s)
         rgb = np.where(mask[:, None], scene.objects[k].rgb[None, :], 0.0)
-        parts.append((o, d, t, depth, rgb, mask.astype(np.float64)))
+        parts.append((o, d, t, depth, rgb, mask.astype(np.float64), t_n, t_f, t_s))
     S = scene.S
     offs = np.zeros(len(object_ids) + 1, dtype=np.int32)
     offs[1:] = np.cumsum(counts)
@@ -349,7 +351,8 @@ def make_batch(scene: Scene, step: int = 0, object_ids: Optional[List[int]] = No
     t = np.sort(t, axis=1)
     out = dict(object_ids=np.asarray(object_ids, dtype=np.int32), ray_offsets=offs,
                rays_o=cat(0, (0, 3)), rays_d=cat(1, (0, 3)), t=t, depth=cat(3, (0,)),
-               rgb=cat(4, (0, 3)), mask=cat(5, (0,)), S=S)
+               rgb=cat(4, (0, 3)), mask=cat(5, (0,)), S=S,
+               t_near=cat(6, (0,)), t_far=cat(7, (0,)), t_guide=cat(8, (0,)))
     if pixel_radius is not None:
         out["var"] = (np.float64(pixel_radius) * t.astype(np.float64)) ** 2
         out["var"] = out["var"].astype(np.float32)

@@ -388,6 +388,10 @@ def test_depth_guided_sampling_matches_oracle(S, n_strat):
     assert np.all(np.diff(t, axis=1) >= 0)
     np.testing.assert_allclose(t, ref, rtol=2.5e-7, atol=0)
     report(f"sampling S={S} n_strat={n_strat}", max_rel=float(np.max(np.abs(t - ref) / np.abs(ref))))
+    # into a given tensor (a batch's t): the same values, bit for bit
+    out = torch.full((R, S), float("nan"), device="cuda")
+    got = objs.sample_rays(tn, tf, depth, S, n_strat, sigma=0.03, seed=seed, out=out)
+    assert got is out and np.array_equal(out.cpu().numpy().view(np.uint32), t.view(np.uint32))
 
 
 # ------------------------------------------------------------------------ integrated encoding
