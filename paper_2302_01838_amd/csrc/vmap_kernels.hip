@@ -2886,16 +2886,17 @@ hipError_t launch_init_scaler(ScalerState* sc, float scale, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Layered path (widths without a fused tile kernel: hidden 16, 256, 512, 1024; BF16). The step
+// Layered path (widths without a fused tile kernel: hidden 256, 512, 1024; BF16). The step
 // of Sec. 3.2-3.3 as a chain of launches over activations kept in device memory: row tiles,
 // encoding, one product launch per layer forward, rendering with its adjoint (the fused kernels'
 // own render_subtile), then per layer one launch for the weight gradient and one for the input
 // gradient. The arithmetic takes the BF16 tile kernels' rounding points: every operand of every
 // product is rounded to BF16 (encoding, activations, weights, deltas, the output layer's seed),
 // products accumulate in FP32 on v_mfma_f32_32x32x16_bf16; biases, sigmoids, rendering, losses
-// and the output layer's bias gradient stay FP32. An object's weight gradient is summed over all
-// its rows by one workgroup per block of each weight matrix, in an order fixed by the object's rows
-// alone: no partials to reduce, and the result does not depend on the grid or on the other objects.
+// and the output layer's bias gradient stay FP32. An object's weight gradient is summed per work
+// tile (about kGenWorkRows of its rows) by one workgroup per block of each weight matrix, in an
+// order fixed by the object's rows alone, into one partial per work tile that the optimiser adds
+// in tile order: the result does not depend on the grid or on the other objects.
 //
 // Row-tile product kernel (k_gen_gemm): a workgroup (four waves) computes a 64 x 64 block of
 // D = A B over one row tile, each wave a 32 x 32 quarter, over K in chunks of 64 staged in LDS as
