@@ -238,22 +238,24 @@ __host__ __device__ constexpr int kernel_width(int H) { return H == 16 ? 32 : H;
 
 // Slot of parameter p of a width-H object in the parameter layout of its kernel width (the
 // layout of the weight images and the tile partials): p itself, except at hidden 16, where
-// layer l's weight (o, i) and bias o keep their indices in the width-32 layout.
+// layer l's weight (o, i) and bias o keep their indices in the width-32 layout. Closed form
+// (no loop: the optimiser evaluates it for every parameter): at hidden 16 the first layer's
+// weights (32 inputs) keep their index, its 16 biases follow at 1024, each hidden layer's 272
+// parameters (16 x 16 weights, 16 biases) land in a 1056-slot block, and the output layer's
+// 4 x 16 weights and 4 biases at 4224.
 __host__ __device__ constexpr int padded_index(int H, int p) {
   if (H != 16) return p;
-  constexpr int H2 = 32;
-  int off = 0, off2 = 0;
-  for (int l = 0; l <= kLayers; ++l) {
-    const int K = (l == 0) ? kEnc : 16, O = (l == kLayers) ? kOut : 16;
-    const int K2 = (l == 0) ? kEnc : H2, O2 = (l == kLayers) ? kOut : H2;
-    if (p < off + O * K) {
-      const int e = p - off, o = e / K, i = e - o * K;
-      return off2 + o * K2 + i;
-    }
-    if (p < off + O * K + O) return off2 + O2 * K2 + (p - off - O * K);
-    off += O * K + O;
-    off2 += O2 * K2 + O2;
+  if (p < 16 * kEnc) return p;                           // W_1 [16][32]: rows of 32 either way
+  if (p < 16 * kEnc + 16) return 32 * kEnc + (p - 16 * kEnc);  // b_1
+  const int h0 = 16 * kEnc + 16, h0_32 = 32 * kEnc + 32;  // first hidden-to-hidden layer
+  if (p < h0 + (kLayers - 1) * 272) {
+    const int l = (p - h0) / 272, e = (p - h0) - l * 272;
+    const int base = h0_32 + l * 1056;
+    return e < 256 ? base + (e >> 4) * 32 + (e & 15) : base + 1024 + (e - 256);
   }
+  const int o0 = h0 + (kLayers - 1) * 272, o0_32 = h0_32 + (kLayers - 1) * 1056;  // output layer
+  if (p < o0 + kOut * 16) return o0_32 + ((p - o0) >> 4) * 32 + ((p - o0) & 15);
+  if (p < o0 + kOut * 16 + kOut) return o0_32 + kOut * 32 + (p - o0 - kOut * 16);
   return -1;  // p beyond the object's parameters
 }
 

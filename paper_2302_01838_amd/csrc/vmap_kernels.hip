@@ -855,15 +855,20 @@ __device__ AdamCoef adam_coef(const OptArgs& a, int t) {
 
 // Parameter p of object k changed to th: its entry in the object's weight image (width 32, also
 // for hidden 16, whose image is the zero-padded width-32 one; the BF16 image of hidden 128), or
-// in its BF16 parameter copy (layered path, hidden 256 and up).
+// in its BF16 parameter copy (layered path, hidden 256 and up). WIDE = false leaves out the
+// hidden-128 image, for k_reduce_adam: a stack that can hold hidden-128 objects has at least
+// kReduceWide parameter slots per object and takes k_reduce_adam_wide (its launcher checks).
+template <bool WIDE = true>
 __device__ __forceinline__ void update_image(const OptArgs& a, int k, int hidden, int p, float th) {
   if (a.gimg && keeps_gimg(hidden)) {
     a.gimg[(size_t)k * a.p_stride + p] = (uint16_t)(pack2(th, 0.f) & 0xffffu);
     return;
   }
-  if (hidden == 128) {
-    if (a.wimage && a.bf16) place_param<128, true>(a.wimage + (size_t)k * a.wimage_stride, p, th);
-    return;
+  if constexpr (WIDE) {
+    if (hidden == 128) {
+      if (a.wimage && a.bf16) place_param<128, true>(a.wimage + (size_t)k * a.wimage_stride, p, th);
+      return;
+    }
   }
   if (!a.img32 || kernel_width(hidden) != 32) return;
   const int q = padded_index(hidden, p);
@@ -2270,7 +2275,7 @@ __global__ void __launch_bounds__(256) k_reduce_adam(const OptArgs a_in) {
     } else {
       atomicOr(&a.flags[k], 2);  // for the skip count (bit 1: see object_bad)
     }
-    update_image(a, k, hidden, p, th);
+    update_image<false>(a, k, hidden, p, th);
   }
   if (lead) a.desc[k].step = t;
 }
@@ -2854,6 +2859,7 @@ hipError_t launch_optimizer(int kind, const OptArgs& a, hipStream_t s) {
     const int per_object = std::max(1, std::min((a.p_stride / 4 + 255) / 256, (4096 + a.n_objects - 1) / a.n_objects));
     hipLaunchKernelGGL(k_reduce_adam_wide, dim3(per_object, a.n_objects + 1), dim3(256), 0, s, a);
   } else {
+    if (a.wimage) return hipErrorInvalidValue;  // hidden-128 images are kept by the wide kernel
     hipLaunchKernelGGL(k_reduce_adam, dim3(grid.x, a.n_objects + 1), dim3(256), 0, s, a);
   }
   return hipGetLastError();
