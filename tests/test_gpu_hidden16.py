@@ -63,6 +63,20 @@ def test_train_step_parity(precision, scene_name):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_size_k50_step(precision):
+    """The 50-object uneven workload (16,881 rays of 20 samples) with every object at hidden 16,
+    in the launch shape the benchmark uses, every object checked."""
+    print(f"[h16] full-size k50 {precision}", flush=True)
+    sc = _h16(scenes.make_scene("k50_uneven"))
+    objs, states = make_pair(sc, precision)
+    errs, errs16, unstable, _ = step_errors(objs, states, scenes.make_batch(sc, 3), precision, sc.B)
+    report(f"h16 step {precision} k50 full (sign-unstable={unstable})", **errs)
+    if errs16:
+        report(f"h16 step {precision} k50 full vs bf16 oracle", **errs16)
+    check_step(errs, errs16, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_backward_parity(precision):
     print(f"[h16] backward {precision}", flush=True)
     sc = SCENES["tiny_k4"]()
