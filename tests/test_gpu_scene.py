@@ -7,6 +7,8 @@ an integer decided by floating point: where the GPU and the oracle pick differen
 two candidates must be tied within FP32 rounding (depths or occupancy at the threshold); all
 other rays are compared value by value.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -62,9 +64,14 @@ def _compare(states, sc, o, d, S, got, occ_threshold=0.5, tol_=1e-5):
     return errs, int(differ.size), int((r_id >= 0).sum())
 
 
+@pytest.mark.parametrize("widths", ["32", "16/32"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_scene_render_parity(precision):
+def test_scene_render_parity(precision, widths):
+    """widths 16/32: every other object at hidden 16 (run zero-padded in the width-32 kernels)."""
     sc = scaled(scenes.make_scene("room50_background"), 8)
+    if widths == "16/32":
+        sc = dataclasses.replace(sc, objects=[dataclasses.replace(o, hidden=16) if k < 12 and k % 2 == 0 else o
+                                              for k, o in enumerate(sc.objects)])
     ids = list(range(12))
     objs, states = make_pair(sc, precision, ids=ids, max_rays=20000)
     # models that differ from their initialisation and from each other: seeded perturbations of
@@ -81,7 +88,7 @@ def test_scene_render_parity(precision):
     torch.cuda.synchronize()
     t = 1e-5 if precision == "fp32" else 2e-2
     errs, n_diff, n_hit = _compare(states, sc, o, d, S, got, tol_=t)
-    report(f"scene render {precision} (rays with an object={n_hit}, tie picks={n_diff})", **errs)
+    report(f"scene render {precision} widths {widths} (rays with an object={n_hit}, tie picks={n_diff})", **errs)
     assert n_hit > 300
     for v in errs.values():
         assert v <= t
