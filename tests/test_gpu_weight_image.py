@@ -87,9 +87,12 @@ def test_hidden128_image_after_training_steps_matches_whole_staging():
         assert torch.equal(a, b)
 
 
-def test_images_after_autograd_adam_step():
-    """The autograd split's Adam kernel keeps the images current as well."""
+@pytest.mark.parametrize("H", [32, 16])
+def test_images_after_autograd_adam_step(H):
+    """The autograd split's Adam kernel keeps the images current as well (hidden 16: the padded
+    slots of its width-32 image)."""
     sc = scenes.make_scene("tiny_k4")
+    sc = dataclasses.replace(sc, objects=[dataclasses.replace(o, hidden=H) for o in sc.objects])
     inc, _ = make_pair(sc, "bf16")
     whole, _ = make_pair(sc, "bf16")
     db = vm.DeviceBatch(scenes.make_batch(sc, 0))
