@@ -478,7 +478,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the step has no "
-              "cross-GPU exchange; objects would be sharded across GPUs, see DESIGN.md)",
+              "cross-GPU exchange; objects would be sharded across GPUs by object)",
               file=sys.stderr)
         sys.exit(2)
 

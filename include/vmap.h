@@ -47,7 +47,7 @@ typedef enum {
   VMAP_ECAPACITY = 2,  /* more objects, rays or bytes than the context was sized for */
   VMAP_EHIP = 3,       /* a HIP runtime call failed (message names it) */
   VMAP_ESTATE = 4,     /* call not valid in the current state (e.g. unregistered object) */
-  VMAP_ENOTSUP = 5     /* configuration this build does not support */
+  VMAP_ENOTSUP = 5     /* configuration the library does not support */
 } vmap_status;
 
 enum { VMAP_FP32 = 0, VMAP_BF16 = 1 };
