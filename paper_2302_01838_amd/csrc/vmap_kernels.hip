@@ -3130,9 +3130,11 @@ __device__ __forceinline__ bool gen_rows(const GenArgs& g, const StepArgs& a, in
 // rows lie; B is rows of W from the object's BF16 parameter copy (the optimiser keeps it equal to
 // the parameters rounded to nearest even), read directly (forward: W rows are
 // the output columns, k contiguous) or transposed (input gradient: W rows are the k index). The
-// next chunk's loads are in flight while the current chunk's products run.
+// next chunk's loads are in flight while the current chunk's products run. The 128-row input
+// gradient is compiled for three waves per SIMD (164 registers, no spill; it had taken 182 and
+// run two), as the forward product already runs.
 template <int KIND, int T>
-__global__ void __launch_bounds__(256) k_gen_gemm(const GenArgs g_in, int l, int ncol_blocks) {
+__global__ void __launch_bounds__(256, (KIND == GEN_DX && T == 128) ? 3 : 1) k_gen_gemm(const GenArgs g_in, int l, int ncol_blocks) {
   static_assert(KIND == GEN_FWD || KIND == GEN_DX, "products over one row block");
   static_assert(T == 64 || T == 128, "block sizes");
   GenArgs g = g_in;
