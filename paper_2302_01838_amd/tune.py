@@ -99,7 +99,7 @@ def tune(workload: str = "k50_uneven", precision: str = "bf16", steps: int = 100
         rnd = 4 * rpw
         cur = lookup(32, S, precision, path=path) or {}
         rpt32 = int(cur.get("rays_per_tile", 0))
-        wides = list(rays_per_tile_wide) or [rnd * m for m in (1, 2, 4, 8, 16)]
+        wides = list(rays_per_tile_wide) or [rnd * m for m in (1, 2, 4, 8, 16, 32)]
         shapes = [(rpt32, rw, int(cur.get("waves", 4))) for rw in wides]
     results = []
     for rpt, rw, w in shapes:
